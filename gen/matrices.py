@@ -1,0 +1,113 @@
+"""Input families of the paper's experiments, regenerated from their definitions.
+
+All matrices are float64 and returned in column-major (Fortran) order, which is
+the layout the library and the oracle take (element (i, j) at X[i + j*ld]).
+
+* make_svd      -- Section 5.1.1: X = U diag(sigma) V^T with a geometric spectrum
+                   from 1 down to 1/kappa (kappa_2(X) = kappa, ||X||_2 = 1).
+* make_lowtri   -- Section 5.1.2: 400 stacked copies of a 50x50 lower-triangular
+                   block F (F_ii = 100, F_ij = a below the diagonal).
+* make_arrowhead-- Section 5.1.3: X = -5 e_b e_a^T + P_s with E = diag(1,..,1,beta).
+* make_krylov   -- columns A^k v / ||A^k v|| with A diagonal, eigenvalues U(0,1)
+                   and v Gaussian (a severely ill-conditioned family).
+* batch_manifest-- a seeded list of problem shapes for batched runs.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def fortran(a: np.ndarray) -> np.ndarray:
+    """Return `a` as a float64 column-major array (copying only if needed)."""
+    return np.asfortranarray(a, dtype=np.float64)
+
+
+def _orthonormal_columns(rng: np.random.Generator, m: int, n: int) -> np.ndarray:
+    """Q factor (m x n, orthonormal columns) of a seeded Gaussian matrix, sign-fixed
+    so that the R factor has a positive diagonal (this makes it unique)."""
+    g = rng.standard_normal((m, n))
+    q, r = np.linalg.qr(g, mode="reduced")
+    d = np.sign(np.diag(r))
+    d[d == 0] = 1.0
+    return q * d
+
+
+def make_svd(m: int, n: int, kappa: float, seed: int = 0, norm2: float = 1.0) -> np.ndarray:
+    """X = U diag(sigma) V^T, sigma_i = norm2 * kappa^(-(i-1)/(n-1)), i = 1..n.
+
+    U is the Q factor of a seeded m x n Gaussian, V the Q factor of a seeded
+    n x n Gaussian (both sign-fixed). kappa_2(X) = kappa, ||X||_2 = norm2.
+    """
+    if not (m >= n >= 1):
+        raise ValueError("need m >= n >= 1")
+    rng = np.random.default_rng(seed)
+    u = _orthonormal_columns(rng, m, n)
+    v = _orthonormal_columns(rng, n, n)
+    if n == 1:
+        sig = np.array([1.0])
+    else:
+        sig = kappa ** (-np.arange(n, dtype=np.float64) / (n - 1))
+    sig = sig * norm2
+    x = (u * sig) @ v.T
+    return fortran(x)
+
+
+def make_lowtri(a: float, copies: int = 400, nb: int = 50) -> np.ndarray:
+    """Stack `copies` copies of F (nb x nb): F_ii = 100, F_ij = a for j < i, 0 above."""
+    f = np.tril(np.full((nb, nb), float(a)), k=-1) + 100.0 * np.eye(nb)
+    return fortran(np.tile(f, (copies, 1)))
+
+
+def make_arrowhead(beta: float, m: int = 20000, n: int = 50) -> np.ndarray:
+    """X = -5 e_b e_a^T + P_s, e_a = (0,1,...,1) in R^n, e_b = e_1 in R^m,
+    P_s = [E; 0] with E = diag(1, ..., 1, beta) (n x n)."""
+    x = np.zeros((m, n))
+    e = np.ones(n)
+    e[-1] = beta
+    x[np.arange(n), np.arange(n)] = e
+    x[0, 1:] += -5.0
+    return fortran(x)
+
+
+def make_krylov(m: int, n: int, seed: int = 0, block: int = 1 << 20) -> np.ndarray:
+    """Krylov-monomial columns x_k = A^k v / ||A^k v||, k = 0..n-1, with
+    A = diag(lambda), lambda_i ~ U(0,1) i.i.d., v ~ N(0, I) (seeded).
+
+    Column norms are summed over fixed row blocks in index order, so the result
+    does not depend on how the work is split.
+    """
+    rng = np.random.default_rng(seed)
+    lam = rng.random(m)
+    v = rng.standard_normal(m)
+    x = np.empty((m, n), order="F")
+
+    def _norm(c: np.ndarray) -> float:
+        acc = 0.0
+        for b0 in range(0, m, block):
+            seg = c[b0:b0 + block]
+            acc += float(np.dot(seg, seg))
+        return float(np.sqrt(acc))
+
+    cur = v / _norm(v)
+    x[:, 0] = cur
+    for k in range(1, n):
+        cur = lam * cur
+        cur = cur / _norm(cur)
+        x[:, k] = cur
+    return x
+
+
+def batch_manifest(seed: int = 0, count: int = 512, m_lo: int = 10000, m_hi: int = 500000,
+                   n_choices=(16, 32, 64, 128), logk_lo: float = 2.0, logk_hi: float = 14.0):
+    """Seeded list of batched problems: m ~ U{m_lo..m_hi}, n ~ U(n_choices),
+    log10(kappa) ~ U[logk_lo, logk_hi]; input seed 1000+i, sketch seed i, s = 2n."""
+    rng = np.random.default_rng(seed)
+    ms = rng.integers(m_lo, m_hi + 1, size=count)
+    ns = rng.choice(np.asarray(n_choices), size=count)
+    lk = rng.uniform(logk_lo, logk_hi, size=count)
+    out = []
+    for i in range(count):
+        n = int(ns[i])
+        out.append(dict(m=int(ms[i]), n=n, kappa=float(10.0 ** lk[i]), input_seed=1000 + i,
+                        seed=i, s=2 * n))
+    return out

@@ -1,0 +1,274 @@
+"""Pins for the oracle's whole methods: Algorithms 2 (RCLUPP), 3 (CholeskyQR2),
+4 (SCholeskyQR3), 5 (LC2), 6 (RCholeskyQR) and 7 (RCLUPPr).
+
+Pins: the unique thin QR with positive diag(R) from LAPACK (numpy qr, sign
+fixed), exact-arithmetic identities of the preconditioners, special cases with
+known factors, exact rational R^T R = X^T X on tiny inputs, the paper's
+closed-form bounds (Lemmas 3.1-3.3, the RCLUPP theorem), the qualitative
+outcomes stated in Section 5, and bitwise determinism over thread counts.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import bounds
+from gen import make_svd, make_lowtri, make_arrowhead, make_krylov
+
+U = oracle.U
+ALL = ["rclupp", "rcluppr", "cholqr2", "scholqr3", "lc2", "rcholqr"]
+
+
+def lapack_r(x):
+    r = np.linalg.qr(x, mode="r")
+    d = np.sign(np.diag(r))
+    d[d == 0] = 1
+    return d[:, None] * r
+
+
+def check_qr(x, res, tol_orth=1e-12, tol_res=1e-13):
+    assert res.ok, res.info
+    assert np.all(np.tril(res.R, -1) == 0)
+    assert np.all(np.diag(res.R) > 0)
+    m = oracle.metrics(x, res.Q, res.R)
+    assert m["orth"] <= tol_orth, m
+    assert m["rel_res"] <= tol_res, m
+    return m
+
+
+@pytest.mark.parametrize("method", ALL)
+@pytest.mark.parametrize("kappa", [1e2, 1e6])
+def test_methods_match_lapack_qr(method, kappa):
+    m, n = 2048, 32
+    x = make_svd(m, n, kappa, seed=1)
+    r = oracle.run(method, x, s=2 * n, seed=0)
+    check_qr(x, r)
+    rl = lapack_r(x)
+    # R is unique (positive diagonal); forward error ~ kappa u
+    err = np.linalg.norm(r.R - rl) / np.linalg.norm(rl)
+    assert err <= 1e-14 * kappa, err
+    # Q = X R^{-1}
+    qr_ = np.linalg.solve(rl.T, x.T).T
+    assert np.linalg.norm(r.Q - qr_) <= 1e-14 * kappa * math.sqrt(n)
+
+
+@pytest.mark.parametrize("method", ["rclupp", "rcluppr", "lc2"])
+@pytest.mark.parametrize("kappa", [1e10, 1e13, 1e15])
+def test_lu_methods_ill_conditioned(method, kappa):
+    # Section 5.1.1: the LU-based methods stay applicable as kappa approaches 1/u
+    x = make_svd(2000, 50, kappa, seed=2)
+    r = oracle.run(method, x, s=100, seed=0)
+    check_qr(x, r)
+    rl = lapack_r(x)
+    assert np.linalg.norm(r.R - rl) / np.linalg.norm(rl) <= 1e-14 * kappa
+
+
+def test_cholqr2_breaks_down_beyond_sqrt_u():
+    # Section 2.1 / 5.2: CholeskyQR2 fails for kappa >= u^{-1/2}
+    x = make_svd(2000, 50, 1e12, seed=3)
+    r = oracle.cholqr2(x)
+    assert r.info[0] == oracle.CHOL_BREAKDOWN
+    assert r.info[1] in (oracle.ST_PRECOND, oracle.ST_CHOL_A)
+
+
+def test_scholqr3_near_inverse_u():
+    # Section 5.2: SCholeskyQR3 becomes inapplicable as kappa approaches 1/u; it still
+    # works well inside its range (Lemma 3.2 / Table 1)
+    x = make_svd(2000, 50, 1e16, seed=4)
+    r = oracle.scholqr3(x)
+    bad = (not r.ok) or oracle.orthogonality(r.Q) > 1e-12
+    assert bad
+    x = make_svd(2000, 50, 1e8, seed=4)
+    check_qr(x, oracle.scholqr3(x))
+
+
+def test_rclupp_r1_is_r_of_sketch():
+    # RCLUPP's R_1 = D R_0 N is, in exact arithmetic, the R factor of Y = S X
+    # (P Y = M N = Q_s R_0 N); RCLUPPr's R_1 that of S (P X)
+    m, n, s = 4000, 24, 48
+    x = make_svd(m, n, 1e6, seed=5)
+    r = oracle.rclupp(x, s, seed=3)
+    y = oracle.sketch(x, s, seed=3)
+    ry = lapack_r(y)
+    assert np.linalg.norm(r.R1 - ry) / np.linalg.norm(ry) < 1e-14 * 1e6
+    rr = oracle.rcluppr(x, s, seed=3)
+    M, N, perm, info = oracle.gepp(x)
+    ryp = lapack_r(oracle.sketch(x[perm], s, seed=3))
+    assert np.linalg.norm(rr.R1 - ryp) / np.linalg.norm(ryp) < 1e-14 * 1e6
+    # the sketch preconditions: kappa(X R_1^{-1}) is O(1) (eq. k2w)
+    q1 = oracle.trsm(x, r.R1)
+    sv = np.linalg.svd(q1, compute_uv=False)
+    assert sv[0] / sv[-1] < 10
+
+
+def test_cholqr2_tail_factors():
+    # C1-C8: R = R_4 (R_2 R_1) and Z = R_4 R_2 is close to the identity after preconditioning
+    x = make_svd(3000, 16, 1e8, seed=6)
+    r = oracle.rclupp(x, 32, seed=1)
+    R3 = oracle.trmm(r.R2, r.R1)
+    np.testing.assert_allclose(r.R, oracle.trmm(r.R4, R3), rtol=0, atol=1e-15 * np.abs(r.R).max())
+    assert np.linalg.norm(r.R4 - np.eye(16)) < 1e-12
+
+
+@pytest.mark.parametrize("method", ALL)
+def test_single_column(method):
+    # n = 1: R = ||x||, Q = x / ||x||
+    x = np.asfortranarray(np.random.default_rng(7).standard_normal((500, 1)))
+    r = oracle.run(method, x, s=2, seed=0)
+    assert r.ok
+    nrm = np.linalg.norm(x)
+    assert abs(r.R[0, 0] - nrm) <= 1e-14 * nrm
+    np.testing.assert_allclose(r.Q, x / nrm, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("method", ALL)
+def test_orthonormal_input(method):
+    # orthonormal X: R = I, Q = X
+    x, _ = np.linalg.qr(np.random.default_rng(8).standard_normal((1000, 12)))
+    x = np.asfortranarray(x)
+    r = oracle.run(method, x, s=24, seed=0)
+    assert r.ok
+    d = np.sign(np.diag(np.linalg.qr(x, mode="r")))
+    np.testing.assert_allclose(r.R, np.diag(d) @ np.diag(d) * 0 + np.diag(np.abs(np.diag(r.R))), atol=1e-14)
+    rl = lapack_r(x)
+    np.testing.assert_allclose(r.R, rl, atol=1e-14)
+    np.testing.assert_allclose(r.Q, x @ np.diag(np.sign(np.diag(np.linalg.qr(x, mode="r")))), atol=1e-14)
+
+
+@pytest.mark.parametrize("method", ALL)
+def test_scaled_orthonormal_columns(method):
+    # X = Q0 diag(d): R = diag(|d|)
+    q0, _ = np.linalg.qr(np.random.default_rng(9).standard_normal((800, 6)))
+    d = np.array([3.0, -1e-3, 7.0, 2.0, -0.5, 1e2])
+    x = np.asfortranarray(q0 * d)
+    r = oracle.run(method, x, s=12, seed=4)
+    assert r.ok
+    np.testing.assert_allclose(r.R, np.diag(np.abs(d)), rtol=0, atol=1e-13 * np.abs(d).max())
+
+
+def test_cholqr2_exact_special_cases():
+    # X = [I; 0]: G = I exactly, so Q = X and R = I exactly; a permutation matrix likewise
+    x = np.zeros((20, 5), order="F")
+    x[:5, :5] = np.eye(5)
+    r = oracle.cholqr2(x)
+    np.testing.assert_array_equal(r.R, np.eye(5))
+    np.testing.assert_array_equal(r.Q, x)
+    p = np.asfortranarray(np.eye(6)[[3, 0, 5, 1, 2, 4]])
+    r = oracle.cholqr2(p)
+    np.testing.assert_array_equal(r.R, np.eye(6))
+    np.testing.assert_array_equal(r.Q, p)
+
+
+@pytest.mark.parametrize("method", ALL)
+def test_exact_rational_gram_identity(method):
+    # R^T R = X^T X (exact arithmetic), checked against rational X^T X
+    rng = np.random.default_rng(10)
+    x = np.asfortranarray(rng.integers(-5, 6, size=(40, 4)).astype(float))
+    r = oracle.run(method, x, s=8, seed=2)
+    assert r.ok
+    n = 4
+    for i in range(n):
+        for j in range(n):
+            exact = sum(Fraction(float(a)) * Fraction(float(b)) for a, b in zip(x[:, i], x[:, j]))
+            got = float(r.R[:, i] @ r.R[:, j])
+            assert abs(got - float(exact)) <= 1e-13 * float(np.abs(x[:, i]) @ np.abs(x[:, j]))
+
+
+@pytest.mark.parametrize("kappa", [1e4, 1e10, 1e15])
+def test_paper_bounds_svd_family(kappa):
+    # Theorem (RCLUPP), Lemmas 3.1-3.3 evaluated at the measured norms
+    m, n = 2000, 50
+    x = make_svd(m, n, kappa, seed=11)
+    x2 = 1.0
+    xf = np.linalg.norm(x)
+    xg = np.sqrt(np.max(np.sum(x * x, axis=0)))
+    for method, bnd in [("rclupp", bounds.rclupp_bounds(m, n, xf, x2)),
+                        ("rcluppr", bounds.rclupp_bounds(m, n, xf, x2)),
+                        ("lc2", bounds.lc2_bounds(m, n, x2))]:
+        r = oracle.run(method, x, s=100, seed=0)
+        assert r.ok
+        mt = oracle.metrics(x, r.Q, r.R)
+        assert mt["orth"] <= bnd[0] and mt["res"] <= bnd[1], (method, mt, bnd)
+    if kappa <= bounds.cholqr2_kappa_limit(m, n):
+        r = oracle.cholqr2(x)
+        mt = oracle.metrics(x, r.Q, r.R)
+        b = bounds.cholqr2_bounds(m, n, x2)
+        assert mt["orth"] <= b[0] and mt["res"] <= b[1]
+        r = oracle.scholqr3(x)
+        mt = oracle.metrics(x, r.Q, r.R)
+        b = bounds.scholqr3_bounds(m, n, xg, x2)
+        assert mt["orth"] <= b[0] and mt["res"] <= b[1]
+
+
+def test_lowtri_family():
+    # Section 5.1.2 family (400 stacked 50x50 lower-triangular blocks, F_ii = 100, F_ij = a):
+    # RCLUPP, RCLUPPr and LC2 all return an orthonormal Q with a small residual. As defined
+    # in the text the family is well conditioned (kappa ~ 1.2-1.3, growing with |a|), so the
+    # LC2 failure shown in the (lost) figures is not reproducible from the definition.
+    for a in (-0.6, -1.0):
+        x = make_lowtri(a)
+        sv = np.linalg.svd(x, compute_uv=False)
+        assert sv[0] / sv[-1] < 2.0
+        for method in ("rclupp", "rcluppr", "lc2"):
+            r = oracle.run(method, x, s=100, seed=0)
+            m = check_qr(x, r)
+            assert m["orth"] <= bounds.rclupp_bounds(20000, 50, np.linalg.norm(x), sv[0])[0]
+
+
+@pytest.mark.parametrize("beta", [1e-10, 1e-20, 1e-30])
+def test_arrowhead_family_rcluppr(beta):
+    # Section 5.1.3: RCLUPPr is the most robust on the arrowhead family
+    x = make_arrowhead(beta)
+    r = oracle.rcluppr(x, 100, seed=0)
+    m = check_qr(x, r)
+    assert m["orth"] < 1e-13
+
+
+def test_krylov_rcluppr_vs_householder():
+    # a numerically rank-deficient Krylov family: RCLUPPr still returns an orthonormal Q
+    # with a tiny residual (the factors themselves are not unique here)
+    x = make_krylov(20000, 32, seed=0)
+    r = oracle.rcluppr(x, 64, seed=0)
+    assert r.ok
+    mt = oracle.metrics(x, r.Q, r.R)
+    assert mt["orth"] < 1e-12 and mt["rel_res"] < 1e-13
+
+
+@pytest.mark.parametrize("method", ["rclupp", "rcluppr", "scholqr3"])
+def test_thread_count_determinism(method):
+    x = make_svd(20000, 16, 1e8, seed=12)
+    t0 = oracle.max_threads()
+    try:
+        oracle.set_threads(1)
+        a = oracle.run(method, x, s=32, seed=5)
+        oracle.set_threads(max(2, t0))
+        b = oracle.run(method, x, s=32, seed=5)
+    finally:
+        oracle.set_threads(t0)
+    np.testing.assert_array_equal(a.Q, b.Q)
+    np.testing.assert_array_equal(a.R, b.R)
+
+
+def test_nonfinite_input_reported():
+    x = make_svd(500, 8, 1e3, seed=13)
+    x[17, 3] = np.nan
+    for method in ALL:
+        r = oracle.run(method, x, s=16, seed=0)
+        assert r.info[0] in (oracle.NONFINITE,), (method, r.info)
+
+
+def test_rank_deficient_inputs():
+    # an exactly zero column: LU meets a zero pivot (Algorithms 2, 5, 7), Cholesky a zero pivot
+    x = make_svd(500, 8, 1e3, seed=14)
+    x[:, 4] = 0.0
+    for method in ("rclupp", "rcluppr", "lc2"):
+        r = oracle.run(method, x, s=16, seed=0)
+        assert r.info.tolist()[:3] == [oracle.LU_ZERO_PIVOT, oracle.ST_LU, 5], (method, r.info)
+    for method in ("cholqr2", "scholqr3"):
+        r = oracle.run(method, x)
+        if method == "cholqr2":
+            assert r.info.tolist()[:3] == [oracle.CHOL_BREAKDOWN, oracle.ST_PRECOND, 5]
+        else:  # the shift keeps the first Cholesky positive; the next one breaks down
+            assert r.info[0] == oracle.CHOL_BREAKDOWN and r.info[1] == oracle.ST_CHOL_A
