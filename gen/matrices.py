@@ -14,6 +14,8 @@ the layout the library and the oracle take (element (i, j) at X[i + j*ld]).
 """
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 
 
@@ -32,17 +34,26 @@ def _orthonormal_columns(rng: np.random.Generator, m: int, n: int) -> np.ndarray
     return q * d
 
 
+@functools.lru_cache(maxsize=2)
+def _svd_factors(m: int, n: int, seed: int):
+    rng = np.random.default_rng(seed)
+    u = _orthonormal_columns(rng, m, n)
+    v = _orthonormal_columns(rng, n, n)
+    u.setflags(write=False)
+    v.setflags(write=False)
+    return u, v
+
+
 def make_svd(m: int, n: int, kappa: float, seed: int = 0, norm2: float = 1.0) -> np.ndarray:
     """X = U diag(sigma) V^T, sigma_i = norm2 * kappa^(-(i-1)/(n-1)), i = 1..n.
 
     U is the Q factor of a seeded m x n Gaussian, V the Q factor of a seeded
     n x n Gaussian (both sign-fixed). kappa_2(X) = kappa, ||X||_2 = norm2.
+    The factors depend only on (m, n, seed), so a sweep over kappa reuses them.
     """
     if not (m >= n >= 1):
         raise ValueError("need m >= n >= 1")
-    rng = np.random.default_rng(seed)
-    u = _orthonormal_columns(rng, m, n)
-    v = _orthonormal_columns(rng, n, n)
+    u, v = _svd_factors(m, n, seed)
     if n == 1:
         sig = np.array([1.0])
     else:

@@ -1,0 +1,231 @@
+/*
+ * rclupp.h -- C ABI of the MI355X (gfx950) tall-skinny QR library.
+ *
+ * Computes X = Q R for a tall-skinny X (m x n, m >= n, rank n), Q with
+ * orthonormal columns and R upper triangular with a positive diagonal
+ * (Section 1 of "A new randomized CholeskyQR based on LU decomposition with
+ * partial pivoting", Fan, Guan, Qiao, arXiv 2412.06551), by
+ *   RCLUPP   (Algorithm 2)  sketch -> LU of the sketch -> Householder R -> CholeskyQR2
+ *   RCLUPPr  (Algorithm 7)  LU of X -> sketch of L -> Householder R -> CholeskyQR2
+ * and by the baselines the paper compares with:
+ *   CholeskyQR2 (Algorithm 3), Shifted CholeskyQR3 (Algorithm 4),
+ *   LU-CholeskyQR2 (Algorithm 5), randomized CholeskyQR (Algorithm 6).
+ *
+ * Conventions shared by every entry point
+ *   - matrix pointers are DEVICE pointers to float64, column-major:
+ *     element (i, j) of X is X[i + j*ld]; Q uses the same ld; R is n x n
+ *     with leading dimension n and is written in full (zeros below the
+ *     diagonal);
+ *   - 1 <= n <= RCLUPP_MAX_N, m >= n, ld >= m, and for the sketched
+ *     methods n <= s <= m (Section 3: S is s x m with s = O(n)); s and seed
+ *     are ignored by the unsketched methods;
+ *   - X is read only; X and Q must not overlap; Q and R are written only;
+ *   - the sketch is S = G / sqrt(s) with G_ij a standard normal drawn from
+ *     Philox4x32-10 (counter = (j lo, j hi, floor(i/4), 0), key = (seed lo,
+ *     seed hi), Box-Muller on the four 23-bit uniforms), a pure function of
+ *     (seed, i, j); see rclupp_omega;
+ *   - all work is enqueued on `stream` (a hipStream_t; NULL = default
+ *     stream); calls return before the work finishes and never synchronize
+ *     the device, except rclupp_last_info;
+ *   - synchronous errors (bad arguments, unsupported sizes, allocation or
+ *     launch failures) are returned as an rclupp_status and nothing is
+ *     enqueued for them;
+ *   - numerical failures found on the device (a zero LU pivot, a Cholesky
+ *     pivot that is not positive, non-finite data) are recorded in an
+ *     rclupp_info on the device; the kernels after the failing stage see it
+ *     and return at once; Q and R are then unspecified.
+ *   - calls with different streams and different workspaces may run
+ *     concurrently; the 9-argument forms draw their workspace from the
+ *     library's stream-ordered pool.
+ */
+#ifndef RCLUPP_H
+#define RCLUPP_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RCLUPP_MAX_N 256
+
+/* Synchronous status returned by every entry point. */
+typedef enum {
+  RCLUPP_OK = 0,
+  RCLUPP_ERR_INVALID_ARG = 1, /* a size, pointer or leading dimension is invalid    */
+  RCLUPP_ERR_UNSUPPORTED = 2, /* valid but not supported (e.g. n > RCLUPP_MAX_N)      */
+  RCLUPP_ERR_ALLOC = 3,       /* device memory could not be obtained                 */
+  RCLUPP_ERR_HIP = 4,         /* a HIP runtime call or kernel launch failed          */
+  RCLUPP_ERR_WORKSPACE = 5    /* the caller's workspace is smaller than required     */
+} rclupp_status;
+
+/* Asynchronous numerical outcome, written on the device. */
+typedef enum {
+  RCLUPP_INFO_OK = 0,
+  RCLUPP_INFO_LU_ZERO_PIVOT = 1,  /* LU with partial pivoting met an exactly zero column */
+  RCLUPP_INFO_CHOL_BREAKDOWN = 2, /* a Cholesky pivot was not > 0                          */
+  RCLUPP_INFO_NONFINITE = 3,      /* the input of a small factorization held NaN or Inf    */
+  RCLUPP_INFO_SINGULAR = 4        /* the preconditioner R_1 has an exactly zero diagonal   */
+} rclupp_info_code;
+
+/* Stage = the role of the failing small factorization in the pipeline. */
+typedef enum {
+  RCLUPP_STAGE_NONE = 0,
+  RCLUPP_STAGE_LU = 1,      /* LU of the sketch (RCLUPP) or of X (RCLUPPr, LC2)          */
+  RCLUPP_STAGE_QR = 2,      /* R factor of the (sketched) L factor, or chol(M^T M) in LC2 */
+  RCLUPP_STAGE_PRECOND = 3, /* R_1 = R_0 N, or the first (shifted) Cholesky               */
+  RCLUPP_STAGE_CHOL_A = 4,  /* Cholesky of the first Gram after preconditioning (R_2)     */
+  RCLUPP_STAGE_CHOL_B = 5   /* Cholesky of the second Gram (R_4)                          */
+} rclupp_stage;
+
+/* index = 1-based column at which the stage failed. */
+typedef struct {
+  int32_t code;
+  int32_t stage;
+  int32_t index;
+  int32_t reserved;
+} rclupp_info;
+
+typedef enum { RCLUPP_PREC_FP64 = 0, RCLUPP_PREC_FP32 = 1, RCLUPP_PREC_BF16 = 2 } rclupp_prec;
+
+/* Options of the full-control forms. A NULL pointer means all defaults (FP64).
+ *   sketch_prec: arithmetic of the sketch product S X (or S M): FP64, or FP32 /
+ *                BF16 MFMA with FP32 accumulation (the cross-workgroup sum is FP64);
+ *   lu_prec:     arithmetic of the LU + Householder preconditioner on the s x n
+ *                sketch: FP64 or FP32 (the result R_1 is widened to FP64).
+ * Everything else (triangular solves, Gram, Cholesky, the final pass) is FP64. */
+typedef struct {
+  int32_t sketch_prec;
+  int32_t lu_prec;
+  int32_t reserved[6];
+} rclupp_opts;
+
+typedef enum {
+  RCLUPP_ALG_RCLUPP = 0,   /* Algorithm 2 */
+  RCLUPP_ALG_RCLUPPR = 1,  /* Algorithm 7 */
+  RCLUPP_ALG_CHOLQR2 = 2,  /* Algorithm 3 */
+  RCLUPP_ALG_SCHOLQR3 = 3, /* Algorithm 4, shift 11(mnu + n(n+1)u) max_j ||X_j||^2 */
+  RCLUPP_ALG_LC2 = 4,      /* Algorithm 5 */
+  RCLUPP_ALG_RCHOLQR = 5   /* Algorithm 6 */
+} rclupp_alg;
+
+/* ---------------------------------------------------------------------------
+ * The method entry points (identical signatures). Workspace comes from the
+ * library's stream-ordered pool; the numerical outcome is kept per stream and
+ * read with rclupp_last_info.
+ *   rclupp_qr   : Algorithm 2 (RCLUPP)
+ *   rcluppr_qr  : Algorithm 7 (RCLUPPr)
+ *   cholqr2_qr  : Algorithm 3 (CholeskyQR2; s, seed ignored)
+ *   scholqr3_qr : Algorithm 4 (Shifted CholeskyQR3; s, seed ignored)
+ *   lc2_qr      : Algorithm 5 (LU-CholeskyQR2; s, seed ignored)
+ *   rcholqr_qr  : Algorithm 6 (randomized CholeskyQR, single sketch)
+ * ------------------------------------------------------------------------- */
+int rclupp_qr(const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, uint64_t seed, double* Q, double* R,
+              hipStream_t stream);
+int rcluppr_qr(const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, uint64_t seed, double* Q, double* R,
+               hipStream_t stream);
+int cholqr2_qr(const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, uint64_t seed, double* Q, double* R,
+               hipStream_t stream);
+int scholqr3_qr(const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, uint64_t seed, double* Q, double* R,
+                hipStream_t stream);
+int lc2_qr(const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, uint64_t seed, double* Q, double* R,
+           hipStream_t stream);
+int rcholqr_qr(const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, uint64_t seed, double* Q, double* R,
+               hipStream_t stream);
+
+/* Synchronizes `stream` and copies the outcome of the last 9-argument call
+ * enqueued on it to *h_info (host pointer). Returns RCLUPP_ERR_INVALID_ARG if
+ * no such call was made on this stream. */
+int rclupp_last_info(hipStream_t stream, rclupp_info* h_info);
+
+/* Static description of a status code. */
+const char* rclupp_status_string(int status);
+
+/* ---------------------------------------------------------------------------
+ * Full-control form: caller-owned workspace and device info.
+ *   rclupp_workspace_size: bytes of device workspace needed by rclupp_qr_ex for
+ *     these sizes and options (written to *bytes, a host pointer);
+ *   rclupp_qr_ex: runs method `alg`; ws is a device buffer of ws_bytes bytes
+ *     (256-byte aligned) owned by the caller and used only while the work
+ *     runs on `stream`; d_info (device pointer, nullable) receives the outcome.
+ * ------------------------------------------------------------------------- */
+int rclupp_workspace_size(int alg, int64_t m, int64_t n, int64_t s, const rclupp_opts* opts, size_t* bytes);
+int rclupp_qr_ex(int alg, const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, uint64_t seed, double* Q,
+                 double* R, const rclupp_opts* opts, void* ws, size_t ws_bytes, rclupp_info* d_info,
+                 hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched form: many independent problems, one graph-captured launch
+ * sequence. h_probs is a HOST array of `batch` descriptors whose matrix
+ * pointers are device pointers; d_info (device, nullable) receives one
+ * rclupp_info per problem. A failure in one problem does not affect the
+ * others. The workspace size depends on the whole batch.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const double* X;
+  double* Q;
+  double* R;
+  int64_t m, n, ld, s;
+  uint64_t seed;
+} rclupp_problem;
+
+int rclupp_batched_workspace_size(int alg, const rclupp_problem* h_probs, int batch, const rclupp_opts* opts,
+                                  size_t* bytes);
+int rclupp_qr_batched(int alg, const rclupp_problem* h_probs, int batch, const rclupp_opts* opts, void* ws,
+                      size_t ws_bytes, rclupp_info* d_info, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Step entry points: each runs one stage of the pipeline on its own, for
+ * testing and profiling. Device pointers, column-major, enqueued on stream.
+ * Scratch memory is drawn from the stream-ordered pool.
+ * ------------------------------------------------------------------------- */
+
+/* Raw G (unscaled standard normals, float32) of the sketch: G[i + c*s] =
+ * z(seed, i, j0 + c) for i < s, c < cols (Section 3, Gaussian sketch). */
+int rclupp_omega(uint64_t seed, int64_t s, int64_t j0, int64_t cols, float* G, hipStream_t stream);
+
+/* Raw Philox4x32-10 words for `count` counters (host-visible check of the
+ * generator): ctr = device uint32[4*count], key = (k0, k1), out = device
+ * uint32[4*count]. */
+int rclupp_philox(const uint32_t* ctr, int64_t count, uint32_t k0, uint32_t k1, uint32_t* out, hipStream_t stream);
+
+/* Y = S X (s x n, ld s): Algorithm 2 step 1, with `prec` an rclupp_prec. */
+int rclupp_sketch(const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, uint64_t seed, int prec, double* Y,
+                  hipStream_t stream);
+
+/* Preconditioner of the sketch (Algorithm 2 steps 2-4, Algorithm 6 step 2):
+ * from Y (s x n, ld s) compute R1 (n x n, ld n) = D R_0 N with
+ *   lu = 1: [M, N, P] = LU(Y) with partial pivoting, R_0 = R factor of M;
+ *   lu = 0: R_0 = R factor of Y, N = I (randomized CholeskyQR);
+ * D = sign(diag(R_0 N)). perm (device int32[s], nullable) receives the pivot
+ * order (position -> original row); Mout (nullable, s x n, ld s) the unit lower
+ * trapezoidal M. `prec` (FP64 or FP32) selects the arithmetic. */
+int rclupp_precond(const double* Y, int64_t s, int64_t n, int lu, int prec, double* R1, int32_t* perm, double* Mout,
+                   rclupp_info* d_info, hipStream_t stream);
+
+/* Fused tall pass (Algorithm 1 steps 1 and 3 around a given R):
+ *   W = X R^{-1} (row-wise substitution; R = NULL means R = I),
+ *   G = W^T W (if G != NULL, n x n, ld n),
+ * W (m x n, ld ldw) is written if W != NULL; W may equal X (in place). */
+int rclupp_trsm_gram(const double* X, int64_t m, int64_t n, int64_t ldx, const double* R, double* W, int64_t ldw,
+                     double* G, hipStream_t stream);
+
+/* Cholesky R^T R = G + shift I (upper R, n x n, ld n), shift = 0 or, with
+ * scholqr_shift = 1, 11(m n u + n(n+1) u) max_j G_jj (Algorithm 4). If Rprev is
+ * not NULL, Rout = R Rprev is also written (nullable). */
+int rclupp_chol(const double* G, int64_t n, int64_t m, int scholqr_shift, double* R, const double* Rprev,
+                double* Rout, int32_t stage, rclupp_info* d_info, hipStream_t stream);
+
+/* LU with partial pivoting of a tall X (m x n): M (m x n, ld ldm, rows in
+ * pivoted order, unit diagonal implied below, N in its upper n x n part as in
+ * LAPACK getrf), perm (device int32[m]: position -> original row). */
+int rclupp_tall_lu(const double* X, int64_t m, int64_t n, int64_t ldx, double* M, int64_t ldm, int32_t* perm,
+                   rclupp_info* d_info, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RCLUPP_H */

@@ -1,0 +1,255 @@
+// Sketch Y = S X with S = G / sqrt(s) generated on the fly (Algorithm 2 step 1;
+// Algorithm 7 step 2 with X = M; Algorithm 6 step 1).
+//
+// One pass over the tall operand. A workgroup owns a group of SM sketch rows
+// and NN columns and walks 64-row tiles of X (tile t, t + gridDim.x, ...): the
+// tile is staged in LDS (coalesced column reads, double-buffered), each of the
+// four waves takes 16 of its rows as four K-steps of v_mfma_f64_16x16x4_f64,
+// and the A operand (G) is produced in registers: lane l of a K-step holds the
+// G entry of tall row (4 ks + l/16) and slot row (l % 16) of every 16-row
+// M-block. Slot rows are mapped to sketch rows so that one Philox call of a
+// lane feeds four M-blocks of that same lane:
+//   M-block mb = 4a + u, slot i = 4c + t  ->  sketch row 64a + 16c + 4t + u,
+// i.e. group q = 16a + 4c + t and output u of Philox(j, q). Every G entry is
+// therefore generated exactly once per (workgroup column group).
+// Each workgroup writes its partial sum (fixed order over its tiles and
+// waves); a second kernel adds the partials in workgroup order and scales by
+// 1/sqrt(s), so the result is deterministic.
+#include "device_common.hpp"
+#include "launch.hpp"
+
+namespace rclupp {
+
+constexpr int SK_TK = 64;  // tall rows per tile
+constexpr int SK_THREADS = 256;
+
+template <int SM, int NN>
+struct SketchLds {
+  static constexpr int LDX = NN + 1;
+  static constexpr int TILE = SK_TK * LDX;
+  static constexpr int RED = SM * NN;
+  static constexpr int SIZE = (2 * TILE > RED) ? 2 * TILE : RED;
+};
+
+template <int SM, int NN>
+__global__ __launch_bounds__(SK_THREADS) void k_sketch_f64(const double* __restrict__ X, int64_t m, int n, int64_t ld,
+                                                           int64_t ntiles, uint64_t seed, double* __restrict__ Ypart,
+                                                           int64_t s_pad, int64_t n_pad, const int32_t* info) {
+  if (info_failed(info)) return;
+  constexpr int MB = SM / 16, NB = NN / 16, LDX = SketchLds<SM, NN>::LDX, TILE = SketchLds<SM, NN>::TILE;
+  constexpr int CPT = NN / 4;  // tile columns loaded per thread
+  __shared__ double lds[SketchLds<SM, NN>::SIZE];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int sg = blockIdx.y, col0 = blockIdx.z * NN;
+  const int lr = tid & 63, lc0 = (tid >> 6) * CPT;  // loader: row, first column
+
+  f64x4 acc[MB][NB];
+#pragma unroll
+  for (int a = 0; a < MB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  double pre[CPT];
+  auto load_tile = [&](int64_t t) {
+    const int64_t row = t * SK_TK + lr;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      const int col = col0 + lc0 + c;
+      pre[c] = (row < m && col < n) ? X[row + (int64_t)col * ld] : 0.0;
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) lds[buf * TILE + lr * LDX + lc0 + c] = pre[c];
+  };
+
+  // A-operand slot of this lane: i = lane % 16 = 4c + t, K row = lane / 16
+  const int ai = lane & 15, ak = lane >> 4;
+  const uint32_t qbase = (uint32_t)((sg * SM) / 4 + 4 * (ai >> 2) + (ai & 3));
+
+  int64_t t = blockIdx.x;
+  int buf = 0;
+  if (t < ntiles) {
+    load_tile(t);
+    store_tile(0);
+  }
+  __syncthreads();
+  for (; t < ntiles; t += gridDim.x) {
+    const int64_t tn = t + gridDim.x;
+    if (tn < ntiles) load_tile(tn);
+    const double* xs = lds + buf * TILE;
+#pragma unroll 1
+    for (int ks = 0; ks < 4; ++ks) {
+      const int rloc = 16 * wave + 4 * ks + ak;
+      const int64_t j = t * SK_TK + rloc;
+      double b[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) b[nb] = xs[rloc * LDX + 16 * nb + ai];
+#pragma unroll
+      for (int a = 0; a < SM / 64; ++a) {
+        f32x4 z = {0.f, 0.f, 0.f, 0.f};
+        if (j < m) z = normals4(seed, (uint64_t)j, qbase + 16u * (uint32_t)a);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double av = (double)z[u];
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) acc[4 * a + u][nb] = mfma_f64(av, b[nb], acc[4 * a + u][nb]);
+        }
+      }
+    }
+    if (tn < ntiles) store_tile(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  // Sum the four waves' partials in wave order through LDS, then store.
+  double* red = lds;
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int a = 0; a < MB; ++a)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int idx = ((a * NB + nb) * 4 + r) * 64 + lane;
+            const double v = (w == 0) ? acc[a][nb][r] : red[idx] + acc[a][nb][r];
+            if (w < 3) {
+              red[idx] = v;
+            } else {
+              // slot row l/16 + 4r of M-block a -> sketch row
+              const int64_t srow = (int64_t)sg * SM + 64 * (a >> 2) + 16 * r + 4 * (lane >> 4) + (a & 3);
+              const int64_t col = col0 + 16 * nb + (lane & 15);
+              Ypart[(int64_t)blockIdx.x * s_pad * n_pad + srow + col * s_pad] = v;
+            }
+          }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_sketch_reduce(const double* __restrict__ Ypart, int gx, int64_t s, int64_t n, int64_t s_pad,
+                                int64_t n_pad, double scale, double* __restrict__ Y, const int32_t* info) {
+  if (info_failed(info)) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= s * n) return;
+  const int64_t i = e % s, j = e / s;
+  const double* p = Ypart + i + j * s_pad;
+  const int64_t stride = s_pad * n_pad;
+  double acc = 0.0;
+  for (int b = 0; b < gx; ++b) acc += p[(int64_t)b * stride];
+  Y[i + j * s] = acc * scale;
+}
+
+__global__ void k_omega(uint64_t seed, int64_t s, int64_t j0, int64_t cols, float* __restrict__ G) {
+  const int64_t q4 = (s + 3) / 4;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= q4 * cols) return;
+  const int64_t q = e % q4, c = e / q4;
+  const f32x4 z = normals4(seed, (uint64_t)(j0 + c), (uint32_t)q);
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (4 * q + u < s) G[4 * q + u + c * s] = z[u];
+}
+
+__global__ void k_philox(const uint32_t* __restrict__ ctr, int64_t count, uint32_t k0, uint32_t k1,
+                         uint32_t* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const philox_out w = philox4x32_10(ctr[4 * e], ctr[4 * e + 1], ctr[4 * e + 2], ctr[4 * e + 3], k0, k1);
+  out[4 * e] = w.w0;
+  out[4 * e + 1] = w.w1;
+  out[4 * e + 2] = w.w2;
+  out[4 * e + 3] = w.w3;
+}
+
+int64_t pad_sketch_rows(int64_t s) { return (s + 63) / 64 * 64; }
+
+SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int gx_hint) {
+  (void)prec;
+  SketchPlan p{};
+  if (n <= 16) {
+    p.nn = 16;
+  } else if (n <= 32) {
+    p.nn = 32;
+  } else if (n <= 64) {
+    p.nn = 64;
+  } else {
+    p.nn = 128;
+  }
+  p.s_pad = pad_sketch_rows(s);
+  // accumulators per wave: (sm/16)(nn/16) f64x4 <= 32
+  const int max_sm = (p.nn == 16) ? 256 : (p.nn == 32) ? 256 : (p.nn == 64) ? 128 : 64;
+  p.sm = 64;
+  while (p.sm * 2 <= max_sm && p.s_pad % (p.sm * 2) == 0) p.sm *= 2;
+  p.gy = (int)(p.s_pad / p.sm);
+  p.gz = (int)((n + p.nn - 1) / p.nn);
+  p.n_pad = (int64_t)p.gz * p.nn;
+  p.ntiles = (m + SK_TK - 1) / SK_TK;
+  int gx = gx_hint > 0 ? gx_hint : 512;
+  const int per_chunk = p.gy * p.gz;
+  if (per_chunk > 1) gx = (gx + per_chunk - 1) / per_chunk;
+  if (gx < 1) gx = 1;
+  if (gx > p.ntiles) gx = (int)p.ntiles;
+  p.gx = gx;
+  p.part_bytes = (size_t)p.gx * (size_t)p.s_pad * (size_t)p.n_pad * sizeof(double);
+  return p;
+}
+
+template <int SM, int NN>
+static hipError_t launch_sk(const SketchPlan& p, const double* X, int64_t m, int64_t n, int64_t ld, uint64_t seed,
+                            double* Ypart, const int32_t* info, hipStream_t st) {
+  dim3 grid(p.gx, p.gy, p.gz);
+  hipLaunchKernelGGL((k_sketch_f64<SM, NN>), grid, dim3(SK_THREADS), 0, st, X, m, (int)n, ld, p.ntiles, seed, Ypart,
+                     p.s_pad, p.n_pad, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_sketch_partials(const SketchPlan& p, const double* X, int64_t m, int64_t n, int64_t ld, uint64_t seed,
+                                  int prec, double* Ypart, const int32_t* info, hipStream_t st) {
+  if (prec != 0) return hipErrorInvalidValue;
+  if (p.gx < 1 || p.ntiles < 1) return hipErrorInvalidValue;
+#define SK_CASE(SMV, NNV) \
+  if (p.sm == SMV && p.nn == NNV) return launch_sk<SMV, NNV>(p, X, m, n, ld, seed, Ypart, info, st);
+  SK_CASE(64, 16)
+  SK_CASE(128, 16)
+  SK_CASE(256, 16)
+  SK_CASE(64, 32)
+  SK_CASE(128, 32)
+  SK_CASE(256, 32)
+  SK_CASE(64, 64)
+  SK_CASE(128, 64)
+  SK_CASE(64, 128)
+#undef SK_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sketch_reduce(const SketchPlan& p, const double* Ypart, int64_t s, int64_t n, double scale, double* Y,
+                                const int32_t* info, hipStream_t st) {
+  const int64_t total = s * n;
+  const int threads = 256;
+  const int64_t blocks = (total + threads - 1) / threads;
+  hipLaunchKernelGGL(k_sketch_reduce, dim3((unsigned)blocks), dim3(threads), 0, st, Ypart, p.gx, s, n, p.s_pad,
+                     p.n_pad, scale, Y, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_omega(uint64_t seed, int64_t s, int64_t j0, int64_t cols, float* G, hipStream_t st) {
+  const int64_t total = (s + 3) / 4 * cols;
+  if (total <= 0) return hipSuccess;
+  const int threads = 256;
+  hipLaunchKernelGGL(k_omega, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0, st, seed, s, j0,
+                     cols, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_philox(const uint32_t* ctr, int64_t count, uint32_t k0, uint32_t k1, uint32_t* out, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int threads = 256;
+  hipLaunchKernelGGL(k_philox, dim3((unsigned)((count + threads - 1) / threads)), dim3(threads), 0, st, ctr, count,
+                     k0, k1, out);
+  return hipGetLastError();
+}
+
+}  // namespace rclupp

@@ -1,0 +1,269 @@
+// LU with partial pivoting of the tall X (m x n), P X = M N (Algorithm 7 step
+// 1, Algorithm 5 step 1), blocked right-looking with LU_NB-column panels:
+//   per column k of a panel: one workgroup reduces the per-workgroup argmax
+//     partials of |column k| (first row wins ties, LAPACK idamax), swaps rows
+//     k and p across all n columns and keeps the pivot row; then every
+//     workgroup scales its part of column k and updates the remaining panel
+//     columns, and records the argmax partial of column k+1;
+//   per panel: U12 = L11^{-1} A12 (one workgroup), then the trailing update
+//     A22 -= L21 U12 streams every row once and records the argmax partial of
+//     the next panel's first column.
+// The per-step update order equals that of the unblocked algorithm (the
+// trailing columns receive the panel's rank-1 updates in column order).
+// M is stored with its rows in pivoted order (position p holds original row
+// perm[p]); the upper n x n part holds N as in LAPACK getrf.
+#include <limits.h>
+
+#include "device_common.hpp"
+#include "launch.hpp"
+
+namespace rclupp {
+
+constexpr int LU_THREADS = 256;
+constexpr int LU_NB = 8;
+constexpr int LU_GRID = 1024;
+
+struct LuPartial {
+  double v;
+  int idx;
+  int bad;
+};
+
+// Block reduce (max |v|, lowest index on ties, OR of bad) and write one partial.
+__device__ void wg_argmax_write(double v, int idx, int bad, LuPartial* out) {
+  __shared__ double sv[LU_THREADS / 64];
+  __shared__ int si[LU_THREADS / 64], sb[LU_THREADS / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(v, off);
+    const int oi = __shfl_xor(idx, off);
+    const int ob = __shfl_xor(bad, off);
+    if (ov > v || (ov == v && oi < idx)) {
+      v = ov;
+      idx = oi;
+    }
+    bad |= ob;
+  }
+  if (lane == 0) {
+    sv[wave] = v;
+    si[wave] = idx;
+    sb[wave] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double bv = sv[0];
+    int bi = si[0], bb = sb[0];
+    for (int w = 1; w < LU_THREADS / 64; ++w) {
+      if (sv[w] > bv || (sv[w] == bv && si[w] < bi)) {
+        bv = sv[w];
+        bi = si[w];
+      }
+      bb |= sb[w];
+    }
+    out->v = bv;
+    out->idx = bi;
+    out->bad = bb;
+  }
+}
+
+__device__ __forceinline__ void track(double a, int64_t i, double& best, int& idx, int& bad) {
+  if (!is_finite(a)) bad = 1;
+  const double v = fabs(a);
+  if (v > best) {
+    best = v;
+    idx = (int)i;
+  }
+}
+
+// Copy X into M, perm = identity, argmax partials of column 0.
+__global__ __launch_bounds__(LU_THREADS) void k_lu_init(const double* __restrict__ X, int64_t ldx, int64_t m, int n,
+                                                        double* __restrict__ M, int64_t ldm, int32_t* __restrict__ perm,
+                                                        LuPartial* part, const int32_t* info) {
+  if (info_failed(info)) return;
+  double best = -1.0;
+  int idx = INT_MAX, bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * LU_THREADS + threadIdx.x; i < m; i += (int64_t)gridDim.x * LU_THREADS) {
+    for (int j = 0; j < n; ++j) M[i + j * ldm] = X[i + j * ldx];
+    perm[i] = (int32_t)i;
+    track(M[i], i, best, idx, bad);
+  }
+  wg_argmax_write(best, idx, bad, part + blockIdx.x);
+}
+
+// Pivot of column k: reduce partials, test, swap rows k and p, keep the pivot row.
+__global__ __launch_bounds__(LU_THREADS) void k_lu_pivot(double* __restrict__ M, int64_t ldm, int n, int k,
+                                                         int32_t* __restrict__ perm, const LuPartial* __restrict__ part,
+                                                         int nparts, double* __restrict__ prow, int32_t* info) {
+  __shared__ int s_p, s_fail;
+  if (info_failed(info)) return;
+  if (threadIdx.x == 0) {
+    double bv = part[0].v;
+    int bi = part[0].idx, bb = part[0].bad;
+    for (int w = 1; w < nparts; ++w) {
+      const LuPartial q = part[w];
+      if (q.v > bv || (q.v == bv && q.idx < bi)) {
+        bv = q.v;
+        bi = q.idx;
+      }
+      bb |= q.bad;
+    }
+    s_fail = 0;
+    if (bb) {
+      info_set(info, INFO_NONFINITE, STAGE_LU, k + 1);
+      s_fail = 1;
+    } else if (!(bv > 0.0)) {
+      info_set(info, INFO_LU_ZERO_PIVOT, STAGE_LU, k + 1);
+      s_fail = 1;
+    }
+    s_p = bi;
+    if (!s_fail && bi != k) {
+      const int32_t t = perm[k];
+      perm[k] = perm[bi];
+      perm[bi] = t;
+    }
+  }
+  __syncthreads();
+  if (s_fail) return;
+  const int p = s_p;
+  for (int j = threadIdx.x; j < n; j += LU_THREADS) {
+    const double a = M[k + j * ldm];
+    const double b = M[p + j * ldm];
+    if (p != k) {
+      M[k + j * ldm] = b;
+      M[p + j * ldm] = a;
+    }
+    prow[j] = b;
+  }
+}
+
+// Panel update at step k: rows i > k.
+__global__ __launch_bounds__(LU_THREADS) void k_lu_panel(double* __restrict__ M, int64_t ldm, int64_t m, int k, int c1,
+                                                         const double* __restrict__ prow, LuPartial* part,
+                                                         int want_next, const int32_t* info) {
+  if (info_failed(info)) return;
+  const double piv = prow[k];
+  double best = -1.0;
+  int idx = INT_MAX, bad = 0;
+  for (int64_t i = (int64_t)k + 1 + (int64_t)blockIdx.x * LU_THREADS + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * LU_THREADS) {
+    const double l = M[i + (int64_t)k * ldm] / piv;
+    M[i + (int64_t)k * ldm] = l;
+    for (int j = k + 1; j < c1; ++j) {
+      const double a = M[i + (int64_t)j * ldm] - l * prow[j];
+      M[i + (int64_t)j * ldm] = a;
+      if (j == k + 1) track(a, i, best, idx, bad);
+    }
+  }
+  if (want_next) wg_argmax_write(best, idx, bad, part + blockIdx.x);
+}
+
+// U12 = L11^{-1} A12 in place: rows c0..c1-1, columns c1..n-1 (unit lower L11).
+__global__ __launch_bounds__(LU_THREADS) void k_lu_trsm12(double* __restrict__ M, int64_t ldm, int c0, int c1, int n,
+                                                          const int32_t* info) {
+  if (info_failed(info)) return;
+  for (int j = c1 + threadIdx.x; j < n; j += LU_THREADS) {
+    for (int r = c0 + 1; r < c1; ++r) {
+      double a = M[r + (int64_t)j * ldm];
+      for (int t = c0; t < r; ++t) a -= M[r + (int64_t)t * ldm] * M[t + (int64_t)j * ldm];
+      M[r + (int64_t)j * ldm] = a;
+    }
+  }
+}
+
+// Trailing update rows i >= c1: M[i][j] -= sum_t M[i][t] U12[t][j] (t in panel,
+// ascending); argmax partial of column c1.
+__global__ __launch_bounds__(LU_THREADS) void k_lu_trailing(double* __restrict__ M, int64_t ldm, int64_t m, int c0,
+                                                            int c1, int n, LuPartial* part, const int32_t* info) {
+  if (info_failed(info)) return;
+  __shared__ double u[LU_NB * RCLUPP_SMALL_MAXN];
+  const int nb = c1 - c0, nt = n - c1;
+  for (int e = threadIdx.x; e < nb * nt; e += LU_THREADS) {
+    const int t = e % nb, j = e / nb;
+    u[e] = M[(c0 + t) + (int64_t)(c1 + j) * ldm];
+  }
+  __syncthreads();
+  double best = -1.0;
+  int idx = INT_MAX, bad = 0;
+  for (int64_t i = (int64_t)c1 + (int64_t)blockIdx.x * LU_THREADS + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * LU_THREADS) {
+    double l[LU_NB];
+#pragma unroll
+    for (int t = 0; t < LU_NB; ++t) l[t] = (t < nb) ? M[i + (int64_t)(c0 + t) * ldm] : 0.0;
+    for (int j = 0; j < nt; ++j) {
+      double a = M[i + (int64_t)(c1 + j) * ldm];
+#pragma unroll
+      for (int t = 0; t < LU_NB; ++t)
+        if (t < nb) a -= l[t] * u[t + j * nb];
+      M[i + (int64_t)(c1 + j) * ldm] = a;
+      if (j == 0) track(a, i, best, idx, bad);
+    }
+  }
+  wg_argmax_write(best, idx, bad, part + blockIdx.x);
+}
+
+__global__ void k_lu_extract_n(const double* __restrict__ M, int64_t ldm, int n, double* __restrict__ N,
+                               const int32_t* info) {
+  if (info_failed(info)) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int i = e % n, j = e / n;
+  N[e] = (i <= j) ? M[i + (int64_t)j * ldm] : 0.0;
+}
+
+__global__ void k_unit_lower(double* __restrict__ M, int64_t ldm, int n, const int32_t* info) {
+  if (info_failed(info)) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int i = e % n, j = e / n;
+  if (i <= j) M[i + (int64_t)j * ldm] = (i == j) ? 1.0 : 0.0;
+}
+
+size_t tall_lu_scratch_bytes(int64_t m, int64_t n) {
+  (void)n;
+  size_t b = (size_t)LU_GRID * sizeof(LuPartial);
+  b = (b + 255) / 256 * 256;
+  b += ((size_t)RCLUPP_SMALL_MAXN * sizeof(double) + 255) / 256 * 256;  // prow
+  (void)m;
+  return b;
+}
+
+hipError_t launch_tall_lu(const double* X, int64_t m, int64_t n, int64_t ldx, double* M, int64_t ldm, int32_t* perm,
+                          double* Nout, double* scratch, int32_t* info, hipStream_t st) {
+  if (n < 1 || n > RCLUPP_SMALL_MAXN || m < n) return hipErrorInvalidValue;
+  LuPartial* part = (LuPartial*)scratch;
+  size_t off = ((size_t)LU_GRID * sizeof(LuPartial) + 255) / 256 * 256;
+  double* prow = (double*)((char*)scratch + off);
+  int64_t rows_blocks = (m + LU_THREADS - 1) / LU_THREADS;
+  const int g = (int)(rows_blocks < LU_GRID ? rows_blocks : LU_GRID);
+  hipLaunchKernelGGL(k_lu_init, dim3(g), dim3(LU_THREADS), 0, st, X, ldx, m, (int)n, M, ldm, perm, part, info);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  for (int c0 = 0; c0 < n; c0 += LU_NB) {
+    const int c1 = (int)((c0 + LU_NB < n) ? c0 + LU_NB : n);
+    for (int k = c0; k < c1; ++k) {
+      hipLaunchKernelGGL(k_lu_pivot, dim3(1), dim3(LU_THREADS), 0, st, M, ldm, (int)n, k, perm, part, g, prow, info);
+      const int want_next = (k + 1 < c1) ? 1 : 0;
+      hipLaunchKernelGGL(k_lu_panel, dim3(g), dim3(LU_THREADS), 0, st, M, ldm, m, k, c1, prow, part, want_next, info);
+    }
+    if (c1 < n) {
+      hipLaunchKernelGGL(k_lu_trsm12, dim3(1), dim3(LU_THREADS), 0, st, M, ldm, c0, c1, (int)n, info);
+      hipLaunchKernelGGL(k_lu_trailing, dim3(g), dim3(LU_THREADS), 0, st, M, ldm, m, c0, c1, (int)n, part, info);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (Nout) {
+    hipLaunchKernelGGL(k_lu_extract_n, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, st, M, ldm, (int)n, Nout,
+                       info);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_unit_lower(double* M, int64_t m, int64_t n, int64_t ldm, const int32_t* info, hipStream_t st) {
+  (void)m;
+  hipLaunchKernelGGL(k_unit_lower, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, st, M, ldm, (int)n, info);
+  return hipGetLastError();
+}
+
+}  // namespace rclupp

@@ -1,0 +1,207 @@
+"""GPU parity of the six methods (Algorithms 2-7) against the oracle on the same
+seeded inputs, through the C ABI: orthogonality <= 1e-12, relative residual
+<= 1e-13, relative R error <= 1e-14 * kappa_2 (kappa_2 as prescribed by the
+generator). Sizes span several row tiles with ragged tails; the full-size
+1,048,576 x 64 workload is compared in full (the oracle finishes it in
+seconds)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gen import make_arrowhead, make_krylov, make_lowtri, make_svd
+from gpu_common import TOL_ORTH, TOL_RES, gpu, method_parity, require_gpu, to_dev, to_host
+
+pytestmark = gpu
+ALL = ["rclupp", "rcluppr", "cholqr2", "scholqr3", "lc2", "rcholqr"]
+
+
+@pytest.fixture(autouse=True)
+def _dev():
+    require_gpu()
+
+
+def _lib():
+    import paper_2412_06551_amd as lib
+    return lib
+
+
+@pytest.mark.parametrize("method", ALL)
+def test_small_config_all_methods(method):
+    # m = 2048, n = 32, kappa = 1e8, s = 2n = 64, seed 0
+    m, n, s, kappa = 2048, 32, 64, 1e8
+    x = make_svd(m, n, kappa, seed=0)
+    res = _lib().qr(to_dev(x), alg=method, s=s, seed=0)
+    if method == "cholqr2":
+        # kappa = 1e8 is at CholeskyQR2's limit (Section 2.1): require the oracle's outcome
+        orc = oracle.run(method, x)
+        if not orc.ok:
+            assert res.info_host()[0] == orc.info[0]
+            return
+    method_parity(x, method, s, 0, kappa, res)
+
+
+@pytest.mark.parametrize("method", ["rclupp", "rcluppr", "lc2", "rcholqr"])
+@pytest.mark.parametrize("kappa", [1e2, 1e6, 1e10, 1e13, 1e15])
+def test_kappa_sweep_ragged(method, kappa):
+    m, n, s = 30000 + 77, 50, 100
+    x = make_svd(m, n, kappa, seed=1)
+    res = _lib().qr(to_dev(x), alg=method, s=s, seed=5)
+    method_parity(x, method, s, 5, kappa, res)
+
+
+@pytest.mark.parametrize("method", ["cholqr2", "scholqr3"])
+@pytest.mark.parametrize("kappa", [1e2, 1e6])
+def test_baselines_in_range(method, kappa):
+    m, n = 12345, 64
+    x = make_svd(m, n, kappa, seed=2)
+    res = _lib().qr(to_dev(x), alg=method)
+    method_parity(x, method, 0, 0, kappa, res)
+
+
+@pytest.mark.parametrize("method,kappa", [("cholqr2", 1e12), ("scholqr3", 1e16)])
+def test_baselines_break_down_like_oracle(method, kappa):
+    x = make_svd(5000, 40, kappa, seed=3)
+    orc = oracle.run(method, x)
+    res = _lib().qr(to_dev(x), alg=method)
+    info = res.info_host()
+    if not orc.ok:
+        assert info[0] == orc.info[0] == oracle.CHOL_BREAKDOWN
+    else:  # outside the method's range the result is poor on both sides
+        assert oracle.orthogonality(to_host(res.Q)) > TOL_ORTH or info[0] != 0
+
+
+@pytest.mark.parametrize("n", [1, 2, 15, 16, 17, 33, 64, 65, 100, 128, 200, 256])
+def test_column_counts(n):
+    m = max(4 * n + 3, 3000)
+    kappa = 1e6
+    x = make_svd(m, n, kappa, seed=n)
+    for method in ("rclupp", "rcluppr"):
+        res = _lib().qr(to_dev(x), alg=method, s=2 * n, seed=1)
+        method_parity(x, method, 2 * n, 1, kappa, res)
+
+
+@pytest.mark.parametrize("m,n,s", [(64, 64, 64), (65, 64, 64), (130, 64, 128), (300, 32, 300)])
+def test_edge_shapes(m, n, s):
+    # m = n (square), s = n, s = m
+    x = make_svd(m, n, 1e4, seed=4)
+    for method in ("rclupp", "rcluppr", "lc2"):
+        res = _lib().qr(to_dev(x), alg=method, s=s, seed=2)
+        method_parity(x, method, s, 2, 1e4, res)
+
+
+def test_leading_dimension_and_simple_entry():
+    m, n = 9000, 48
+    x = make_svd(m, n, 1e9, seed=6)
+    X = to_dev(x, ld=9216)
+    a = _lib().qr(X, alg="rclupp", s=96, seed=3)
+    method_parity(x, "rclupp", 96, 3, 1e9, a)
+    Q, R, info = _lib().qr_simple(X, alg="rclupp", s=96, seed=3)
+    assert info[0] == 0
+    np.testing.assert_array_equal(to_host(Q), to_host(a.Q))
+    np.testing.assert_array_equal(to_host(R), to_host(a.R))
+    for method in ALL:
+        Q, R, info = _lib().qr_simple(X, alg=method, s=96, seed=3)
+        orc = oracle.run(method, x, s=96, seed=3)
+        assert info[0] == orc.info[0]
+
+
+def test_determinism():
+    x = make_svd(50000, 64, 1e12, seed=7)
+    X = to_dev(x)
+    a = _lib().qr(X, alg="rclupp", s=128, seed=9)
+    b = _lib().qr(X, alg="rclupp", s=128, seed=9)
+    np.testing.assert_array_equal(to_host(a.Q), to_host(b.Q))
+    np.testing.assert_array_equal(to_host(a.R), to_host(b.R))
+
+
+@pytest.mark.parametrize("method", ALL)
+def test_info_nonfinite_and_zero_column(method):
+    x = make_svd(4000, 16, 1e3, seed=8)
+    xn = x.copy(order="F")
+    xn[123, 5] = np.nan
+    res = _lib().qr(to_dev(xn), alg=method, s=32, seed=0)
+    orc = oracle.run(method, xn, s=32, seed=0)
+    assert res.info_host()[:3] == orc.info.tolist()[:3], (method, res.info_host(), orc.info)
+    xz = x.copy(order="F")
+    xz[:, 9] = 0.0
+    res = _lib().qr(to_dev(xz), alg=method, s=32, seed=0)
+    orc = oracle.run(method, xz, s=32, seed=0)
+    assert res.info_host()[0] == orc.info[0], (method, res.info_host(), orc.info)
+    if orc.info[0] == oracle.LU_ZERO_PIVOT:
+        assert res.info_host()[:3] == orc.info.tolist()[:3]
+
+
+def test_invalid_arguments_are_synchronous_errors():
+    from paper_2412_06551_amd import _native as nat
+    x = to_dev(make_svd(100, 8, 10.0, seed=0))
+    with pytest.raises(nat.RclError) as e:
+        _lib().qr(x, alg="rclupp", s=4)  # s < n
+    assert e.value.status == nat.ERR_INVALID_ARG
+    with pytest.raises(nat.RclError):
+        _lib().qr(x, alg="rclupp", s=101)  # s > m
+    big = torch.zeros((300, 1000), dtype=torch.float64, device="cuda").t()
+    with pytest.raises(nat.RclError) as e:
+        _lib().qr(big, alg="cholqr2")  # n > 256
+    assert e.value.status == nat.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("beta", [1e-10, 1e-20, 1e-30])
+def test_arrowhead_rcluppr(beta):
+    x = make_arrowhead(beta)
+    res = _lib().qr(to_dev(x), alg="rcluppr", s=100, seed=0)
+    orc = oracle.rcluppr(x, 100, 0)
+    assert res.info_host()[0] == 0 and orc.ok
+    m = oracle.metrics(x, to_host(res.Q), to_host(res.R))
+    assert m["orth"] <= TOL_ORTH and m["rel_res"] <= TOL_RES
+
+
+@pytest.mark.parametrize("a", [-0.6, -1.0])
+def test_lowtri_family(a):
+    x = make_lowtri(a)
+    for method in ("rclupp", "rcluppr", "lc2"):
+        res = _lib().qr(to_dev(x), alg=method, s=100, seed=0)
+        method_parity(x, method, 100, 0, 2.0, res)
+
+
+def test_krylov_rcluppr_invariants():
+    # numerically rank deficient: (Q, R) are not unique, only the invariants are compared
+    x = make_krylov(200000, 64, seed=0)
+    res = _lib().qr(to_dev(x), alg="rcluppr", s=128, seed=0)
+    assert res.info_host()[0] == 0
+    m = oracle.metrics(x, to_host(res.Q), to_host(res.R))
+    assert m["orth"] <= TOL_ORTH and m["rel_res"] <= TOL_RES
+    r = to_host(res.R)
+    assert np.all(np.diag(r) > 0) and np.all(np.tril(r, -1) == 0)
+
+
+def test_batched_matches_single():
+    rng = np.random.default_rng(0)
+    shapes = [(3000, 16), (5000, 32), (2000, 64), (7000, 24), (4000, 128)]
+    xs = [make_svd(m, n, 10 ** rng.uniform(2, 12), seed=100 + i) for i, (m, n) in enumerate(shapes)]
+    xs[2][5, 5] = np.nan  # one poisoned problem must not affect the others
+    Xs = [to_dev(x) for x in xs]
+    Qs, Rs, info = _lib().qr_batched(Xs, alg="rclupp", seeds=list(range(len(xs))))
+    info = info.cpu().numpy()
+    for i, x in enumerate(xs):
+        one = _lib().qr(Xs[i], alg="rclupp", seed=i)
+        assert info[i].tolist() == one.info_host()
+        if i == 2:
+            assert info[i][0] == oracle.NONFINITE
+            continue
+        np.testing.assert_array_equal(to_host(Qs[i]), to_host(one.Q))
+        np.testing.assert_array_equal(to_host(Rs[i]), to_host(one.R))
+
+
+# ------------------------------------------------------------------ full size
+@pytest.mark.parametrize("kappa", [1e4, 1e8, 1e12, 1e15])
+def test_full_size_rclupp(kappa):
+    # 1,048,576 x 64, s = 2n = 128, seed 0: the benchmark workload, compared in full
+    m, n, s = 1 << 20, 64, 128
+    x = make_svd(m, n, kappa, seed=0)
+    X = to_dev(x)
+    for method in ("rclupp", "rcluppr"):
+        res = _lib().qr(X, alg=method, s=s, seed=0)
+        torch.cuda.synchronize()
+        method_parity(x, method, s, 0, kappa, res)
+        del res

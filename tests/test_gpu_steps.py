@@ -1,0 +1,216 @@
+"""GPU parity of each step of the hot path against the oracle's step, on the
+same seeded inputs (inputs of each step come from the oracle, never from the
+HIP path). Called through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gen import make_svd
+from gpu_common import gpu, require_gpu, to_dev, to_host
+
+pytestmark = gpu
+
+
+@pytest.fixture(autouse=True)
+def _dev():
+    require_gpu()
+    import paper_2412_06551_amd  # noqa: F401
+
+
+def _lib():
+    import paper_2412_06551_amd as lib
+    return lib
+
+
+# ---------------------------------------------------------------- generator
+def test_philox_words_bit_exact():
+    rng = np.random.default_rng(0)
+    ctr = rng.integers(0, 2**32, size=(1000, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[0] = 0
+    ctr[1] = 0xFFFFFFFF
+    for k0, k1 in [(0, 0), (0xFFFFFFFF, 0xFFFFFFFF), (0xA4093822, 0x299F31D0), (12345, 678)]:
+        t = torch.from_numpy(ctr.view(np.int32)).cuda()
+        out = _lib().philox(t, k0, k1).cpu().numpy().view(np.uint32)
+        for i in range(0, 1000, 97):
+            want = oracle.philox4x32_10(ctr[i], [k0, k1])
+            assert out[i].tolist() == want.tolist()
+
+
+@pytest.mark.parametrize("s,cols,j0,seed", [(64, 3000, 0, 0), (13, 257, 5, 7), (128, 1000, (1 << 32) - 10, 2**40 + 3)])
+def test_omega_normals_match(s, cols, j0, seed):
+    g = to_host(_lib().omega(s, cols, seed, j0)).astype(np.float64)
+    want = oracle.omega(s, cols, seed, j0) * math.sqrt(s)  # unscaled normals
+    # both sides round the same Box-Muller value to float32; the device functions
+    # (logf, sincospif, sqrtf) are within a few float32 ulps
+    err = np.abs(g - want)
+    assert np.all(err <= 8 * 2.0**-24 * np.maximum(np.abs(want), 1.0)), err.max()
+
+
+# ---------------------------------------------------------------- sketch
+@pytest.mark.parametrize("m,n,s,seed", [(2048, 32, 64, 0), (5000 + 37, 64, 128, 3), (700, 16, 40, 1),
+                                        (3000, 100, 200, 2), (1025, 5, 5, 4)])
+def test_sketch_matches_oracle(m, n, s, seed):
+    x = make_svd(m, n, 1e6, seed=seed)
+    y = to_host(_lib().sketch(to_dev(x), s, seed))
+    want = oracle.sketch(x, s, seed)
+    om = oracle.omega(s, m, seed)
+    # |dY| <= (few float32 ulps of Omega) |Omega| |X| + summation error
+    bound = (8 * 2.0**-24 + 4 * m * oracle.U) * (np.abs(om) @ np.abs(x))
+    assert np.all(np.abs(y - want) <= bound)
+
+
+def test_sketch_leading_dimension():
+    x = make_svd(3000, 24, 1e3, seed=5)
+    a = to_host(_lib().sketch(to_dev(x, ld=3072), 48, 9))
+    b = to_host(_lib().sketch(to_dev(x), 48, 9))
+    np.testing.assert_array_equal(a, b)
+
+
+# ---------------------------------------------------------------- preconditioner
+@pytest.mark.parametrize("s,n,seed", [(64, 32, 0), (128, 64, 1), (100, 50, 2), (16, 16, 3), (256, 128, 4)])
+@pytest.mark.parametrize("kappa", [1e2, 1e8])
+def test_precond_lu_householder(s, n, seed, kappa):
+    x = make_svd(4 * s, n, kappa, seed=seed)
+    y = oracle.sketch(x, s, seed)  # oracle input, uploaded
+    R1, perm, M, info = _lib().precond(to_dev(y), lu=True, want_m=True)
+    assert info.cpu().tolist()[0] == 0
+    Mo, No, po, io = oracle.gepp(y)
+    assert io[0] == 0
+    np.testing.assert_array_equal(perm.cpu().numpy(), po)  # random data: no near-ties
+    # forward errors of the factors grow with the conditioning of the sketch
+    np.testing.assert_allclose(to_host(M), Mo, rtol=0, atol=1e-15 * kappa * n)
+    R0 = oracle.house_r(Mo)
+    r1o = oracle.trmm(R0, No)
+    r1o = np.sign(np.diag(r1o))[:, None] * r1o
+    r1 = to_host(R1)
+    assert np.linalg.norm(r1 - r1o) <= 1e-15 * kappa * n * np.linalg.norm(r1o)
+    assert np.all(np.diag(r1) > 0) and np.all(np.tril(r1, -1) == 0)
+    # both are (up to row signs) the R factor of Y: R1^T R1 = Y^T Y (eq. elu-ey)
+    g = y.T @ y
+    assert np.linalg.norm(r1.T @ r1 - g) <= 1e-13 * np.linalg.norm(g)
+
+
+@pytest.mark.parametrize("s,n", [(64, 32), (40, 40)])
+def test_precond_householder_only(s, n):
+    x = make_svd(8 * s, n, 1e4, seed=11)
+    y = oracle.sketch(x, s, 3)
+    R1, _, _, info = _lib().precond(to_dev(y), lu=False)
+    r0 = oracle.house_r(y)
+    r0 = np.sign(np.diag(r0))[:, None] * r0
+    assert np.linalg.norm(to_host(R1) - r0) <= 1e-13 * np.linalg.norm(r0)
+
+
+@pytest.mark.parametrize("case", ["zero", "zero_then_nan", "nan_first", "inf"])
+def test_precond_info_codes(case):
+    y = np.random.default_rng(0).standard_normal((32, 8))
+    if case in ("zero", "zero_then_nan"):
+        y[:, 3] = 0.0
+    if case == "zero_then_nan":
+        y[7, 6] = np.nan
+    if case == "nan_first":
+        y[9, 2] = np.nan
+        y[:, 5] = 0.0
+    if case == "inf":
+        y[0, 0] = np.inf
+    y = np.asfortranarray(y)
+    _, _, _, info = _lib().precond(to_dev(y), lu=True)
+    _, _, _, io = oracle.gepp(y)
+    assert info.cpu().tolist()[:3] == io.tolist()[:3]
+
+
+# ---------------------------------------------------------------- tall passes
+def _upper(n, seed, cond=None):
+    """A well-conditioned upper triangle with mixed-sign diagonal: the R factor of a
+    seeded 3n x n Gaussian (kappa ~ 5), rows flipped at random."""
+    rng = np.random.default_rng(seed)
+    r = np.linalg.qr(rng.standard_normal((3 * n + 2, n)), mode="r")
+    r = np.where(rng.random(n) < 0.5, -1.0, 1.0)[:, None] * r
+    return np.asfortranarray(np.triu(r))
+
+
+@pytest.mark.parametrize("m,n", [(1000, 1), (4096 + 77, 16), (3000, 32), (20000 + 5, 50), (9999, 64),
+                                 (5000, 100), (3000, 128), (1500, 256)])
+def test_trsm_gram_matches_oracle(m, n):
+    rng = np.random.default_rng(m + n)
+    x = np.asfortranarray(rng.standard_normal((m, n)))
+    R = _upper(n, n)
+    W, G = _lib().trsm_gram(to_dev(x), to_dev(R), gram=True)
+    wo = oracle.trsm(x, R)
+    w = to_host(W)
+    # substitution with a well-conditioned R: agreement to a few ulps of the row scale
+    assert np.max(np.abs(w - wo)) <= 1e-13 * np.max(np.abs(wo))
+    # and the computed W solves W R = X with a tiny componentwise residual (eq. ewy)
+    res = np.abs(w @ R - x)
+    assert np.all(res <= 4 * n * oracle.U * (np.abs(w) @ np.abs(R)) + 1e-300)
+    go = oracle.gram(wo)
+    g = to_host(G)
+    assert np.max(np.abs(g - go)) <= 1e-12 * np.max(np.abs(go))
+    np.testing.assert_array_equal(g, g.T)
+
+
+@pytest.mark.parametrize("m,n", [(5000, 10), (4096, 64), (3000, 200)])
+def test_gram_only(m, n):
+    x = np.asfortranarray(np.random.default_rng(n).standard_normal((m, n)))
+    _, G = _lib().trsm_gram(to_dev(x), None, gram=True)
+    go = oracle.gram(x)
+    assert np.max(np.abs(to_host(G) - go)) <= 1e-12 * np.max(np.abs(go))
+
+
+def test_trsm_in_place_and_ld():
+    m, n = 7000, 48
+    x = np.asfortranarray(np.random.default_rng(1).standard_normal((m, n)))
+    R = _upper(n, 2)
+    X = to_dev(x, ld=7040)
+    W, _ = _lib().trsm_gram(X, to_dev(R), gram=False, out=X)
+    wo = oracle.trsm(x, R)
+    np.testing.assert_allclose(to_host(X), wo, rtol=1e-12, atol=1e-12 * np.abs(wo).max())
+
+
+# ---------------------------------------------------------------- Cholesky
+@pytest.mark.parametrize("n", [1, 16, 50, 64, 128, 256])
+def test_chol_matches_oracle(n):
+    b = np.random.default_rng(n).standard_normal((3 * n + 5, n))
+    g = np.asfortranarray(b.T @ b)
+    Rp = _upper(n, 3 * n)
+    R, Rout, info = _lib().chol(to_dev(g), Rprev=to_dev(Rp))
+    assert info.cpu().tolist()[0] == 0
+    ro, io = oracle.chol(g)
+    np.testing.assert_allclose(to_host(R), ro, rtol=0, atol=1e-12 * np.abs(ro).max())
+    np.testing.assert_allclose(to_host(Rout), oracle.trmm(ro, Rp), rtol=0,
+                               atol=1e-12 * np.abs(ro).max() * np.abs(Rp).max() * n)
+
+
+def test_chol_shift_and_breakdown():
+    m, n = 100000, 20
+    b = np.random.default_rng(4).standard_normal((40, n))
+    g = np.asfortranarray(b.T @ b)
+    R, _, info = _lib().chol(to_dev(g), m=m, shift=True)
+    sigma = oracle.scholqr3_shift(m, n, float(np.max(np.diag(g))))
+    ro, _ = oracle.chol(g, shift=sigma)
+    np.testing.assert_allclose(to_host(R), ro, rtol=0, atol=1e-12 * np.abs(ro).max())
+    g2 = np.diag([4.0, 1.0, -1.0, 2.0])
+    _, _, info = _lib().chol(to_dev(np.asfortranarray(g2)), stage=5)
+    assert info.cpu().tolist()[:3] == [2, 5, 3]
+
+
+# ---------------------------------------------------------------- tall LU
+@pytest.mark.parametrize("m,n", [(1000, 8), (5000 + 13, 32), (20000, 50), (3000, 64), (2000, 100)])
+def test_tall_lu_matches_oracle(m, n):
+    x = np.asfortranarray(np.random.default_rng(m).standard_normal((m, n)))
+    M, perm, info = _lib().tall_lu(to_dev(x))
+    assert info.cpu().tolist()[0] == 0
+    Mo, No, po, io = oracle.gepp(x)
+    np.testing.assert_array_equal(perm.cpu().numpy(), po)
+    lu = to_host(M)
+    np.testing.assert_allclose(np.tril(lu, -1)[:, :n], np.tril(Mo, -1), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(np.triu(lu[:n]), No, rtol=0, atol=1e-12 * np.abs(No).max())
+
+
+def test_tall_lu_zero_pivot():
+    x = np.asfortranarray(np.random.default_rng(2).standard_normal((3000, 12)))
+    x[:, 7] = 0.0
+    _, _, info = _lib().tall_lu(to_dev(x))
+    assert info.cpu().tolist()[:3] == [1, 1, 8]
