@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the MI355X tall-skinny QR library.
+
+Workload (one step = one full RCLUPP factorization, Algorithm 2, every stage on
+the GPU): X = U diag(sigma) V^T, m = 1,048,576, n = 64, geometric spectrum with
+kappa_2 = 1e15, seed 0; Gaussian sketch with s = 2n = 128 rows, sketch seed 0;
+FP64 throughout. Inputs are resident in HBM before the timed region.
+
+Reported (one JSON line):
+  value       = algorithmic bytes of the tall passes / time per step (GB/s):
+                sketch 8mn + three substitution passes 16mn each = 56mn bytes;
+  tflops      = algorithmic FP64 flops / time: 2smn (sketch) + 2(mn^2 + mn(n+1))
+                (two substitution+Gram passes) + mn^2 (final substitution);
+  roofline    = the dominant kernel's algorithmic rate (per launch, from HIP
+                events recorded between the launches on the library's stream)
+                against MI355X's published peak for its binding resource;
+  cpu_baseline= the CPU oracle (oracle/) timed on the host cores on the same
+                input; the same leg also checks the GPU result against it.
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "tall QR GB/s + FP64 TFLOP/s (plain vs mixed, orth≤1e-12); batched QRs/s"
+M, N, S, KAPPA, SEED = 1 << 20, 64, 128, 1e15, 0
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, GB/s
+FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 (vector and matrix), TFLOP/s
+
+
+def tall_bytes(m, n):
+    """Algorithmic HBM bytes per RCLUPP step and per kernel launch."""
+    return {"sketch": 8 * m * n, "trsm_gram": 16 * m * n, "trsm_final": 16 * m * n,
+            "total": 8 * m * n + 3 * 16 * m * n}
+
+
+def tall_flops(m, n, s):
+    return {"sketch": 2 * s * m * n, "trsm_gram": m * n * n + m * n * (n + 1), "trsm_final": m * n * n,
+            "total": 2 * s * m * n + 2 * (m * n * n + m * n * (n + 1)) + m * n * n}
+
+
+def kernel_source_hash(name):
+    src = {"sketch": "k_sketch.hip", "trsm_gram": "k_tall.hip", "trsm_final": "k_tall.hip"}.get(name)
+    if src is None:
+        return None
+    with open(os.path.join(ROOT, "paper_2412_06551_amd", "csrc", src), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(name):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they were
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = t.get(name)
+    if not e or e.get("source_sha256_16") != kernel_source_hash(name):
+        return None
+    return e.get("bytes_per_launch")
+
+
+def roofline_entry(stages, m, n, s):
+    """Dominant kernel (largest total time among the tall kernels) and its rate."""
+    by = tall_bytes(m, n)
+    fl = tall_flops(m, n, s)
+    best = None
+    for name in ("sketch", "trsm_gram", "trsm_final"):
+        if name not in stages:
+            continue
+        ms, cnt = stages[name]
+        if best is None or ms > best[1]:
+            best = (name, ms, cnt)
+    if best is None:
+        return None
+    name, ms, cnt = best
+    avg_s = ms / cnt / 1e3
+    # binding resource from arithmetic intensity vs the FP64 ridge (78.6 TF / 8 TB/s)
+    ai = fl[name] / by[name]
+    if ai > FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9):
+        achieved = fl[name] / avg_s / 1e12
+        ent = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+               "frac": round(achieved / FP64_PEAK_TFLOPS, 4)}
+    else:
+        achieved = by[name] / avg_s / 1e9
+        ent = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    ent["kernel"] = name
+    ent["avg_launch_ms"] = round(ms / cnt, 5)
+    ent["launches"] = cnt
+    ent["traffic"] = measured_traffic(name)
+    return ent
+
+
+def cpu_baseline(x, s, seed, q_gpu, r_gpu, budget_s=12.0):
+    """Oracle RCLUPP on the host cores (same input), plus the GPU result's accuracy."""
+    import numpy as np
+
+    import oracle
+    m, n = x.shape
+    times = []
+    res = None
+    t_end = time.time() + budget_s
+    while not times or (time.time() < t_end and len(times) < 5):
+        t0 = time.perf_counter()
+        res = oracle.rclupp(x, s, seed)
+        times.append(time.perf_counter() - t0)
+    t = min(times)
+    met = oracle.metrics(x, q_gpu, r_gpu)
+    rerr = float(np.linalg.norm(r_gpu - res.R) / np.linalg.norm(res.R))
+    base = {"value": round(tall_bytes(m, n)["total"] / t / 1e9, 3), "unit": "GB/s", "cores": oracle.max_threads(),
+            "kind": "oracle", "seconds_per_qr": round(t, 3),
+            "sample": "full workload, %d run(s) of oracle RCLUPP (best taken)" % len(times)}
+    acc = {"orth": met["orth"], "rel_res": met["rel_res"], "r_rel_err_vs_oracle": rerr,
+           "oracle_info": int(res.info[0])}
+    return base, acc
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-extras", action="store_true", help="skip the other methods")
+    ap.add_argument("--kappa", type=float, default=KAPPA)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2412_06551_amd as lib
+    from paper_2412_06551_amd import _native as nat
+    from gen import make_svd
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    m, n, s = M, N, S
+    print("bench: generating %dx%d kappa=%.0e input" % (m, n, args.kappa), file=sys.stderr, flush=True)
+    x = make_svd(m, n, args.kappa, seed=SEED)
+    X = torch.empty((n, m), dtype=torch.float64, device=dev).t()
+    X.copy_(torch.from_numpy(x))
+    Q = torch.empty((n, m), dtype=torch.float64, device=dev).t()
+    R = torch.empty((n, n), dtype=torch.float64, device=dev).t()
+    info = torch.zeros(4, dtype=torch.int32, device=dev)
+    ws = torch.empty(lib.workspace_size("rclupp", m, n, s), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(alg="rclupp"):
+        lib.qr(X, alg=alg, s=s, seed=SEED, Q=Q, R=R, workspace=ws if alg == "rclupp" else None, info=info,
+               stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    gpu_info = info.cpu().tolist()
+    print("bench: rclupp %.4f ms/step info=%s" % (ms, gpu_info), file=sys.stderr, flush=True)
+
+    # stage timing over a second timed region (events between the library's launches)
+    nat.trace_enable(64 * args.steps)
+    for _ in range(args.steps):
+        step()
+    stages = nat.trace_read()
+    nat.trace_enable(0)
+    torch.cuda.synchronize()
+
+    by, fl = tall_bytes(m, n), tall_flops(m, n, s)
+    out = {
+        "metric": METRIC,
+        "value": round(by["total"] / (ms / 1e3) / 1e9, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "rclupp m=%d n=%d s=%d kappa=%.0e (SVD-based geometric spectrum, seed %d)"
+                               % (m, n, s, args.kappa, SEED),
+                   "method": "RCLUPP (Algorithm 2)", "m": m, "n": n, "s": s, "kappa": args.kappa},
+        "tflops": round(fl["total"] / (ms / 1e3) / 1e12, 3),
+        "gpu_info": gpu_info,
+        "stages_ms_per_step": {k: round(v[0] / args.steps, 5) for k, v in stages.items()},
+        "roofline": roofline_entry(stages, m, n, s),
+    }
+
+    if not args.no_extras:
+        extra = {}
+        for alg in ("rcluppr", "cholqr2", "scholqr3", "lc2", "rcholqr"):
+            lib.qr(X, alg=alg, s=s, seed=SEED)
+            torch.cuda.synchronize()
+            k = max(2, args.steps // 4)
+            a0 = torch.cuda.Event(enable_timing=True)
+            a1 = torch.cuda.Event(enable_timing=True)
+            a0.record(stream)
+            last = None
+            for _ in range(k):
+                last = lib.qr(X, alg=alg, s=s, seed=SEED)
+            a1.record(stream)
+            torch.cuda.synchronize()
+            t = a0.elapsed_time(a1) / k
+            extra[alg] = {"ms": round(t, 4), "info": last.info_host()}
+        out["other_methods_ms"] = extra
+        step()
+        torch.cuda.synchronize()
+
+    if not args.no_cpu:
+        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
+        q = np.asfortranarray(Q.cpu().numpy())
+        r = np.asfortranarray(R.cpu().numpy())
+        base, acc = cpu_baseline(x, s, SEED, q, r)
+        out["cpu_baseline"] = base
+        out["accuracy"] = acc
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

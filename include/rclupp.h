@@ -224,6 +224,20 @@ int rclupp_chol(const double* G, int64_t n, int64_t m, int scholqr_shift, double
 int rclupp_tall_lu(const double* X, int64_t m, int64_t n, int64_t ldx, double* M, int64_t ldm, int32_t* perm,
                    rclupp_info* d_info, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Stage timing (profiling aid). rclupp_trace_enable(max_marks > 0) makes every
+ * later rclupp_qr_ex call record a hipEvent on its stream before each stage
+ * (sketch, sketch_reduce, precond, tall_lu, gram, trsm_gram, gram_reduce,
+ * chol, trsm_final) and after its last stage, up to max_marks events in all;
+ * max_marks = 0 turns it off. rclupp_trace_read synchronizes on the recorded
+ * events, sums the elapsed time per stage name over all traced calls, writes
+ * up to max_stages entries (names: max_stages x name_len chars, ms: total
+ * milliseconds, launches: number of occurrences; host arrays), sets *count to
+ * the number of distinct stages and clears the record.
+ * ------------------------------------------------------------------------- */
+int rclupp_trace_enable(int max_marks);
+int rclupp_trace_read(int max_stages, char* names, int name_len, float* ms, int* launches, int* count);
+
 #ifdef __cplusplus
 }
 #endif

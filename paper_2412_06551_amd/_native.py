@@ -28,6 +28,7 @@ EXPORTS = [
     "rclupp_last_info", "rclupp_status_string", "rclupp_workspace_size", "rclupp_qr_ex",
     "rclupp_batched_workspace_size", "rclupp_qr_batched", "rclupp_omega", "rclupp_philox",
     "rclupp_sketch", "rclupp_precond", "rclupp_trsm_gram", "rclupp_chol", "rclupp_tall_lu",
+    "rclupp_trace_enable", "rclupp_trace_read",
 ]
 
 
@@ -80,6 +81,8 @@ def load(path: str = LIB_PATH):
         "rclupp_trsm_gram": [P, I64, I64, I64, P, P, I64, P, P],
         "rclupp_chol": [P, I64, I64, ctypes.c_int, P, P, P, I32, P, P],
         "rclupp_tall_lu": [P, I64, I64, I64, P, I64, P, P, P],
+        "rclupp_trace_enable": [ctypes.c_int],
+        "rclupp_trace_read": [ctypes.c_int, ctypes.c_char_p, ctypes.c_int, P, P, P],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -96,6 +99,25 @@ def status_string(status: int) -> str:
         return load().rclupp_status_string(int(status)).decode()
     except Exception:  # pragma: no cover - only used in error paths
         return "status %d" % status
+
+
+def trace_enable(max_marks: int) -> None:
+    check(load().rclupp_trace_enable(int(max_marks)), "rclupp_trace_enable")
+
+
+def trace_read(max_stages: int = 32, name_len: int = 32):
+    """{stage name: (total ms, launches)} for the traced calls since trace_enable."""
+    names = ctypes.create_string_buffer(max_stages * name_len)
+    ms = (ctypes.c_float * max_stages)()
+    cnt = (ctypes.c_int * max_stages)()
+    count = ctypes.c_int()
+    check(load().rclupp_trace_read(max_stages, names, name_len, ms, cnt, ctypes.byref(count)), "rclupp_trace_read")
+    out = {}
+    raw = names.raw
+    for k in range(min(count.value, max_stages)):
+        nm = raw[k * name_len:(k + 1) * name_len].split(b"\0", 1)[0].decode()
+        out[nm] = (float(ms[k]), int(cnt[k]))
+    return out
 
 
 def check(status: int, what: str) -> None:

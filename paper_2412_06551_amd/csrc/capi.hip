@@ -21,6 +21,8 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
+#include <vector>
 
 #include "../../include/rclupp.h"
 #include "launch.hpp"
@@ -116,6 +118,26 @@ __global__ void k_zero_info(rclupp_info* info) {
     if (e_ != hipSuccess) return RCLUPP_ERR_HIP; \
   } while (0)
 
+// ---- optional stage timing: an event is recorded on the stream before every
+// stage of rclupp_qr_ex and after its last one (profiling aid, off by default).
+struct TraceMark {
+  const char* name;  // stage that starts at this mark (nullptr = end of a call)
+  hipEvent_t ev;
+};
+std::mutex g_trace_mu;
+bool g_trace_on = false;
+std::vector<hipEvent_t> g_trace_pool;
+std::vector<TraceMark> g_trace_marks;
+
+void trace_mark(const char* name, hipStream_t st) {
+  if (!g_trace_on) return;
+  std::lock_guard<std::mutex> lk(g_trace_mu);
+  if (g_trace_marks.size() >= g_trace_pool.size()) return;
+  hipEvent_t ev = g_trace_pool[g_trace_marks.size()];
+  if (hipEventRecord(ev, st) == hipSuccess) g_trace_marks.push_back({name, ev});
+}
+#define STAGE(name) trace_mark(name, st)
+
 // The CholeskyQR2 tail, Q holds nothing yet: Q_1 = X R_1^{-1} is the first pass.
 int tail_cholqr2(const Layout& L, char* ws, const double* X, int64_t m, int64_t n, int64_t ld, double* Q, double* R,
                  int32_t* info, hipStream_t st) {
@@ -127,12 +149,19 @@ int tail_cholqr2(const Layout& L, char* ws, const double* X, int64_t m, int64_t 
   double* g = (double*)(ws + L.g);
   double* small = (double*)(ws + L.small);
   const int np = L.tp.np;
+  STAGE("trsm_gram");
   HIPCHK(launch_tall_pass(L.tp, X, ld, m, n, r1, Q, ld, gpart, info, st));
+  STAGE("gram_reduce");
   HIPCHK(launch_gram_reduce(L.tp, gpart, n, g, info, st));
+  STAGE("chol");
   HIPCHK(launch_chol(g, np, n, m, 0, r2, r3, 0, r1, nullptr, 0, small, info, RCLUPP_STAGE_CHOL_A, st));
+  STAGE("trsm_gram");
   HIPCHK(launch_tall_pass(L.tp, Q, ld, m, n, r2, Q, ld, gpart, info, st));
+  STAGE("gram_reduce");
   HIPCHK(launch_gram_reduce(L.tp, gpart, n, g, info, st));
+  STAGE("chol");
   HIPCHK(launch_chol(g, np, n, m, 0, r4, R, 1, r3, nullptr, 0, small, info, RCLUPP_STAGE_CHOL_B, st));
+  STAGE("trsm_final");
   HIPCHK(launch_tall_pass(L.tp, Q, ld, m, n, r4, Q, ld, gpart, info, st));  // Gram unused
   return RCLUPP_OK;
 }
@@ -146,9 +175,13 @@ int tail_cholqr1(const Layout& L, char* ws, const double* X, int64_t m, int64_t 
   double* g = (double*)(ws + L.g);
   double* small = (double*)(ws + L.small);
   const int np = L.tp.np;
+  STAGE("trsm_gram");
   HIPCHK(launch_tall_pass(L.tp, X, ld, m, n, r1, Q, ld, gpart, info, st));
+  STAGE("gram_reduce");
   HIPCHK(launch_gram_reduce(L.tp, gpart, n, g, info, st));
+  STAGE("chol");
   HIPCHK(launch_chol(g, np, n, m, 0, r2, R, 1, r1, nullptr, 0, small, info, RCLUPP_STAGE_CHOL_A, st));
+  STAGE("trsm_final");
   HIPCHK(launch_tall_pass(L.tp, Q, ld, m, n, r2, Q, ld, gpart, info, st));  // Gram unused
   return RCLUPP_OK;
 }
@@ -157,7 +190,9 @@ int sketch_into(const Layout& L, char* ws, const double* A, int64_t m, int64_t n
                 uint64_t seed, int prec, int32_t* info, hipStream_t st) {
   double* ypart = (double*)(ws + L.ypart);
   double* y = (double*)(ws + L.y);
+  STAGE("sketch");
   HIPCHK(launch_sketch_partials(L.sk, A, m, n, lda, seed, prec, ypart, info, st));
+  STAGE("sketch_reduce");
   HIPCHK(launch_sketch_reduce(L.sk, ypart, s, n, 1.0 / std::sqrt((double)s), y, info, st));
   return RCLUPP_OK;
 }
@@ -175,41 +210,55 @@ int run_method(int alg, const Layout& L, char* ws, const double* X, int64_t m, i
   switch (alg) {
     case RCLUPP_ALG_RCLUPP:
       if ((rc = sketch_into(L, ws, X, m, n, ld, s, seed, sk_prec, info, st))) return rc;
+      STAGE("precond");
       HIPCHK(launch_precond((double*)(ws + L.y), s, n, 1, lu_prec, nullptr, 0, r1, nullptr, nullptr, nullptr, small,
                             info, RCLUPP_STAGE_QR, st));
       return tail_cholqr2(L, ws, X, m, n, ld, Q, R, info, st);
     case RCLUPP_ALG_RCHOLQR:
       if ((rc = sketch_into(L, ws, X, m, n, ld, s, seed, sk_prec, info, st))) return rc;
+      STAGE("precond");
       HIPCHK(launch_precond((double*)(ws + L.y), s, n, 0, lu_prec, nullptr, 0, r1, nullptr, nullptr, nullptr, small,
                             info, RCLUPP_STAGE_QR, st));
       return tail_cholqr1(L, ws, X, m, n, ld, Q, R, info, st);
     case RCLUPP_ALG_RCLUPPR: {
       int32_t* perm = (int32_t*)(ws + L.perm);
       double* nmat = (double*)(ws + L.nmat);
+      STAGE("tall_lu");
       HIPCHK(launch_tall_lu(X, m, n, ld, Q, ld, perm, nmat, (double*)(ws + L.lu), info, st));
       HIPCHK(launch_unit_lower(Q, m, n, ld, info, st));
       if ((rc = sketch_into(L, ws, Q, m, n, ld, s, seed, sk_prec, info, st))) return rc;
+      STAGE("precond");
       HIPCHK(launch_precond((double*)(ws + L.y), s, n, 0, lu_prec, nmat, n, r1, nullptr, nullptr, nullptr, small, info,
                             RCLUPP_STAGE_QR, st));
       return tail_cholqr2(L, ws, X, m, n, ld, Q, R, info, st);
     }
     case RCLUPP_ALG_CHOLQR2:
+      STAGE("gram");
       HIPCHK(launch_tall_pass(L.tp, X, ld, m, n, nullptr, nullptr, ld, gpart, info, st));
+      STAGE("gram_reduce");
       HIPCHK(launch_gram_reduce(L.tp, gpart, n, g, info, st));
+      STAGE("chol");
       HIPCHK(launch_chol(g, np, n, m, 0, r1, nullptr, 0, nullptr, nullptr, 0, small, info, RCLUPP_STAGE_PRECOND, st));
       return tail_cholqr1(L, ws, X, m, n, ld, Q, R, info, st);
     case RCLUPP_ALG_SCHOLQR3:
+      STAGE("gram");
       HIPCHK(launch_tall_pass(L.tp, X, ld, m, n, nullptr, nullptr, ld, gpart, info, st));
+      STAGE("gram_reduce");
       HIPCHK(launch_gram_reduce(L.tp, gpart, n, g, info, st));
+      STAGE("chol");
       HIPCHK(launch_chol(g, np, n, m, 1, r1, nullptr, 0, nullptr, nullptr, 0, small, info, RCLUPP_STAGE_PRECOND, st));
       return tail_cholqr2(L, ws, X, m, n, ld, Q, R, info, st);
     case RCLUPP_ALG_LC2: {
       int32_t* perm = (int32_t*)(ws + L.perm);
       double* nmat = (double*)(ws + L.nmat);
+      STAGE("tall_lu");
       HIPCHK(launch_tall_lu(X, m, n, ld, Q, ld, perm, nmat, (double*)(ws + L.lu), info, st));
       HIPCHK(launch_unit_lower(Q, m, n, ld, info, st));
+      STAGE("gram");
       HIPCHK(launch_tall_pass(L.tp, Q, ld, m, n, nullptr, nullptr, ld, gpart, info, st));
+      STAGE("gram_reduce");
       HIPCHK(launch_gram_reduce(L.tp, gpart, n, g, info, st));
+      STAGE("chol");
       HIPCHK(launch_chol(g, np, n, m, 0, r1, nullptr, 0, nullptr, nmat, n, small, info, RCLUPP_STAGE_QR, st));
       return tail_cholqr1(L, ws, X, m, n, ld, Q, R, info, st);
     }
@@ -301,7 +350,57 @@ int rclupp_qr_ex(int alg, const double* X, int64_t m, int64_t n, int64_t ld, int
   rclupp_info* info = d_info ? d_info : (rclupp_info*)(w + L.info);
   hipLaunchKernelGGL(k_zero_info, dim3(1), dim3(64), 0, stream, info);
   if (hipGetLastError() != hipSuccess) return RCLUPP_ERR_HIP;
-  return run_method(alg, L, w, X, m, n, ld, s, seed, Q, R, opts, (int32_t*)info, stream);
+  const int rc2 = run_method(alg, L, w, X, m, n, ld, s, seed, Q, R, opts, (int32_t*)info, stream);
+  trace_mark(nullptr, stream);
+  return rc2;
+}
+
+int rclupp_trace_enable(int max_marks) {
+  std::lock_guard<std::mutex> lk(g_trace_mu);
+  g_trace_marks.clear();
+  if (max_marks <= 0) {
+    g_trace_on = false;
+    return RCLUPP_OK;
+  }
+  while ((int)g_trace_pool.size() < max_marks) {
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) return RCLUPP_ERR_HIP;
+    g_trace_pool.push_back(ev);
+  }
+  g_trace_on = true;
+  return RCLUPP_OK;
+}
+
+int rclupp_trace_read(int max_stages, char* names, int name_len, float* ms, int* launches, int* count) {
+  if (!count || (max_stages > 0 && (!names || !ms || !launches || name_len < 2))) return RCLUPP_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_trace_mu);
+  std::vector<std::string> keys;
+  std::vector<float> tot;
+  std::vector<int> cnt;
+  for (size_t i = 0; i + 1 < g_trace_marks.size(); ++i) {
+    if (!g_trace_marks[i].name) continue;
+    if (hipEventSynchronize(g_trace_marks[i + 1].ev) != hipSuccess) return RCLUPP_ERR_HIP;
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, g_trace_marks[i].ev, g_trace_marks[i + 1].ev) != hipSuccess) return RCLUPP_ERR_HIP;
+    size_t k = 0;
+    while (k < keys.size() && keys[k] != g_trace_marks[i].name) ++k;
+    if (k == keys.size()) {
+      keys.push_back(g_trace_marks[i].name);
+      tot.push_back(0.f);
+      cnt.push_back(0);
+    }
+    tot[k] += t;
+    cnt[k] += 1;
+  }
+  *count = (int)keys.size();
+  for (int k = 0; k < (int)keys.size() && k < max_stages; ++k) {
+    std::strncpy(names + (size_t)k * name_len, keys[k].c_str(), (size_t)name_len - 1);
+    names[(size_t)k * name_len + name_len - 1] = 0;
+    ms[k] = tot[k];
+    launches[k] = cnt[k];
+  }
+  g_trace_marks.clear();
+  return RCLUPP_OK;
 }
 
 int rclupp_qr(const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, uint64_t seed, double* Q, double* R,
