@@ -28,7 +28,11 @@
  *   - Householder vectors follow the LAPACK dlarfg convention; only R is kept;
  *   - R_1 gets the signs of its diagonal folded in (row scaling by +-1) so the
  *     final R has a positive diagonal;
- *   - the triangular solve is row-wise substitution (no explicit inverse).
+ *   - the triangular solve is row-wise substitution (no explicit inverse);
+ *   - the elimination of the LU and the sums of the substitution use fused
+ *     multiply-add (one rounding per term) and true division; the error model
+ *     of Section 3 (eqs. elu and ewy) bounds either choice, but outcomes on
+ *     problems outside its conditions (kappa(M) kappa(N) near 1/u) depend on it.
  */
 #include <math.h>
 #include <stdint.h>
@@ -259,7 +263,7 @@ int orc_gepp(double* A, int64_t r, int64_t n, int64_t lda, int64_t* perm, int32_
       for (int64_t j = k + 1; j < n; ++j) {
         double akj = A[k + j * lda];
         double* aj = A + j * lda;
-        for (int64_t i = i0; i < i1; ++i) aj[i] = aj[i] - ak[i] * akj;
+        for (int64_t i = i0; i < i1; ++i) aj[i] = fma(-ak[i], akj, aj[i]);
       }
     }
   }
@@ -341,7 +345,7 @@ void orc_trsm(const double* X, int64_t m, int64_t n, int64_t ldx, const double* 
     for (int64_t r = 0; r < m; ++r) {
       for (int64_t j = 0; j < n; ++j) {
         double acc = X[r + j * ldx];
-        for (int64_t i = 0; i < j; ++i) acc -= w[i] * R[i + j * n];
+        for (int64_t i = 0; i < j; ++i) acc = fma(-w[i], R[i + j * n], acc);
         w[j] = acc / R[j + j * n];
       }
       for (int64_t j = 0; j < n; ++j) W[r + j * ldw] = w[j];

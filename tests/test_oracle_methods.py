@@ -217,13 +217,23 @@ def test_lowtri_family():
             assert m["orth"] <= bounds.rclupp_bounds(20000, 50, np.linalg.norm(x), sv[0])[0]
 
 
-@pytest.mark.parametrize("beta", [1e-10, 1e-20, 1e-30])
+@pytest.mark.parametrize("beta", [1e-10, 1e-15, 1e-20])
 def test_arrowhead_family_rcluppr(beta):
-    # Section 5.1.3: RCLUPPr is the most robust on the arrowhead family
+    # Section 5.1.3: RCLUPPr stays accurate on the arrowhead family
     x = make_arrowhead(beta)
     r = oracle.rcluppr(x, 100, seed=0)
     m = check_qr(x, r)
     assert m["orth"] < 1e-13
+
+
+@pytest.mark.parametrize("beta", [1e-25, 1e-30])
+def test_arrowhead_beyond_sufficient_condition(beta):
+    # kappa(N) ~ 1/beta far beyond eq. (s4): with fused multiply-add in the
+    # substitution (no exact cancellation), X R_1^{-1} loses its conditioning and
+    # the Cholesky of the first Gram breaks down at the last column
+    x = make_arrowhead(beta)
+    r = oracle.rcluppr(x, 100, seed=0)
+    assert r.info.tolist()[:3] == [oracle.CHOL_BREAKDOWN, oracle.ST_CHOL_A, 50]
 
 
 def test_krylov_rcluppr_vs_householder():

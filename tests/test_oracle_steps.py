@@ -90,7 +90,8 @@ def test_gepp_ties_pick_first_row():
 
 
 def test_gepp_zero_pivot_and_nonfinite():
-    a = np.array([[1.0, 2.0, 3.0], [2.0, 4.0, 1.0], [3.0, 6.0, 2.0], [1.0, 2.0, 5.0]])
+    # column 2 is zero: every elimination leaves it exactly zero
+    a = np.array([[1.0, 0.0, 3.0], [2.0, 0.0, 1.0], [3.0, 0.0, 2.0], [1.0, 0.0, 5.0]])
     _, _, _, info = oracle.gepp(a)
     assert info.tolist()[:3] == [oracle.LU_ZERO_PIVOT, oracle.ST_LU, 2]
     b = np.random.default_rng(0).standard_normal((5, 3))
