@@ -1,0 +1,561 @@
+// Register-resident small dense stages for n <= 64, one workgroup of 1024
+// threads each (these steps are O(s n^2) and O(n^3): their time is the length
+// of the chain of dependent column steps, so the layout is chosen to make each
+// step short):
+//   k_precond_reg : [M, N, P] = LU(Y) with partial pivoting (eq. elu), the R
+//                   factor R_0 of M by Householder reflections (eq. eh, Q_s
+//                   never formed), R_1 = D R_0 N with D = sign(diag(R_0 N))
+//                   (eq. ey). Algorithm 2 steps 2-4; Algorithm 7 steps 3-4
+//                   with an external N; Algorithm 6 step 2 without the LU.
+//   k_chol_reg    : upper Cholesky of G (+ the shift of Algorithm 4), then an
+//                   optional product with an earlier factor (R_3 = R_2 R_1,
+//                   R = R_4 R_3; eqs. C4, C8) or an optional right factor with
+//                   the sign fix (LC2's R_1 = D S_c N, Algorithm 5).
+//
+// Layout: thread (wave w, lane l) owns column j = 4w + l/16 and the rows
+// i = l%16 + 16a, a < A. The 16 lanes of a DPP row therefore hold one whole
+// column: a column reduction is four DPP exchanges inside one wave. A column
+// step is: the wave owning column k reduces it (pivot search, or the
+// reflector's norm), publishes a vector of s values to LDS, one barrier, then
+// every thread applies a rank-1 update to the A values it holds. Rows are
+// never moved: the LU keeps a position for every row (pivoting swaps
+// positions only), so the pivot search scans the rows at positions >= k and
+// ties go to the smaller position, as in LAPACK's getrf.
+//
+// The n x n products (R_0 N, R R_prev, R N) run on FP64 MFMA 16x16x4 from LDS
+// tables, one 16 x 16 output block per wave.
+#include <limits.h>
+
+#include "device_common.hpp"
+#include "launch.hpp"
+
+namespace rclupp {
+
+constexpr int DN_THREADS = 1024;
+constexpr int DN_NP = 64;          // largest n handled here
+constexpr int DN_LD = DN_NP + 1;   // row stride of the 64 x 64 LDS tables
+
+// ---- DPP exchanges within 16-lane rows ----------------------------------------
+constexpr int DPP_XOR1 = 0xB1;         // quad_perm [1,0,3,2]
+constexpr int DPP_XOR2 = 0x4E;         // quad_perm [2,3,0,1]
+constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <- lane 7-i within each 8
+constexpr int DPP_MIRROR = 0x140;       // lane i <- lane 15-i within each 16
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_b32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp(int v) {
+  return dpp_b32<CTRL>(v);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(dpp_b32<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_b32<CTRL>((int)b), hi = dpp_b32<CTRL>((int)(b >> 32));
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+// Sum over the 16 lanes of a DPP row. Each exchange pairs lanes that then add
+// the same two operands, so every lane ends with the same bits.
+template <typename T>
+__device__ __forceinline__ T row16_sum(T v) {
+  v = v + dpp<DPP_XOR1>(v);
+  v = v + dpp<DPP_XOR2>(v);
+  v = v + dpp<DPP_HALF_MIRROR>(v);
+  v = v + dpp<DPP_MIRROR>(v);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T dn_abs(T v) {
+  return v < T(0) ? -v : v;
+}
+
+// Pivot candidate order: larger |v| first, then the smaller key (position).
+template <typename T>
+__device__ __forceinline__ void piv_take(T& v, int& key, T ov, int okey) {
+  const T a = dn_abs(v), b = dn_abs(ov);
+  if (b > a || (b == a && okey < key)) {
+    v = ov;
+    key = okey;
+  }
+}
+
+template <int CTRL, typename T>
+__device__ __forceinline__ void piv_step(T& v, int& key) {
+  const T ov = dpp<CTRL>(v);
+  const int ok = dpp<CTRL>(key);
+  piv_take(v, key, ov, ok);
+}
+
+template <typename T>
+__device__ __forceinline__ void row16_argmax(T& v, int& key) {
+  piv_step<DPP_XOR1>(v, key);
+  piv_step<DPP_XOR2>(v, key);
+  piv_step<DPP_HALF_MIRROR>(v, key);
+  piv_step<DPP_MIRROR>(v, key);
+}
+
+__device__ __forceinline__ double dn_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float dn_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// ---------------------------------------------------------------------------
+// Preconditioner. A = rows per thread / 16 (s <= 16 A). Dynamic LDS:
+// precond_reg_lds_bytes<T>(A).
+// ---------------------------------------------------------------------------
+template <typename T>
+constexpr size_t precond_reg_lds(int A) {
+  return 2 * DN_NP * DN_LD * sizeof(double) + 2 * 16 * A * sizeof(T) + 2 * 16 * A * sizeof(int);
+}
+
+template <typename T, int A>
+__global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __restrict__ Y, int s, int n, int lu,
+                                                            const double* __restrict__ Nin, int ldn, double* R1pad,
+                                                            int np, double* R1out, int32_t* perm_out, double* Mout,
+                                                            int32_t* info, int32_t stage_qr) {
+  constexpr int SR = 16 * A;
+  extern __shared__ __align__(16) unsigned char dn_smem[];
+  double* R0l = (double*)dn_smem;         // R_0(i, j) at i*DN_LD + j
+  double* Nl = R0l + DN_NP * DN_LD;       // N(i, j) at i*DN_LD + j
+  T* vb = (T*)(Nl + DN_NP * DN_LD);       // [2][SR] step vectors, entry of row r at (r%16)*A + r/16
+  int* posl = (int*)(vb + 2 * SR);        // position of row r at (r%16)*A + r/16
+  int* rowl = posl + SR;                  // row at position p
+  __shared__ int bc_row[2];
+  __shared__ T bc_tau[2];
+  __shared__ int bc_fail, bc_min;
+  __shared__ double dsg[DN_NP];
+  if (info_failed(info)) return;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tr = lane & 15, col = 4 * wave + (lane >> 4);
+  T x[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) {
+    const int row = tr + 16 * a;
+    x[a] = (row < s && col < n) ? (T)Y[row + (int64_t)col * s] : T(0);
+  }
+  for (int e = tid; e < 2 * DN_NP * DN_LD; e += DN_THREADS) R0l[e] = 0.0;  // R0l and Nl
+  for (int r = tid; r < SR; r += DN_THREADS) {
+    posl[(r & 15) * A + (r >> 4)] = r;
+    rowl[r] = r;
+  }
+  if (tid == 0) {
+    bc_fail = 0;
+    bc_min = INT_MAX;
+  }
+  __syncthreads();
+
+  if (lu) {
+    for (int k = 0; k < n; ++k) {
+      const int buf = k & 1;
+      if (wave == (k >> 2)) {
+        // pivot search over the rows at positions >= k of column k
+        int pos[A];
+#pragma unroll
+        for (int a = 0; a < A; ++a) pos[a] = posl[tr * A + a];
+        T best = T(0);
+        int key = INT_MAX, bad = 0;
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+          const int row = tr + 16 * a;
+          if (row < s && pos[a] >= k) {
+            bad |= !is_finite((double)x[a]);
+            piv_take(best, key, x[a], (pos[a] << 12) | row);
+          }
+        }
+        row16_argmax(best, key);
+        const bool own = (col == k);
+        const bool anybad = __ballot(own && bad) != 0;
+        if (own) {
+          const int prow = key & 4095, ppos = key >> 12;
+          const int code = anybad ? INFO_NONFINITE : (dn_abs(best) > T(0) ? 0 : INFO_LU_ZERO_PIVOT);
+          if (code) {
+            if (tr == 0) {
+              info_set(info, code, STAGE_LU, k + 1);
+              bc_fail = 1;
+            }
+          } else {
+            // multipliers l_i = x_ik / pivot (true division) for the rows still to eliminate
+#pragma unroll
+            for (int a = 0; a < A; ++a) {
+              const int row = tr + 16 * a;
+              const bool live = row < s && pos[a] >= k && row != prow;
+              const T l = live ? x[a] / best : T(0);
+              if (live) x[a] = l;
+              vb[buf * SR + tr * A + a] = l;
+            }
+            if (tr == 0) {
+              // positions k and ppos trade rows
+              const int q = rowl[k];
+              rowl[k] = prow;
+              rowl[ppos] = q;
+              posl[(prow & 15) * A + (prow >> 4)] = k;
+              posl[(q & 15) * A + (q >> 4)] = ppos;
+              bc_row[buf] = prow;
+            }
+          }
+        }
+      }
+      __syncthreads();
+      if (bc_fail) return;
+      if (4 * wave + 3 > k) {
+        // rank-1 update of the columns j > k with the pivot row's entries
+        const int prow = __builtin_amdgcn_readfirstlane(bc_row[buf]);
+        const int ap = prow >> 4;
+        T u = x[0];
+#pragma unroll
+        for (int a = 1; a < A; ++a)
+          if (a == ap) u = x[a];
+        u = __shfl(u, (lane & 48) | (prow & 15));
+        // columns <= k are final: a zero factor leaves them unchanged
+        if (col <= k) u = T(0);
+#pragma unroll
+        for (int a = 0; a < A; ++a) x[a] = dn_fma(-vb[buf * SR + tr * A + a], u, x[a]);
+      }
+    }
+    __syncthreads();
+  }
+
+  int pos[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) pos[a] = posl[tr * A + a];
+  if (lu) {
+    // N = the rows at positions < n (upper part); M = unit lower trapezoid
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      if (pos[a] < n) {
+        if (col < n && col >= pos[a]) Nl[pos[a] * DN_LD + col] = (double)x[a];
+        x[a] = (col < pos[a]) ? x[a] : (col == pos[a] ? T(1) : T(0));
+      }
+    }
+    if (perm_out)
+      for (int p = tid; p < s; p += DN_THREADS) perm_out[p] = rowl[p];
+  } else {
+    // M = Y; N external (upper part) or the identity. Non-finite entries of M
+    // are reported before the reflections (lowest column).
+#pragma unroll
+    for (int a = 0; a < A; ++a)
+      if (tr + 16 * a < s && col < n && !is_finite((double)x[a])) atomicMin(&bc_min, col);
+    for (int e = tid; e < n * n; e += DN_THREADS) {
+      const int i = e % n, j = e / n;
+      Nl[i * DN_LD + j] = Nin ? ((i <= j) ? Nin[i + (int64_t)j * ldn] : 0.0) : (i == j ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    if (bc_min != INT_MAX) {
+      if (tid == 0) info_set(info, INFO_NONFINITE, stage_qr, bc_min + 1);
+      return;
+    }
+  }
+  if (Mout) {
+#pragma unroll
+    for (int a = 0; a < A; ++a)
+      if (tr + 16 * a < s && col < n) Mout[pos[a] + (int64_t)col * s] = (double)x[a];
+  }
+
+  // Householder reflections (LAPACK dlarfg convention) on the rows in position order
+  for (int k = 0; k < n; ++k) {
+    const int buf = k & 1;
+    if (wave == (k >> 2)) {
+      T sq = T(0), al = T(0);
+#pragma unroll
+      for (int a = 0; a < A; ++a) {
+        if (pos[a] > k && tr + 16 * a < s) sq = dn_fma(x[a], x[a], sq);
+        if (pos[a] == k) al = x[a];
+      }
+      sq = row16_sum(sq);
+      al = row16_sum(al);  // one non-zero term: exact
+      if (col == k) {
+        const T xnorm = sqrt(sq);
+        T tau = T(0), scal = T(0), beta = al;
+        if (xnorm != T(0)) {
+          beta = -copysign(hypot(al, xnorm), al);
+          tau = (beta - al) / beta;
+          scal = T(1) / (al - beta);
+        }
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+          const T v = (pos[a] > k && tr + 16 * a < s) ? x[a] * scal : (pos[a] == k ? T(1) : T(0));
+          if (tau != T(0)) {
+            if (pos[a] > k)
+              x[a] = v;
+            else if (pos[a] == k)
+              x[a] = beta;
+          }
+          vb[buf * SR + tr * A + a] = v;
+        }
+        if (tr == 0) bc_tau[buf] = tau;
+      }
+    }
+    __syncthreads();
+    if (4 * wave + 3 > k) {
+      const T tau = bc_tau[buf];
+      if (tau != T(0)) {
+        // w_j = v^T M(:, j); M(:, j) -= tau w_j v for the columns j > k
+        T v[A];
+        T p = T(0);
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+          v[a] = vb[buf * SR + tr * A + a];
+          p = dn_fma(v[a], x[a], p);
+        }
+        p = row16_sum(p);
+        const T t = (col > k) ? tau * p : T(0);
+#pragma unroll
+        for (int a = 0; a < A; ++a) x[a] = dn_fma(-t, v[a], x[a]);
+      }
+    }
+  }
+
+  // R_0: the rows at positions < n, columns >= position
+#pragma unroll
+  for (int a = 0; a < A; ++a)
+    if (pos[a] < n && col < n && col >= pos[a]) R0l[pos[a] * DN_LD + col] = (double)x[a];
+  __syncthreads();
+  // diag(R_0 N) = diag(R_0) diag(N) (both triangular); D and the first failing index
+  if (tid < n) {
+    const double d = R0l[tid * DN_LD + tid] * Nl[tid * DN_LD + tid];
+    dsg[tid] = d;
+    if (!is_finite(d) || d == 0.0) atomicMin(&bc_min, tid);
+  }
+  __syncthreads();
+  if (bc_min != INT_MAX) {
+    if (tid == 0) info_set(info, is_finite(dsg[bc_min]) ? INFO_SINGULAR : INFO_NONFINITE, STAGE_PRECOND, bc_min + 1);
+    return;
+  }
+  // R_1 = D R_0 N on MFMA: wave w computes output block (w/4, w%4)
+  const int I = wave >> 2, J = wave & 3, nb = np / 16;
+  if (I < nb && J < nb) {
+    const int lr = lane & 15, lq = lane >> 4;
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    if (I <= J) {
+      for (int K = I; K <= J; ++K)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const double av = R0l[(16 * I + lr) * DN_LD + 16 * K + 4 * kk + lq];
+          const double bv = Nl[(16 * K + 4 * kk + lq) * DN_LD + 16 * J + lr];
+          acc = mfma_f64(av, bv, acc);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * I + lq + 4 * r, j = 16 * J + lr;
+      double v;
+      if (i < n && j < n)
+        v = (i > j) ? 0.0 : (dsg[i] < 0.0 ? -acc[r] : acc[r]);
+      else
+        v = (i == j) ? 1.0 : 0.0;
+      R1pad[i * np + j] = v;
+      if (R1out && i < n && j < n) R1out[i + (int64_t)j * n] = v;
+    }
+  }
+  if (tid < np) R1pad[np * np + tid] = (tid < n) ? 1.0 / fabs(dsg[tid]) : 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky, right-looking on the full symmetric matrix: thread (column j,
+// rows l%16 + 16a, a < 4). Step k: the owner of column k forms row k of R
+// (its column, by symmetry) into LDS; every column j > k subtracts
+// R(k, :)^T R(k, j).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(DN_THREADS) void k_chol_reg(const double* __restrict__ G, int ldg, int n, int64_t m,
+                                                         int shift_mode, double* Rpad, int np, double* Rout,
+                                                         int rout_user, const double* __restrict__ Rprev,
+                                                         const double* __restrict__ Npost, int ldnp, int32_t* info,
+                                                         int32_t stage) {
+  __shared__ double Rl[DN_NP * DN_LD];  // R(i, j) at i*DN_LD + j
+  __shared__ double dg[DN_NP];
+  __shared__ int bc_fail, bc_min;
+  if (info_failed(info)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tr = lane & 15, col = 4 * wave + (lane >> 4);
+  double x[4];
+  // the upper triangle of G is read; the lower one is its mirror
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int row = tr + 16 * a;
+    x[a] = (row < n && col < n) ? (row <= col ? G[row + (int64_t)col * ldg] : G[col + (int64_t)row * ldg]) : 0.0;
+  }
+  for (int e = tid; e < DN_NP * DN_LD; e += DN_THREADS) Rl[e] = 0.0;
+  if (tid == 0) {
+    bc_fail = 0;
+    bc_min = INT_MAX;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int row = tr + 16 * a;
+    if (row <= col && col < n && !is_finite(x[a])) atomicMin(&bc_min, col);
+    if (row == col && col < n) dg[col] = x[a];
+  }
+  __syncthreads();
+  if (bc_min != INT_MAX) {
+    if (tid == 0) info_set(info, INFO_NONFINITE, stage, bc_min + 1);
+    return;
+  }
+  if (shift_mode == 1) {
+    // Algorithm 4's shift: 11 (m n u + n (n+1) u) max_j G_jj
+    double gm = 0.0;
+    for (int j = 0; j < n; ++j) gm = fmax(gm, dg[j]);
+    const double u = 0x1p-53;
+    const double sigma = 11.0 * ((double)m * (double)n * u + (double)n * (double)(n + 1) * u) * gm;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      if (tr + 16 * a == col && col < n) x[a] += sigma;
+  }
+  for (int k = 0; k < n; ++k) {
+    if (wave == (k >> 2)) {
+      double xs = x[0];
+#pragma unroll
+      for (int a = 1; a < 4; ++a)
+        if (a == (k >> 4)) xs = x[a];
+      const double d = __shfl(xs, (lane & 48) | (k & 15));
+      if (col == k) {
+        if (!(d > 0.0)) {
+          if (tr == 0) {
+            info_set(info, INFO_CHOL_BREAKDOWN, stage, k + 1);
+            bc_fail = 1;
+          }
+        } else {
+          const double rkk = sqrt(d);
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            const int row = tr + 16 * a;
+            Rl[k * DN_LD + row] = (row > k) ? x[a] / rkk : (row == k ? rkk : 0.0);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (bc_fail) return;
+    if (4 * wave + 3 > k) {
+      const double rkj = (col > k) ? Rl[k * DN_LD + col] : 0.0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) x[a] = __builtin_fma(-Rl[k * DN_LD + tr + 16 * a], rkj, x[a]);
+    }
+  }
+
+  const int I = wave >> 2, J = wave & 3, nb = np / 16;
+  const int lr = lane & 15, lq = lane >> 4;
+  if (Npost) {
+    // Rpad = D R N (N upper, user layout): diag(R N) = diag(R) diag(N)
+    if (tid < n) {
+      const double d = Rl[tid * DN_LD + tid] * Npost[tid + (int64_t)tid * ldnp];
+      dg[tid] = d;
+      if (!is_finite(d) || d == 0.0) atomicMin(&bc_min, tid);
+    }
+    __syncthreads();
+    if (bc_min != INT_MAX) {
+      if (tid == 0) info_set(info, is_finite(dg[bc_min]) ? INFO_SINGULAR : INFO_NONFINITE, STAGE_PRECOND, bc_min + 1);
+      return;
+    }
+    if (I < nb && J < nb) {
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+      if (I <= J) {
+        for (int K = I; K <= J; ++K)
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const int kr = 16 * K + 4 * kk + lq, j = 16 * J + lr;
+            const double av = Rl[(16 * I + lr) * DN_LD + 16 * K + 4 * kk + lq];
+            const double bv = (kr <= j && j < n) ? Npost[kr + (int64_t)j * ldnp] : 0.0;
+            acc = mfma_f64(av, bv, acc);
+          }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * I + lq + 4 * r, j = 16 * J + lr;
+        double v;
+        if (i < n && j < n)
+          v = (i > j) ? 0.0 : (dg[i] < 0.0 ? -acc[r] : acc[r]);
+        else
+          v = (i == j) ? 1.0 : 0.0;
+        Rpad[i * np + j] = v;
+      }
+    }
+    if (tid < np) Rpad[np * np + tid] = (tid < n) ? 1.0 / fabs(dg[tid]) : 1.0;
+    return;
+  }
+
+  for (int e = tid; e < np * np; e += DN_THREADS) {
+    const int i = e / np, j = e % np;
+    Rpad[e] = (i < n && j < n) ? Rl[i * DN_LD + j] : (i == j ? 1.0 : 0.0);
+  }
+  if (tid < np) Rpad[np * np + tid] = (tid < n) ? 1.0 / Rl[tid * DN_LD + tid] : 1.0;
+  if (Rout && I < nb && J < nb) {
+    // Rout = R Rprev, Rprev a padded triangle (row-major, identity padding)
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    if (I <= J) {
+      for (int K = I; K <= J; ++K)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const double av = Rl[(16 * I + lr) * DN_LD + 16 * K + 4 * kk + lq];
+          const double bv = Rprev[(int64_t)(16 * K + 4 * kk + lq) * np + 16 * J + lr];
+          acc = mfma_f64(av, bv, acc);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * I + lq + 4 * r, j = 16 * J + lr;
+      if (rout_user) {
+        if (i < n && j < n) Rout[i + (int64_t)j * n] = (i > j) ? 0.0 : acc[r];
+      } else {
+        Rout[i * np + j] = (i < n && j < n) ? ((i > j) ? 0.0 : acc[r]) : (i == j ? 1.0 : 0.0);
+        if (i == j) Rout[np * np + i] = (i < n) ? 1.0 / acc[r] : 1.0;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+bool precond_reg_fits(int64_t s, int64_t n) { return n >= 1 && n <= DN_NP && s >= n && s <= 256; }
+
+template <typename T, int A>
+static hipError_t launch_pr(const double* Y, int64_t s, int64_t n, int lu, const double* Nin, int64_t ldn,
+                            double* R1pad, double* R1out, int32_t* perm, double* Mout, int32_t* info, int32_t stage_qr,
+                            hipStream_t st) {
+  const size_t lds = precond_reg_lds<T>(A);
+  static_assert(precond_reg_lds<double>(16) <= 96 * 1024, "LDS budget");
+  hipError_t e = hipFuncSetAttribute((const void*)k_precond_reg<T, A>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return e;
+  }
+  hipLaunchKernelGGL((k_precond_reg<T, A>), dim3(1), dim3(DN_THREADS), lds, st, Y, (int)s, (int)n, lu, Nin, (int)ldn,
+                     R1pad, pad_cols(n), R1out, perm, Mout, info, stage_qr);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_pr_t(const double* Y, int64_t s, int64_t n, int lu, const double* Nin, int64_t ldn,
+                              double* R1pad, double* R1out, int32_t* perm, double* Mout, int32_t* info,
+                              int32_t stage_qr, hipStream_t st) {
+  if (s <= 16) return launch_pr<T, 1>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, info, stage_qr, st);
+  if (s <= 32) return launch_pr<T, 2>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, info, stage_qr, st);
+  if (s <= 64) return launch_pr<T, 4>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, info, stage_qr, st);
+  if (s <= 128) return launch_pr<T, 8>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, info, stage_qr, st);
+  return launch_pr<T, 16>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, info, stage_qr, st);
+}
+
+hipError_t launch_precond_reg(const double* Y, int64_t s, int64_t n, int lu, int prec, const double* Nin, int64_t ldn,
+                              double* R1pad, double* R1out, int32_t* perm, double* Mout, int32_t* info,
+                              int32_t stage_qr, hipStream_t st) {
+  if (!precond_reg_fits(s, n)) return hipErrorInvalidValue;
+  if (prec == 1) return launch_pr_t<float>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, info, stage_qr, st);
+  return launch_pr_t<double>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, info, stage_qr, st);
+}
+
+hipError_t launch_chol_reg(const double* G, int ldg, int64_t n, int64_t m, int shift_mode, double* Rpad, double* Rout,
+                           int rout_user, const double* Rprev, const double* Npost, int64_t ldnp, int32_t* info,
+                           int32_t stage, hipStream_t st) {
+  if (n < 1 || n > DN_NP || (Npost && Rout)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_chol_reg, dim3(1), dim3(DN_THREADS), 0, st, G, ldg, (int)n, m, shift_mode, Rpad, pad_cols(n),
+                     Rout, rout_user, Rprev, Npost, (int)ldnp, info, stage);
+  return hipGetLastError();
+}
+
+}  // namespace rclupp

@@ -129,16 +129,18 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch_f64(const double* __restr
   }
 }
 
-__global__ void k_sketch_reduce(const double* __restrict__ Ypart, int gx, int64_t s, int64_t n, int64_t s_pad,
-                                int64_t n_pad, double scale, double* __restrict__ Y, const int32_t* info) {
+// Y[i + j*s] = scale * sum_y lvl[y][i + j*s_pad] (the level-1 sums of the
+// per-workgroup partials, added in split order).
+__global__ void k_sketch_final(const double* __restrict__ lvl, int splits, int64_t s, int64_t n, int64_t s_pad,
+                               int64_t n_pad, double scale, double* __restrict__ Y, const int32_t* info) {
   if (info_failed(info)) return;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= s * n) return;
   const int64_t i = e % s, j = e / s;
-  const double* p = Ypart + i + j * s_pad;
+  const double* p = lvl + i + j * s_pad;
   const int64_t stride = s_pad * n_pad;
   double acc = 0.0;
-  for (int b = 0; b < gx; ++b) acc += p[(int64_t)b * stride];
+  for (int y = 0; y < splits; ++y) acc += p[(int64_t)y * stride];
   Y[i + j * s] = acc * scale;
 }
 
@@ -193,7 +195,8 @@ SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int gx_hint) {
   if (gx < 1) gx = 1;
   if (gx > p.ntiles) gx = (int)p.ntiles;
   p.gx = gx;
-  p.part_bytes = (size_t)p.gx * (size_t)p.s_pad * (size_t)p.n_pad * sizeof(double);
+  // per-workgroup partials followed by the level-1 sums of the reduction
+  p.part_bytes = ((size_t)p.gx + reduce_splits(p.gx)) * (size_t)p.s_pad * (size_t)p.n_pad * sizeof(double);
   return p;
 }
 
@@ -227,10 +230,15 @@ hipError_t launch_sketch_partials(const SketchPlan& p, const double* X, int64_t 
 
 hipError_t launch_sketch_reduce(const SketchPlan& p, const double* Ypart, int64_t s, int64_t n, double scale, double* Y,
                                 const int32_t* info, hipStream_t st) {
+  const int64_t stride = p.s_pad * p.n_pad;
+  const int splits = reduce_splits(p.gx);
+  double* lvl = const_cast<double*>(Ypart) + (int64_t)p.gx * stride;
+  hipError_t e = launch_partial_sum(Ypart, p.gx, stride, splits, lvl, info, st);
+  if (e != hipSuccess) return e;
   const int64_t total = s * n;
   const int threads = 256;
   const int64_t blocks = (total + threads - 1) / threads;
-  hipLaunchKernelGGL(k_sketch_reduce, dim3((unsigned)blocks), dim3(threads), 0, st, Ypart, p.gx, s, n, p.s_pad,
+  hipLaunchKernelGGL(k_sketch_final, dim3((unsigned)blocks), dim3(threads), 0, st, lvl, splits, s, n, p.s_pad,
                      p.n_pad, scale, Y, info);
   return hipGetLastError();
 }

@@ -449,6 +449,9 @@ __global__ void k_pad(const double* __restrict__ R, int n, int np, double* __res
 }
 
 // ---------------------------------------------------------------------------
+// Launchers. n <= 64 (and s <= 256 for the preconditioner) go to the
+// register-resident kernels of k_dense.hip.
+// ---------------------------------------------------------------------------
 size_t precond_scratch_bytes(int64_t s, int64_t n) {
   // A (s*n) + wv (n) + N (n*n) + R (n*n) in doubles, + perm (s ints), aligned
   size_t b = ((size_t)s * n + n + 2 * (size_t)n * n) * sizeof(double);
@@ -471,9 +474,12 @@ static hipError_t launch_pc(const double* Y, int64_t s, int64_t n, int lu, const
   const size_t lds = ((size_t)s * n + n) * sizeof(T);
   const int use_lds = lds <= SD_LDS_LIMIT;
   if (use_lds && lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_precond<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)SD_LDS_LIMIT);
-    if (e != hipSuccess) return e;
+    hipError_t e =
+        hipFuncSetAttribute((const void*)k_precond<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return e;
+    }
   }
   hipLaunchKernelGGL((k_precond<T>), dim3(1), dim3(SD_THREADS), use_lds ? lds : 0, st, Y, (int)s, (int)n, lu, Nin,
                      (int)ldn, R1pad, np, R1out, perm, Mout, gA, gN, gR, gperm, use_lds, info, stage_qr);
@@ -484,6 +490,8 @@ hipError_t launch_precond(const double* Y, int64_t s, int64_t n, int lu, int pre
                           double* R1pad, double* R1out, int32_t* perm, double* Mout, double* scratch, int32_t* info,
                           int32_t stage_qr, hipStream_t st) {
   if (s < n || n < 1 || n > 256) return hipErrorInvalidValue;
+  if (precond_reg_fits(s, n))
+    return launch_precond_reg(Y, s, n, lu, prec, Nin, ldn, R1pad, R1out, perm, Mout, info, stage_qr, st);
   if (prec == 1) return launch_pc<float>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, scratch, info, stage_qr, st);
   return launch_pc<double>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, scratch, info, stage_qr, st);
 }
@@ -495,14 +503,18 @@ hipError_t launch_chol(const double* G, int ldg, int64_t n, int64_t m, int shift
                        int32_t* info, int32_t stage, hipStream_t st) {
   if (n < 1 || n > 256) return hipErrorInvalidValue;
   const int np = pad_cols(n);
+  if (n <= 64 && !(Npost && Rout))
+    return launch_chol_reg(G, ldg, n, m, shift_mode, Rpad, Rout, rout_user, Rprev, Npost, ldnp, info, stage, st);
   const size_t lds = (size_t)n * n * sizeof(double);
   const int use_lds = lds <= SD_LDS_LIMIT;
   double* gA = scratch;
   double* gT = scratch + (size_t)n * n;
   if (use_lds && lds > 64 * 1024) {
-    hipError_t e =
-        hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)SD_LDS_LIMIT);
-    if (e != hipSuccess) return e;
+    hipError_t e = hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return e;
+    }
   }
   hipLaunchKernelGGL(k_chol, dim3(1), dim3(SD_THREADS), use_lds ? lds : 0, st, G, ldg, (int)n, m, shift_mode, Rpad, np,
                      Rout, rout_user, Rprev, Npost, (int)ldnp, gA, gT, use_lds, info, stage);

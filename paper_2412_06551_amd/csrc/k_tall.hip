@@ -32,106 +32,207 @@ int pad_cols(int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
-// n <= 64: fused substitution + Gram.
+// n <= 64: blocked substitution on the matrix cores, fused Gram.
+//
+// The solve is written transposed, W^T = R^{-T} X^T, in 16-column blocks b:
+//   C_b^T = X_b^T - sum_{c<b} R_{c,b}^T W_c^T            (v_mfma_f64_16x16x4_f64)
+//   W_b^T = R_{b,b}^{-T} C_b^T by substitution over its 16 columns.
+// MFMA roles: M = the 16 columns of block b, N = 16 rows of X, K = 4 columns of
+// an earlier block c. The output layout (lane l, register r holds row l%16,
+// column 16b + l/16 + 4r) is exactly the B-operand layout the later blocks
+// need (B fragment kk of block c = output register kk), so solved blocks stay
+// in registers. The off-diagonal A fragments (-R_{c,b}^T) are loaded into
+// registers once per workgroup. In the substitution each column is owned by
+// one 16-lane group (column = group + 4 r); its solved value is broadcast to
+// the other three groups of the same row (ds_bpermute) and the trailing
+// columns are updated with R entries read from an LDS table (entries at or
+// left of the pivot column are stored as zero, so no masking is needed).
+// Each wave handles two 16-row blocks (32 rows); the four waves of a
+// workgroup cover a 128-row tile. X and W move in 128-byte row segments.
+// The Gram partial sums stage the solved rows in a per-wave LDS region
+// (column-major, stride 33) and use v_mfma_f64_16x16x4_f64 on the upper
+// 16x16 blocks.
 // ---------------------------------------------------------------------------
+constexpr int TM_ROWS_WAVE = 32;
+constexpr int TM_TILE = 4 * TM_ROWS_WAVE;  // rows per workgroup tile
+constexpr int TM_LDG = 17;                 // Gram staging: 16 rows + pad per column
+
 template <int NP, bool TRSM, bool GRAM, bool WRITE>
-__global__ __launch_bounds__(TP_THREADS) void k_tall_pass(const double* X, int64_t ldx, int64_t m, int n,
-                                                          const double* __restrict__ Rp, double* W, int64_t ldw,
-                                                          double* __restrict__ Gpart, int64_t ntiles,
-                                                          const int32_t* info) {
+__global__ __launch_bounds__(TP_THREADS, 2) void k_tall_mfma(const double* X, int64_t ldx, int64_t m, int n,
+                                                            const double* __restrict__ Rp, double* W, int64_t ldw,
+                                                            double* __restrict__ Gpart, int64_t ntiles,
+                                                            const int32_t* info) {
   if (info_failed(info)) return;
-  constexpr int NBK = NP / 16;
-  constexpr int NBLK = NBK * (NBK + 1) / 2;
-  __shared__ double lds[GRAM ? 4 * NP * TP_LDW : 1];
+  constexpr int NB = NP / 16;                  // column blocks
+  constexpr int NOFF = NB * (NB - 1) / 2;      // off-diagonal block pairs c < b
+  constexpr int NBLK = NB * (NB + 1) / 2;      // upper Gram blocks
+  constexpr int DTAB = TRSM ? NB * 16 * 16 : 1;  // diagonal tables: [b][jj][q][r]
+  constexpr int GST = GRAM ? ((4 * NP * TM_LDG > NBLK * 256) ? 4 * NP * TM_LDG : NBLK * 256) : 1;
+  constexpr int OTAB = (TRSM && NOFF > 0) ? NOFF * 4 * 64 : 1;  // [pair][kk][lane]
+  __shared__ double dtab[DTAB];
+  __shared__ double otab[OTAB];
+  __shared__ double gst[GST];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+
+  if (TRSM) {
+    // off-diagonal A fragments: otab[(pair*4 + kk)*64 + lane] = -R[16c + 4kk + l/16][16b + l%16]
+    for (int e = tid; e < OTAB && NOFF > 0; e += TP_THREADS) {
+      const int l = e & 63, kk = (e >> 6) & 3, pr = e >> 8;
+      int b = 1, c = pr;
+      while (c >= b) {
+        c -= b;
+        ++b;
+      }
+      otab[e] = -Rp[(16 * c + 4 * kk + (l >> 4)) * NP + 16 * b + (l & 15)];
+    }
+    // diagonal tables: dtab[((b*16 + jj)*4 + q)*4 + r] = R[16b+jj][16b+q+4r] if q+4r > jj else 0
+    for (int e = tid; e < DTAB; e += TP_THREADS) {
+      const int r = e & 3, q = (e >> 2) & 3, jj = (e >> 4) & 15, b = e >> 8;
+      const int col = q + 4 * r;
+      dtab[e] = (col > jj) ? Rp[(16 * b + jj) * NP + 16 * b + col] : 0.0;
+    }
+  }
+  __syncthreads();
 
   f64x4 gacc[GRAM ? NBLK : 1];
 #pragma unroll
-  for (int b = 0; b < (GRAM ? NBLK : 1); ++b) gacc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
-  double* ws = lds + wave * NP * TP_LDW;
+  for (int g = 0; g < (GRAM ? NBLK : 1); ++g) gacc[g] = f64x4{0.0, 0.0, 0.0, 0.0};
+  double* ws = gst + wave * NP * TM_LDG;
 
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int64_t row = t * TP_THREADS + tid;
-    const bool live = row < m;
-    double w[NP];
-    {
-      const double* xp = X + row;
-      const int64_t step = opaque_i64(ldx);
+    const int64_t row0 = t * TM_TILE + wave * TM_ROWS_WAVE;
+    f64x4 acc[2][NB];
+    // addresses: a wave-uniform column base (scalar) plus a 32-bit per-lane offset
+    // (row + (l/16) ld); requires 4 ld + m < 2^29 rows, checked by the launcher
 #pragma unroll
-      for (int c = 0; c < NP; ++c) {
-        w[c] = (live && c < n) ? *xp : 0.0;
-        xp += opaque_i64(step);
-      }
+    for (int h = 0; h < 2; ++h) {
+      const int64_t row = row0 + 16 * h + lr;
+      const bool live = row < m;
+      const uint32_t voff = (uint32_t)(row + (int64_t)lq * ldx);
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int col = 16 * b + lq + 4 * r;
+          const double* cb = X + (int64_t)(16 * b + 4 * r) * ldx;
+          acc[h][b][r] = (live && col < n) ? cb[voff] : 0.0;
+        }
     }
-    __builtin_amdgcn_sched_barrier(0);
     if (TRSM) {
-      const cdptr R = opaque_uniform(Rp);  // row-major padded triangle
+      // opaque per tile: keeps the table reads inside the tile loop (hoisting
+      // all of them would need hundreds of registers)
+      int dofs = 0;
+      asm volatile("" : "+s"(dofs));
+      const cdptr Rt = opaque_uniform(Rp);
 #pragma unroll
-      for (int j = 0; j < NP; ++j) {
-        w[j] *= R[NP * NP + j];
+      for (int b = 0; b < NB; ++b) {
+        // C_b^T -= R_{c,b}^T W_c^T for the solved blocks c < b
+        int p = b * (b - 1) / 2;
 #pragma unroll
-        for (int k = j + 1; k < NP; ++k) w[k] = __builtin_fma(-w[j], R[j * NP + k], w[k]);
+        for (int c = 0; c < b; ++c) {
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const double a = otab[dofs + (p * 4 + kk) * 64 + lane];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) acc[h][b] = mfma_f64(a, acc[h][c][kk], acc[h][b]);
+          }
+          ++p;
+        }
+        // substitution within the diagonal block
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+          const int qo = jj & 3, ro = jj >> 2;
+          // true division by the diagonal (not a reciprocal multiply): the same
+          // rounding as the row-wise substitution w_j = (x_j - sum) / R_jj
+          const double dv = Rt[(16 * b + jj) * NP + 16 * b + jj];
+          const double* tb = dtab + dofs + ((b * 16 + jj) * 4 + lq) * 4;
+          const double t0 = tb[0], t1 = tb[1], t2 = tb[2], t3 = tb[3];
+          const int src = lr + 16 * qo;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const double wv = __shfl(acc[h][b][ro] / dv, src);
+            const bool own = (lq == qo);
+            acc[h][b][0] = (own && ro == 0) ? wv : __builtin_fma(-wv, t0, acc[h][b][0]);
+            acc[h][b][1] = (own && ro == 1) ? wv : __builtin_fma(-wv, t1, acc[h][b][1]);
+            acc[h][b][2] = (own && ro == 2) ? wv : __builtin_fma(-wv, t2, acc[h][b][2]);
+            acc[h][b][3] = (own && ro == 3) ? wv : __builtin_fma(-wv, t3, acc[h][b][3]);
+          }
+        }
       }
     }
-    __builtin_amdgcn_sched_barrier(0);
-    if (WRITE && live) {
-      double* wp = W + row;
-      const int64_t step = opaque_i64(ldw);
+    if (WRITE) {
 #pragma unroll
-      for (int c = 0; c < NP; ++c) {
-        if (c < n) *wp = w[c];
-        wp += opaque_i64(step);
+      for (int h = 0; h < 2; ++h) {
+        const int64_t row = row0 + 16 * h + lr;
+        const uint32_t voff = (uint32_t)(row + (int64_t)lq * ldw);
+        if (row < m) {
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int col = 16 * b + lq + 4 * r;
+              double* cb = W + (int64_t)(16 * b + 4 * r) * ldw;
+              if (col < n) cb[voff] = acc[h][b][r];
+            }
+        }
       }
     }
     if (GRAM) {
+      // stage 16 rows at a time column-major (stride TP_LDW), then Gram fragments
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        if ((lane >> 5) == h) {
 #pragma unroll
-          for (int c = 0; c < NP; ++c) ws[c * TP_LDW + (lane & 31)] = w[c];
-        }
-        __syncthreads();
+        for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int kk = 0; kk < TP_HALF / 4; ++kk) {
-          double f[NBK];
+          for (int r = 0; r < 4; ++r) ws[(16 * b + lq + 4 * r) * TM_LDG + lr] = acc[h][b][r];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-          for (int ib = 0; ib < NBK; ++ib) f[ib] = ws[(16 * ib + (lane & 15)) * TP_LDW + 4 * kk + (lane >> 4)];
-          int b = 0;
+        for (int kk = 0; kk < 4; ++kk) {
+          double f[NB];
 #pragma unroll
-          for (int jb = 0; jb < NBK; ++jb)
+          for (int ib = 0; ib < NB; ++ib) f[ib] = ws[(16 * ib + lr) * TM_LDG + 4 * kk + lq];
+          int g = 0;
+#pragma unroll
+          for (int jb = 0; jb < NB; ++jb)
 #pragma unroll
             for (int ib = 0; ib <= jb; ++ib) {
-              gacc[b] = mfma_f64(f[ib], f[jb], gacc[b]);
-              ++b;
+              gacc[g] = mfma_f64(f[ib], f[jb], gacc[g]);
+              ++g;
             }
         }
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     }
   }
 
   if (GRAM) {
     // sum the four waves in order, then write the workgroup partial (upper blocks)
-    double* red = lds;  // NBLK * 4 * 64 doubles <= 4 * NP * TP_LDW
+    __syncthreads();
+    double* red = gst;  // NBLK * 4 * 64 doubles <= GST
     for (int w = 0; w < 4; ++w) {
       if (wave == w) {
-        int b = 0;
+        int g = 0;
 #pragma unroll
-        for (int jb = 0; jb < NBK; ++jb)
+        for (int jb = 0; jb < NB; ++jb)
 #pragma unroll
           for (int ib = 0; ib <= jb; ++ib) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              const int idx = (b * 4 + r) * 64 + lane;
-              const double v = (w == 0) ? gacc[b][r] : red[idx] + gacc[b][r];
+              const int idx = (g * 4 + r) * 64 + lane;
+              const double v = (w == 0) ? gacc[g][r] : red[idx] + gacc[g][r];
               if (w < 3) {
                 red[idx] = v;
               } else {
-                const int gi = 16 * ib + (lane >> 4) + 4 * r, gj = 16 * jb + (lane & 15);
+                const int gi = 16 * ib + lq + 4 * r, gj = 16 * jb + lr;
                 Gpart[(int64_t)blockIdx.x * NP * NP + gi + gj * NP] = v;
               }
             }
-            ++b;
+            ++g;
           }
       }
       __syncthreads();
@@ -166,7 +267,7 @@ __global__ __launch_bounds__(TP_THREADS) void k_tall_trsm_big(const double* X, i
 #pragma unroll
       for (int j = 0; j < 64; ++j) {
         const cdptr Rj = opaque_after(Rp + (int64_t)(c0 + j) * NP + c0, acc[j >= 2 ? j - 2 : 0]);
-        acc[j] *= Rj[NP * NP - (c0 + j) * NP - c0 + c0 + j];
+        acc[j] = acc[j] / Rj[j];
 #pragma unroll
         for (int k = j + 1; k < 64; ++k) acc[k] = __builtin_fma(-acc[j], Rj[k], acc[k]);
       }
@@ -242,10 +343,26 @@ __global__ __launch_bounds__(TP_THREADS) void k_gram_big(const double* __restric
   }
 }
 
-// G[i + j*np] = sum_b Gpart[b][i + j*np] for i <= j (mirrored), padded with the
+// Level 1 of the deterministic partial-sum reduction: lvl[y][e] = sum of
+// part[b][e] over the contiguous chunk of workgroups b assigned to split y
+// (in b order). Consecutive threads read consecutive e (coalesced).
+__global__ void k_partial_sum(const double* __restrict__ part, int nparts, int64_t stride, int splits,
+                              double* __restrict__ lvl, const int32_t* info) {
+  if (info_failed(info)) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= stride) return;
+  const int y = blockIdx.y;
+  const int per = (nparts + splits - 1) / splits;
+  const int b0 = y * per, b1 = (b0 + per < nparts) ? b0 + per : nparts;
+  double acc = 0.0;
+  for (int b = b0; b < b1; ++b) acc += part[(int64_t)b * stride + e];
+  lvl[(int64_t)y * stride + e] = acc;
+}
+
+// G[i + j*np] = sum_y lvl[y][i + j*np] for i <= j (mirrored), padded with the
 // identity beyond n (so a padded Cholesky stays the identity there).
-__global__ void k_gram_reduce(const double* __restrict__ Gpart, int gx, int np, int64_t n, double* __restrict__ G,
-                              const int32_t* info) {
+__global__ void k_gram_final(const double* __restrict__ lvl, int splits, int np, int64_t n, double* __restrict__ G,
+                             const int32_t* info) {
   if (info_failed(info)) return;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)np * np) return;
@@ -257,23 +374,39 @@ __global__ void k_gram_reduce(const double* __restrict__ Gpart, int gx, int np, 
   } else {
     const int64_t stride = (int64_t)np * np;
     v = 0.0;
-    for (int b = 0; b < gx; ++b) v += Gpart[(int64_t)b * stride + e];
+    for (int y = 0; y < splits; ++y) v += lvl[(int64_t)y * stride + e];
   }
   G[i + (int64_t)j * np] = v;
   G[j + (int64_t)i * np] = v;
+}
+
+int reduce_splits(int nparts) {
+  int sp = nparts / 16;
+  if (sp < 1) sp = 1;
+  if (sp > 64) sp = 64;
+  return sp;
+}
+
+hipError_t launch_partial_sum(const double* part, int nparts, int64_t stride, int splits, double* lvl,
+                              const int32_t* info, hipStream_t st) {
+  const int threads = 256;
+  dim3 grid((unsigned)((stride + threads - 1) / threads), (unsigned)splits);
+  hipLaunchKernelGGL(k_partial_sum, grid, dim3(threads), 0, st, part, nparts, stride, splits, lvl, info);
+  return hipGetLastError();
 }
 
 TallPlan plan_tall(int64_t m, int64_t n, int gx_hint) {
   TallPlan p{};
   p.np = pad_cols(n);
   p.fused_gram = p.np <= 64;
-  p.tile_rows = TP_THREADS;
-  p.ntiles = (m + TP_THREADS - 1) / TP_THREADS;
+  p.tile_rows = p.fused_gram ? TM_TILE : TP_THREADS;
+  p.ntiles = (m + p.tile_rows - 1) / p.tile_rows;
   int gx = gx_hint > 0 ? gx_hint : 512;
   if (gx > p.ntiles) gx = (int)p.ntiles;
   if (gx < 1) gx = 1;
   p.gx = gx;
-  p.part_bytes = (size_t)gx * p.np * p.np * sizeof(double);
+  // per-workgroup partials followed by the level-1 sums of the reduction
+  p.part_bytes = ((size_t)gx + reduce_splits(gx)) * p.np * p.np * sizeof(double);
   return p;
 }
 
@@ -285,11 +418,12 @@ static hipError_t launch_tp(const TallPlan& p, const double* X, int64_t ldx, int
   if (NP <= 64) {
 #define TP_CASE(T, G, Wr)                                                                                          \
   if (trsm == T && gram == G && write == Wr) {                                                                     \
-    hipLaunchKernelGGL((k_tall_pass<(NP <= 64 ? NP : 64), T, G, Wr>), grid, block, 0, st, X, ldx, m, (int)n, Rp, W, \
+    hipLaunchKernelGGL((k_tall_mfma<(NP <= 64 ? NP : 64), T, G, Wr>), grid, block, 0, st, X, ldx, m, (int)n, Rp, W, \
                        ldw, Gpart, p.ntiles, info);                                                                 \
     return hipGetLastError();                                                                                       \
   }
     TP_CASE(true, true, true)
+    TP_CASE(true, false, true)
     TP_CASE(false, true, false)
 #undef TP_CASE
     return hipErrorInvalidValue;
@@ -330,10 +464,16 @@ hipError_t launch_tall_pass(const TallPlan& p, const double* X, int64_t ldx, int
 
 hipError_t launch_gram_reduce(const TallPlan& p, const double* Gpart, int64_t n, double* G, const int32_t* info,
                               hipStream_t st) {
-  const int64_t total = (int64_t)p.np * p.np;
+  // level 1 writes into the tail of the partial buffer's own space is not
+  // possible (it is still being read), so the plan reserves lvl after it
+  const int64_t stride = (int64_t)p.np * p.np;
+  const int splits = reduce_splits(p.gx);
+  double* lvl = const_cast<double*>(Gpart) + (int64_t)p.gx * stride;
+  hipError_t e = launch_partial_sum(Gpart, p.gx, stride, splits, lvl, info, st);
+  if (e != hipSuccess) return e;
   const int threads = 256;
-  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0, st, Gpart,
-                     p.gx, p.np, n, G, info);
+  hipLaunchKernelGGL(k_gram_final, dim3((unsigned)((stride + threads - 1) / threads)), dim3(threads), 0, st, lvl,
+                     splits, p.np, n, G, info);
   return hipGetLastError();
 }
 

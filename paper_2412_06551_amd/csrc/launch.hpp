@@ -1,5 +1,5 @@
 // Host-side launchers of the gfx950 kernels (internal interface between the
-// C ABI in capi.cpp and the kernel translation units). Every launcher checks
+// C ABI in capi.hip and the kernel translation units). Every launcher checks
 // its own shape assumptions and returns hipSuccess or the launch error.
 #pragma once
 
@@ -13,6 +13,12 @@ namespace rclupp {
 int pad_cols(int64_t n);
 // Padded sketch rows used by the sketch kernels (multiple of 64).
 int64_t pad_sketch_rows(int64_t s);
+
+// Deterministic two-level reduction of per-workgroup partial sums (k_tall.hip):
+// lvl[y][e] = sum over the workgroups of split y (in order) of part[b][e].
+int reduce_splits(int nparts);
+hipError_t launch_partial_sum(const double* part, int nparts, int64_t stride, int splits, double* lvl,
+                              const int32_t* info, hipStream_t st);
 
 // ---- sketch (k_sketch.hip) --------------------------------------------------
 struct SketchPlan {
@@ -36,8 +42,9 @@ hipError_t launch_omega(uint64_t seed, int64_t s, int64_t j0, int64_t cols, floa
 hipError_t launch_philox(const uint32_t* ctr, int64_t count, uint32_t k0, uint32_t k1, uint32_t* out, hipStream_t st);
 
 // ---- tall passes (k_tall.hip) -------------------------------------------------
-// R operands of the tall kernels are "padded triangles": NP x NP column-major
-// with identity padding beyond n, followed by NP reciprocals of the diagonal.
+// R operands of the tall kernels are "padded triangles": NP x NP row-major
+// (element (i, j) at i*NP + j) with identity padding beyond n, followed by NP
+// reciprocals of the diagonal.
 inline size_t padded_r_doubles(int np) { return (size_t)np * np + np; }
 
 struct TallPlan {
@@ -73,6 +80,15 @@ size_t chol_scratch_bytes(int64_t n);
 hipError_t launch_chol(const double* G, int ldg, int64_t n, int64_t m, int shift_mode, double* Rpad, double* Rout,
                        int rout_user, const double* Rprev, const double* Npost, int64_t ldnp, double* scratch,
                        int32_t* info, int32_t stage, hipStream_t st);
+// Register-resident forms for n <= 64 (k_dense.hip); launch_precond and
+// launch_chol route to them.
+bool precond_reg_fits(int64_t s, int64_t n);
+hipError_t launch_precond_reg(const double* Y, int64_t s, int64_t n, int lu, int prec, const double* Nin, int64_t ldn,
+                              double* R1pad, double* R1out, int32_t* perm, double* Mout, int32_t* info,
+                              int32_t stage_qr, hipStream_t st);
+hipError_t launch_chol_reg(const double* G, int ldg, int64_t n, int64_t m, int shift_mode, double* Rpad, double* Rout,
+                           int rout_user, const double* Rprev, const double* Npost, int64_t ldnp, int32_t* info,
+                           int32_t stage, hipStream_t st);
 // Copy a padded triangle to a user n x n matrix.
 hipError_t launch_unpad(const double* Rpad, int64_t n, double* R, hipStream_t st);
 // Build a padded triangle (R and reciprocal diagonal) from a user n x n matrix.
