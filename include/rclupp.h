@@ -191,7 +191,11 @@ int rclupp_omega(uint64_t seed, int64_t s, int64_t j0, int64_t cols, float* G, h
  * uint32[4*count]. */
 int rclupp_philox(const uint32_t* ctr, int64_t count, uint32_t k0, uint32_t k1, uint32_t* out, hipStream_t stream);
 
-/* Y = S X (s x n, ld s): Algorithm 2 step 1, with `prec` an rclupp_prec. */
+/* Y = S X (s x n, ld s): Algorithm 2 step 1, with `prec` an rclupp_prec.
+ * FP64: exact products of the FP32 normals with X, FP64 sums. FP32: X rounded
+ * to FP32, FP32 products and sums within a wave. BF16: G and X (through FP32)
+ * rounded to BF16, FP32 sums within a wave. All forms add the per-wave and
+ * per-workgroup partial sums in FP64 in a fixed order. */
 int rclupp_sketch(const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, uint64_t seed, int prec, double* Y,
                   hipStream_t stream);
 

@@ -61,7 +61,6 @@ int validate(int alg, int64_t m, int64_t n, int64_t ld, int64_t s, const rclupp_
   if (n <= 64 && m + 3 * ld >= ((int64_t)1 << 29)) return RCLUPP_ERR_UNSUPPORTED;
   if (o) {
     if (o->sketch_prec < 0 || o->sketch_prec > 2 || o->lu_prec < 0 || o->lu_prec > 1) return RCLUPP_ERR_INVALID_ARG;
-    if (o->sketch_prec != RCLUPP_PREC_FP64) return RCLUPP_ERR_UNSUPPORTED;
   }
   return RCLUPP_OK;
 }
@@ -491,7 +490,7 @@ int rclupp_sketch(const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, 
                   hipStream_t stream) {
   if (!X || !Y || n < 1 || m < 1 || ld < m || s < 1) return RCLUPP_ERR_INVALID_ARG;
   if (n > RCLUPP_MAX_N || s > 4096) return RCLUPP_ERR_UNSUPPORTED;
-  if (prec != RCLUPP_PREC_FP64) return RCLUPP_ERR_UNSUPPORTED;
+  if (prec < RCLUPP_PREC_FP64 || prec > RCLUPP_PREC_BF16) return RCLUPP_ERR_INVALID_ARG;
   const SketchPlan sk = plan_sketch(m, n, s, prec, env_int("RCLUPP_SKETCH_GRID", 0));
   return with_scratch(sk.part_bytes, stream, [&](char* p) {
     if (launch_sketch_partials(sk, X, m, n, ld, seed, prec, (double*)p, nullptr, stream) != hipSuccess)

@@ -129,6 +129,187 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch_f64(const double* __restr
   }
 }
 
+// ---------------------------------------------------------------------------
+// Mixed-precision sketch: the same walk with the products on the FP32 or BF16
+// matrix cores and FP32 accumulation inside a wave; the four waves' partials
+// are added in FP64 and the cross-workgroup reduction is the FP64 one above.
+//   FP32: v_mfma_f32_16x16x4_f32, G exact (it is generated in FP32), X rounded
+//         to FP32 when staged; 64-row tiles, four K-steps of 4 rows per wave.
+//   BF16: v_mfma_f32_16x16x32_bf16, G and X rounded to BF16 (round to nearest
+//         even; X through FP32); 128-row tiles, one K-step of 32 rows per wave.
+//         Operand slots: lane l, element e of A is (row l%16, k = 8(l/16)+e),
+//         of B (k = 8(l/16)+e, column l%16).
+// Both FP32-output forms return register r of lane l as row 4(l/16) + r,
+// column l%16 (the FP64 form returns row l/16 + 4r).
+// ---------------------------------------------------------------------------
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+
+__device__ __forceinline__ unsigned short f32_to_bf16_rne(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+template <int SM, int NN, bool BF>
+struct SketchLpLds {
+  static constexpr int TK = BF ? 128 : 64;           // tall rows per tile
+  static constexpr int LD = BF ? TK + 8 : NN + 1;    // BF16: [col][row]; FP32: [row][col]
+  static constexpr int TILE_BYTES = BF ? NN * LD * 2 : TK * LD * 4;
+  static constexpr int RED_BYTES = SM * NN * 8;
+  static constexpr int BYTES = (2 * TILE_BYTES > RED_BYTES) ? 2 * TILE_BYTES : RED_BYTES;
+};
+
+template <int SM, int NN, bool BF>
+__global__ __launch_bounds__(SK_THREADS) void k_sketch_lp(const double* __restrict__ X, int64_t m, int n, int64_t ld,
+                                                          int64_t ntiles, uint64_t seed, double* __restrict__ Ypart,
+                                                          int64_t s_pad, int64_t n_pad, const int32_t* info) {
+  if (info_failed(info)) return;
+  using L = SketchLpLds<SM, NN, BF>;
+  constexpr int MB = SM / 16, NB = NN / 16, TK = L::TK, LD = L::LD;
+  constexpr int RPT = TK / 64 * 1;           // loader: rows per thread group
+  constexpr int CPT = NN * TK / SK_THREADS;  // tile entries loaded per thread
+  __shared__ __align__(16) unsigned char lds_raw[L::BYTES];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int sg = blockIdx.y, col0 = blockIdx.z * NN;
+  // loader: thread -> row (tid % TK), columns (tid / TK) + (SK_THREADS / TK) c
+  constexpr int CSTEP = SK_THREADS / TK;
+  const int lrow = tid % TK, lcol0 = tid / TK;
+  (void)RPT;
+
+  f32x4 acc[MB][NB];
+#pragma unroll
+  for (int a = 0; a < MB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // prefetch registers: FP32 values, or BF16 pairs (two columns per word)
+  constexpr int PRE = BF ? CPT / 2 : CPT;
+  uint32_t pre[PRE];
+  auto load_tile = [&](int64_t t) {
+    const int64_t row = t * TK + lrow;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      const int col = col0 + lcol0 + CSTEP * c;
+      const float v = (row < m && col < n) ? (float)X[row + (int64_t)col * ld] : 0.f;
+      if constexpr (BF) {
+        const uint32_t h = f32_to_bf16_rne(v);
+        pre[c >> 1] = (c & 1) ? (pre[c >> 1] | (h << 16)) : h;
+      } else {
+        pre[c] = __float_as_uint(v);
+      }
+    }
+  };
+  auto store_tile = [&](int buf) {
+    if constexpr (BF) {
+      unsigned short* xs = (unsigned short*)(lds_raw + buf * L::TILE_BYTES);
+#pragma unroll
+      for (int c = 0; c < CPT; ++c)
+        xs[(lcol0 + CSTEP * c) * LD + lrow] = (unsigned short)((c & 1) ? (pre[c >> 1] >> 16) : (pre[c >> 1] & 0xFFFFu));
+    } else {
+      float* xs = (float*)(lds_raw + buf * L::TILE_BYTES);
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) xs[lrow * LD + lcol0 + CSTEP * c] = __uint_as_float(pre[c]);
+    }
+  };
+
+  const int ai = lane & 15, ag = lane >> 4;
+  const uint32_t qbase = (uint32_t)((sg * SM) / 4 + 4 * (ai >> 2) + (ai & 3));
+
+  int64_t t = blockIdx.x;
+  int buf = 0;
+  if (t < ntiles) {
+    load_tile(t);
+    store_tile(0);
+  }
+  __syncthreads();
+  for (; t < ntiles; t += gridDim.x) {
+    const int64_t tn = t + gridDim.x;
+    if (tn < ntiles) load_tile(tn);
+    if constexpr (BF) {
+      const unsigned short* xs = (const unsigned short*)(lds_raw + buf * L::TILE_BYTES);
+      const int r0 = 32 * wave + 8 * ag;  // this lane's 8 tall rows within the tile
+      bf16x8 b[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const uint4 q = *(const uint4*)(xs + (16 * nb + ai) * LD + r0);
+        b[nb] = __builtin_bit_cast(bf16x8, q);
+      }
+      const int64_t j0 = t * TK + r0;
+#pragma unroll
+      for (int a = 0; a < SM / 64; ++a) {
+        // packed BF16 pairs: pk[u][e/2] holds elements e, e+1 of M-block 4a+u
+        uint32_t pk[4][4];
+#pragma unroll
+        for (int e = 0; e < 8; e += 2) {
+          f32x4 z0 = {0.f, 0.f, 0.f, 0.f}, z1 = {0.f, 0.f, 0.f, 0.f};
+          if (j0 + e < m) z0 = normals4(seed, (uint64_t)(j0 + e), qbase + 16u * (uint32_t)a);
+          if (j0 + e + 1 < m) z1 = normals4(seed, (uint64_t)(j0 + e + 1), qbase + 16u * (uint32_t)a);
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            pk[u][e >> 1] = (uint32_t)f32_to_bf16_rne(z0[u]) | ((uint32_t)f32_to_bf16_rne(z1[u]) << 16);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const uint4 q4 = {pk[u][0], pk[u][1], pk[u][2], pk[u][3]};
+          const bf16x8 A = __builtin_bit_cast(bf16x8, q4);
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            acc[4 * a + u][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, b[nb], acc[4 * a + u][nb], 0, 0, 0);
+        }
+      }
+    } else {
+      const float* xs = (const float*)(lds_raw + buf * L::TILE_BYTES);
+#pragma unroll 1
+      for (int ks = 0; ks < 4; ++ks) {
+        const int rloc = 16 * wave + 4 * ks + ag;
+        const int64_t j = t * TK + rloc;
+        float b[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) b[nb] = xs[rloc * LD + 16 * nb + ai];
+#pragma unroll
+        for (int a = 0; a < SM / 64; ++a) {
+          f32x4 z = {0.f, 0.f, 0.f, 0.f};
+          if (j < m) z = normals4(seed, (uint64_t)j, qbase + 16u * (uint32_t)a);
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+              acc[4 * a + u][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(z[u], b[nb], acc[4 * a + u][nb], 0, 0, 0);
+        }
+      }
+    }
+    if (tn < ntiles) store_tile(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  // Sum the four waves' partials in wave order (FP64) through LDS, then store.
+  double* red = (double*)lds_raw;
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int a = 0; a < MB; ++a)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int idx = ((a * NB + nb) * 4 + r) * 64 + lane;
+            const double v = (w == 0) ? (double)acc[a][nb][r] : red[idx] + (double)acc[a][nb][r];
+            if (w < 3) {
+              red[idx] = v;
+            } else {
+              // slot row of M-block a -> sketch row 64(a/4) + 16c + 4t + a%4 for slot 4c + t
+              const int slot = 4 * (lane >> 4) + r;
+              const int64_t srow = (int64_t)sg * SM + 64 * (a >> 2) + 16 * (slot >> 2) + 4 * (slot & 3) + (a & 3);
+              const int64_t col = col0 + 16 * nb + (lane & 15);
+              Ypart[(int64_t)blockIdx.x * s_pad * n_pad + srow + col * s_pad] = v;
+            }
+          }
+    }
+    __syncthreads();
+  }
+}
+
 // Y[i + j*s] = scale * sum_y lvl[y][i + j*s_pad] (the level-1 sums of the
 // per-workgroup partials, added in split order).
 __global__ void k_sketch_final(const double* __restrict__ lvl, int splits, int64_t s, int64_t n, int64_t s_pad,
@@ -169,7 +350,6 @@ __global__ void k_philox(const uint32_t* __restrict__ ctr, int64_t count, uint32
 int64_t pad_sketch_rows(int64_t s) { return (s + 63) / 64 * 64; }
 
 SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int gx_hint) {
-  (void)prec;
   SketchPlan p{};
   if (n <= 16) {
     p.nn = 16;
@@ -188,7 +368,8 @@ SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int gx_hint) {
   p.gy = (int)(p.s_pad / p.sm);
   p.gz = (int)((n + p.nn - 1) / p.nn);
   p.n_pad = (int64_t)p.gz * p.nn;
-  p.ntiles = (m + SK_TK - 1) / SK_TK;
+  const int tk = (prec == 2) ? 128 : SK_TK;  // BF16 tiles are 128 rows
+  p.ntiles = (m + tk - 1) / tk;
   int gx = gx_hint > 0 ? gx_hint : 512;
   const int per_chunk = p.gy * p.gz;
   if (per_chunk > 1) gx = (gx + per_chunk - 1) / per_chunk;
@@ -202,19 +383,26 @@ SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int gx_hint) {
 
 template <int SM, int NN>
 static hipError_t launch_sk(const SketchPlan& p, const double* X, int64_t m, int64_t n, int64_t ld, uint64_t seed,
-                            double* Ypart, const int32_t* info, hipStream_t st) {
+                            int prec, double* Ypart, const int32_t* info, hipStream_t st) {
   dim3 grid(p.gx, p.gy, p.gz);
-  hipLaunchKernelGGL((k_sketch_f64<SM, NN>), grid, dim3(SK_THREADS), 0, st, X, m, (int)n, ld, p.ntiles, seed, Ypart,
-                     p.s_pad, p.n_pad, info);
+  if (prec == 0)
+    hipLaunchKernelGGL((k_sketch_f64<SM, NN>), grid, dim3(SK_THREADS), 0, st, X, m, (int)n, ld, p.ntiles, seed, Ypart,
+                       p.s_pad, p.n_pad, info);
+  else if (prec == 1)
+    hipLaunchKernelGGL((k_sketch_lp<SM, NN, false>), grid, dim3(SK_THREADS), 0, st, X, m, (int)n, ld, p.ntiles, seed,
+                       Ypart, p.s_pad, p.n_pad, info);
+  else
+    hipLaunchKernelGGL((k_sketch_lp<SM, NN, true>), grid, dim3(SK_THREADS), 0, st, X, m, (int)n, ld, p.ntiles, seed,
+                       Ypart, p.s_pad, p.n_pad, info);
   return hipGetLastError();
 }
 
 hipError_t launch_sketch_partials(const SketchPlan& p, const double* X, int64_t m, int64_t n, int64_t ld, uint64_t seed,
                                   int prec, double* Ypart, const int32_t* info, hipStream_t st) {
-  if (prec != 0) return hipErrorInvalidValue;
+  if (prec < 0 || prec > 2) return hipErrorInvalidValue;
   if (p.gx < 1 || p.ntiles < 1) return hipErrorInvalidValue;
 #define SK_CASE(SMV, NNV) \
-  if (p.sm == SMV && p.nn == NNV) return launch_sk<SMV, NNV>(p, X, m, n, ld, seed, Ypart, info, st);
+  if (p.sm == SMV && p.nn == NNV) return launch_sk<SMV, NNV>(p, X, m, n, ld, seed, prec, Ypart, info, st);
   SK_CASE(64, 16)
   SK_CASE(128, 16)
   SK_CASE(256, 16)

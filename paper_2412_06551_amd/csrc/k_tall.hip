@@ -1,19 +1,15 @@
 // Tall passes of CholeskyQR (Algorithm 1 steps 1 and 3) around a small upper
 // triangular R:  W = X R^{-1}  and  G = W^T W.
 //
-// Layout and mapping. One thread owns one row of the tall operand: its n
-// entries are read with one coalesced 512-byte access per column per wave
-// (column-major data), the row is solved in registers by substitution
+// n <= 64: one fused kernel per pass (k_tall_mfma). The substitution
 //   w_j = (x_j - sum_{i<j} w_i R_ij) / R_jj   (backward stable, eq. ewy; no
-//   explicit inverse of the possibly very ill-conditioned R_1),
-// with R (wave-uniform) streamed through the scalar data path, and written
-// back with the same coalesced pattern. For n <= 64 the Gram partial sum is
-// fused: each wave stages its rows (32 at a time) column-major in its own LDS
-// region and feeds v_mfma_f64_16x16x4_f64 with 16-column fragments, upper
-// 16x16 blocks only. For larger n the substitution walks 64-column blocks
-// (earlier blocks of the row are re-read from W, which the thread wrote) and
-// the Gram is a separate MFMA pass over W.
-// Per-workgroup Gram partials are added in workgroup order by a second kernel.
+//   explicit inverse of the possibly very ill-conditioned R_1)
+// runs blocked on the FP64 matrix cores with the diagonal blocks finished row
+// by row in registers; the Gram partial sum of the solved rows is fused.
+// n > 64: a blocked substitution kernel (64-column blocks, one row per thread)
+// and a separate MFMA Gram kernel over W.
+// Per-workgroup Gram partials are added in a fixed two-level order by
+// k_partial_sum and k_gram_final, so results do not depend on timing.
 #include "device_common.hpp"
 #include "launch.hpp"
 
@@ -40,22 +36,37 @@ int pad_cols(int64_t n) {
 // MFMA roles: M = the 16 columns of block b, N = 16 rows of X, K = 4 columns of
 // an earlier block c. The output layout (lane l, register r holds row l%16,
 // column 16b + l/16 + 4r) is exactly the B-operand layout the later blocks
-// need (B fragment kk of block c = output register kk), so solved blocks stay
-// in registers. The off-diagonal A fragments (-R_{c,b}^T) are loaded into
-// registers once per workgroup. In the substitution each column is owned by
-// one 16-lane group (column = group + 4 r); its solved value is broadcast to
-// the other three groups of the same row (ds_bpermute) and the trailing
-// columns are updated with R entries read from an LDS table (entries at or
-// left of the pivot column are stored as zero, so no masking is needed).
+// need (B fragment kk of block c = output register kk, columns 16c + 4kk + k
+// in K order), so solved blocks stay in registers and every column takes its
+// terms in ascending order. The off-diagonal A fragments (-R_{c,b}^T) are
+// built in LDS once per workgroup.
+// The diagonal block is solved row by row: the wave's 32 rows go through a
+// per-wave LDS transpose so that lane l < 32 holds the 16 block entries of one
+// row, which it finishes in registers, w_j = (x_j - sum_{i<j} w_i R_ij) / R_jj
+// in ascending i with fused multiply-adds, the quotient correctly rounded
+// (from the correctly rounded reciprocal of R_jj with two Markstein
+// corrections; exact away from underflow and overflow). That is the
+// row-wise substitution's arithmetic, so W is bit-identical to it.
 // Each wave handles two 16-row blocks (32 rows); the four waves of a
 // workgroup cover a 128-row tile. X and W move in 128-byte row segments.
 // The Gram partial sums stage the solved rows in a per-wave LDS region
-// (column-major, stride 33) and use v_mfma_f64_16x16x4_f64 on the upper
+// (column-major, stride 17) and use v_mfma_f64_16x16x4_f64 on the upper
 // 16x16 blocks.
 // ---------------------------------------------------------------------------
 constexpr int TM_ROWS_WAVE = 32;
 constexpr int TM_TILE = 4 * TM_ROWS_WAVE;  // rows per workgroup tile
 constexpr int TM_LDG = 17;                 // Gram staging: 16 rows + pad per column
+constexpr int TM_LDT = 18;                 // diagonal transpose: 16 entries + pad per row (16-byte aligned)
+
+// a / b from y = RN(1/b): q0 = a y is within two ulps; one correction makes it
+// faithful, the second (Markstein) makes it the correctly rounded quotient.
+__device__ __forceinline__ double quot_rn(double a, double b, double y) {
+  double q = a * y;
+  double r = __builtin_fma(-q, b, a);
+  q = __builtin_fma(r, y, q);
+  r = __builtin_fma(-q, b, a);
+  return __builtin_fma(r, y, q);
+}
 
 template <int NP, bool TRSM, bool GRAM, bool WRITE>
 __global__ __launch_bounds__(TP_THREADS, 2) void k_tall_mfma(const double* X, int64_t ldx, int64_t m, int n,
@@ -66,12 +77,14 @@ __global__ __launch_bounds__(TP_THREADS, 2) void k_tall_mfma(const double* X, in
   constexpr int NB = NP / 16;                  // column blocks
   constexpr int NOFF = NB * (NB - 1) / 2;      // off-diagonal block pairs c < b
   constexpr int NBLK = NB * (NB + 1) / 2;      // upper Gram blocks
-  constexpr int DTAB = TRSM ? NB * 16 * 16 : 1;  // diagonal tables: [b][jj][q][r]
+  constexpr int DTAB = TRSM ? NB * 272 : 1;    // diagonal blocks [b][j][k] then reciprocals [b][j]
+  constexpr int TTAB = TRSM ? 4 * TM_ROWS_WAVE * TM_LDT : 1;  // per-wave transpose regions
   constexpr int GST = GRAM ? ((4 * NP * TM_LDG > NBLK * 256) ? 4 * NP * TM_LDG : NBLK * 256) : 1;
   constexpr int OTAB = (TRSM && NOFF > 0) ? NOFF * 4 * 64 : 1;  // [pair][kk][lane]
   __shared__ double dtab[DTAB];
   __shared__ double otab[OTAB];
   __shared__ double gst[GST];
+  __shared__ __align__(16) double ttab[TTAB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lq = lane >> 4;
 
@@ -86,11 +99,15 @@ __global__ __launch_bounds__(TP_THREADS, 2) void k_tall_mfma(const double* X, in
       }
       otab[e] = -Rp[(16 * c + 4 * kk + (l >> 4)) * NP + 16 * b + (l & 15)];
     }
-    // diagonal tables: dtab[((b*16 + jj)*4 + q)*4 + r] = R[16b+jj][16b+q+4r] if q+4r > jj else 0
+    // diagonal blocks dtab[b*256 + j*16 + k] = R[16b+j][16b+k] (zero below the
+    // diagonal), then dtab[NB*256 + 16b + j] = RN(1 / R[16b+j][16b+j])
     for (int e = tid; e < DTAB; e += TP_THREADS) {
-      const int r = e & 3, q = (e >> 2) & 3, jj = (e >> 4) & 15, b = e >> 8;
-      const int col = q + 4 * r;
-      dtab[e] = (col > jj) ? Rp[(16 * b + jj) * NP + 16 * b + col] : 0.0;
+      if (e < NB * 256) {
+        const int k = e & 15, j = (e >> 4) & 15, b = e >> 8;
+        dtab[e] = (k >= j) ? Rp[(16 * b + j) * NP + 16 * b + k] : 0.0;
+      } else {
+        dtab[e] = Rp[NP * NP + (e - NB * 256)];
+      }
     }
   }
   __syncthreads();
@@ -104,7 +121,7 @@ __global__ __launch_bounds__(TP_THREADS, 2) void k_tall_mfma(const double* X, in
     const int64_t row0 = t * TM_TILE + wave * TM_ROWS_WAVE;
     f64x4 acc[2][NB];
     // addresses: a wave-uniform column base (scalar) plus a 32-bit per-lane offset
-    // (row + (l/16) ld); requires 4 ld + m < 2^29 rows, checked by the launcher
+    // (row + (l/16) ld); requires 3 ld + m < 2^29, checked by the launcher
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int64_t row = row0 + 16 * h + lr;
@@ -139,26 +156,47 @@ __global__ __launch_bounds__(TP_THREADS, 2) void k_tall_mfma(const double* X, in
           }
           ++p;
         }
-        // substitution within the diagonal block
+        // the diagonal block: transpose so that lane l < 32 holds row l's 16
+        // entries, substitute in registers, transpose back
+        double* tt = ttab + wave * TM_ROWS_WAVE * TM_LDT;
 #pragma unroll
-        for (int jj = 0; jj < 16; ++jj) {
-          const int qo = jj & 3, ro = jj >> 2;
-          // true division by the diagonal (not a reciprocal multiply): the same
-          // rounding as the row-wise substitution w_j = (x_j - sum) / R_jj
-          const double dv = Rt[(16 * b + jj) * NP + 16 * b + jj];
-          const double* tb = dtab + dofs + ((b * 16 + jj) * 4 + lq) * 4;
-          const double t0 = tb[0], t1 = tb[1], t2 = tb[2], t3 = tb[3];
-          const int src = lr + 16 * qo;
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const double wv = __shfl(acc[h][b][ro] / dv, src);
-            const bool own = (lq == qo);
-            acc[h][b][0] = (own && ro == 0) ? wv : __builtin_fma(-wv, t0, acc[h][b][0]);
-            acc[h][b][1] = (own && ro == 1) ? wv : __builtin_fma(-wv, t1, acc[h][b][1]);
-            acc[h][b][2] = (own && ro == 2) ? wv : __builtin_fma(-wv, t2, acc[h][b][2]);
-            acc[h][b][3] = (own && ro == 3) ? wv : __builtin_fma(-wv, t3, acc[h][b][3]);
+          for (int r = 0; r < 4; ++r) tt[(16 * h + lr) * TM_LDT + lq + 4 * r] = acc[h][b][r];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < TM_ROWS_WAVE) {
+          double v[16];
+          const double2* src = (const double2*)(tt + lane * TM_LDT);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const double2 q = src[e];
+            v[2 * e] = q.x;
+            v[2 * e + 1] = q.y;
           }
+          const double* rb = dtab + dofs + b * 256;
+          const double* yb = dtab + dofs + NB * 256 + 16 * b;
+#pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            v[j] = quot_rn(v[j], rb[j * 16 + j], yb[j]);
+#pragma unroll
+            for (int k = j + 1; k < 16; ++k) v[k] = __builtin_fma(-v[j], rb[j * 16 + k], v[k]);
+          }
+          double2* dst = (double2*)(tt + lane * TM_LDT);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) dst[e] = double2{v[2 * e], v[2 * e + 1]};
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[h][b][r] = tt[(16 * h + lr) * TM_LDT + lq + 4 * r];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     }
     if (WRITE) {
@@ -179,7 +217,7 @@ __global__ __launch_bounds__(TP_THREADS, 2) void k_tall_mfma(const double* X, in
       }
     }
     if (GRAM) {
-      // stage 16 rows at a time column-major (stride TP_LDW), then Gram fragments
+      // stage 16 rows at a time column-major (stride TM_LDG), then Gram fragments
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
 #pragma unroll
@@ -401,7 +439,7 @@ TallPlan plan_tall(int64_t m, int64_t n, int gx_hint) {
   p.fused_gram = p.np <= 64;
   p.tile_rows = p.fused_gram ? TM_TILE : TP_THREADS;
   p.ntiles = (m + p.tile_rows - 1) / p.tile_rows;
-  int gx = gx_hint > 0 ? gx_hint : 512;
+  int gx = gx_hint > 0 ? gx_hint : 1024;
   if (gx > p.ntiles) gx = (int)p.ntiles;
   if (gx < 1) gx = 1;
   p.gx = gx;

@@ -211,6 +211,40 @@ def test_batched_matches_single():
         np.testing.assert_array_equal(to_host(Rs[i]), to_host(one.R))
 
 
+# ------------------------------------------------------------------ mixed precision
+# FP32 or BF16 sketch on MFMA and an FP32 preconditioner; the tall passes, the
+# Cholesky factors and the last CholeskyQR pass stay FP64, so the final Q and R
+# must meet the same bar against the FP64 oracle wherever the rounded
+# preconditioner still brings Q_1 into CholeskyQR2's range.
+@pytest.mark.parametrize("sk,lu,kappa", [("fp32", "fp32", 1e2), ("fp32", "fp32", 1e8), ("fp32", "fp32", 1e14),
+                                         ("fp32", "fp64", 1e14), ("bf16", "fp32", 1e2), ("bf16", "fp32", 1e6),
+                                         ("bf16", "fp64", 1e6)])
+def test_mixed_rclupp(sk, lu, kappa):
+    m, n, s = 40000 + 11, 64, 256
+    x = make_svd(m, n, kappa, seed=21)
+    res = _lib().qr(to_dev(x), alg="rclupp", s=s, seed=4, sketch_prec=sk, lu_prec=lu)
+    method_parity(x, "rclupp", s, 4, kappa, res)
+
+
+@pytest.mark.parametrize("kappa", [1e4, 1e10, 1e15])
+def test_mixed_rcluppr_bf16(kappa):
+    # the sketch of the well-conditioned M factor tolerates BF16 at any kappa
+    m, n, s = 30000 + 5, 48, 96
+    x = make_svd(m, n, kappa, seed=22)
+    res = _lib().qr(to_dev(x), alg="rcluppr", s=s, seed=1, sketch_prec="bf16", lu_prec="fp32")
+    method_parity(x, "rcluppr", s, 1, kappa, res)
+
+
+@pytest.mark.parametrize("sk", ["fp32", "bf16"])
+@pytest.mark.parametrize("kappa", [1e2, 1e8])
+def test_mixed_wide(sk, kappa):
+    # the n = 256, s = 4n shape of the mixed-precision workload at reduced m
+    m, n, s = 20000 + 3, 256, 1024
+    x = make_svd(m, n, kappa, seed=23)
+    res = _lib().qr(to_dev(x), alg="rclupp", s=s, seed=0, sketch_prec=sk, lu_prec="fp32")
+    method_parity(x, "rclupp", s, 0, kappa, res)
+
+
 # ------------------------------------------------------------------ full size
 @pytest.mark.parametrize("kappa", [1e4, 1e8, 1e12, 1e15])
 def test_full_size_rclupp(kappa):

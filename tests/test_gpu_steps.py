@@ -62,6 +62,23 @@ def test_sketch_matches_oracle(m, n, s, seed):
     assert np.all(np.abs(y - want) <= bound)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("m,n,s,seed", [(2048, 32, 64, 0), (5000 + 37, 64, 128, 3), (3000, 100, 200, 2),
+                                        (4099, 256, 512, 5), (700, 16, 40, 1)])
+def test_sketch_low_precision(prec, m, n, s, seed):
+    x = make_svd(m, n, 1e6, seed=seed)
+    y = to_host(_lib().sketch(to_dev(x), s, seed, prec=prec))
+    want = oracle.sketch(x, s, seed)
+    ab = np.abs(oracle.omega(s, m, seed)) @ np.abs(x)
+    # inputs rounded to the working precision (FP32: X; BF16: G and X), products
+    # exact in FP32, at most m terms added in FP32 per accumulator, then FP64
+    uin = 2.0**-24 if prec == "fp32" else 2.0**-8
+    assert np.all(np.abs(y - want) <= (2 * uin + (m + 8) * 2.0**-24) * ab)
+    # the typical error is at the rounding level: a misplaced row or column would be O(1)
+    rel = np.abs(y - want) / ab
+    assert np.median(rel) <= 4 * uin + 4 * np.sqrt(m) * 2.0**-24
+
+
 def test_sketch_leading_dimension():
     x = make_svd(3000, 24, 1e3, seed=5)
     a = to_host(_lib().sketch(to_dev(x, ld=3072), 48, 9))
@@ -91,6 +108,22 @@ def test_precond_lu_householder(s, n, seed, kappa):
     # both are (up to row signs) the R factor of Y: R1^T R1 = Y^T Y (eq. elu-ey)
     g = y.T @ y
     assert np.linalg.norm(r1.T @ r1 - g) <= 1e-13 * np.linalg.norm(g)
+
+
+@pytest.mark.parametrize("s,n,seed", [(64, 32, 0), (128, 64, 1), (256, 128, 4)])
+@pytest.mark.parametrize("kappa", [1e2, 1e4])
+def test_precond_fp32(s, n, seed, kappa):
+    # FP32 LU + Householder on the FP64 sketch, R_1 widened to FP64: an FP32-accurate R factor of Y
+    x = make_svd(4 * s, n, kappa, seed=seed)
+    y = oracle.sketch(x, s, seed)
+    R1, _, _, info = _lib().precond(to_dev(y), lu=True, prec="fp32")
+    assert info.cpu().tolist()[0] == 0
+    Mo, No, _, _ = oracle.gepp(y)
+    r1o = oracle.trmm(oracle.house_r(Mo), No)
+    r1o = np.sign(np.diag(r1o))[:, None] * r1o
+    r1 = to_host(R1)
+    assert np.all(np.diag(r1) > 0) and np.all(np.tril(r1, -1) == 0)
+    assert np.linalg.norm(r1 - r1o) <= 64 * 2.0**-24 * kappa * n * np.linalg.norm(r1o)
 
 
 @pytest.mark.parametrize("s,n", [(64, 32), (40, 40)])
