@@ -16,7 +16,15 @@ Reported (one JSON line):
                 against MI355X's published peak for its binding resource;
   cpu_baseline= the CPU oracle (oracle/) timed on the host cores on the same
                 input; the same leg also checks the GPU result against it.
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Further legs (skipped with --no-extras), each with its own time and accuracy:
+  other_methods_ms = the other five methods on the same input;
+  mixed        = m = 4,194,304, n = 256, s = 4n = 1024, kappa = 1e8: plain FP64
+                 RCLUPP against the FP32 (sketch and LU) and BF16 (sketch) forms;
+  batched      = 512 problems (m in [1e4, 5e5], n in {16, 32, 64, 128}, kappa
+                 log-uniform in [1e2, 1e14], s = 2n) in one call: QRs/s;
+  krylov       = RCLUPPr on m = 16,777,216, n = 128 Krylov-monomial columns.
+Large inputs are generated on the GPU (gen.make_*_device).
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
 """
 from __future__ import annotations
 
@@ -127,6 +135,112 @@ def cpu_baseline(x, s, seed, q_gpu, r_gpu, budget_s=12.0):
     return base, acc
 
 
+def gpu_accuracy(X, Q, R):
+    """||Q^T Q - I||_F and ||QR - X||_F / ||X||_F in FP64 with plain torch products."""
+    import torch
+    n = Q.shape[1]
+    qtq = Q.t() @ Q
+    qtq -= torch.eye(n, dtype=torch.float64, device=Q.device)
+    orth = float(torch.linalg.matrix_norm(qtq))
+    res = float(torch.linalg.matrix_norm(Q @ R - X) / torch.linalg.matrix_norm(X))
+    return orth, res
+
+
+def time_qr(lib, X, alg, s, seed, reps, sketch_prec="fp64", lu_prec="fp64"):
+    """Median-free simple timing: one warm-up call, then `reps` calls between events."""
+    import torch
+    m, n = X.shape
+    stream = torch.cuda.current_stream()
+    Q = torch.empty((n, m), dtype=torch.float64, device=X.device).t()
+    R = torch.empty((n, n), dtype=torch.float64, device=X.device).t()
+    info = torch.zeros(4, dtype=torch.int32, device=X.device)
+    ws = torch.empty(lib.workspace_size(alg, m, n, s, sketch_prec, lu_prec), dtype=torch.uint8, device=X.device)
+
+    def call():
+        lib.qr(X, alg=alg, s=s, seed=seed, sketch_prec=sketch_prec, lu_prec=lu_prec, Q=Q, R=R, workspace=ws,
+               info=info, stream=stream)
+
+    call()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        call()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps, info.cpu().tolist(), Q, R
+
+
+def bench_mixed(lib, reps=3, kappa=1e8):
+    import torch
+    from gen import make_svd_device
+    m, n, s = 4194304, 256, 1024
+    print("bench: mixed leg, generating %dx%d" % (m, n), file=sys.stderr, flush=True)
+    X = make_svd_device(m, n, kappa, seed=0)
+    by = tall_bytes(m, n)["total"]
+    fl = tall_flops(m, n, s)["total"]
+    out = {"workload": "rclupp m=%d n=%d s=%d kappa=%.0e (SVD-based, device-generated)" % (m, n, s, kappa)}
+    r64 = None
+    for tag, sk, lu in (("fp64", "fp64", "fp64"), ("fp32", "fp32", "fp32"), ("bf16", "bf16", "fp32")):
+        ms, info, Q, R = time_qr(lib, X, "rclupp", s, 0, reps, sk, lu)
+        orth, res = gpu_accuracy(X, Q, R)
+        ent = {"sketch_prec": sk, "lu_prec": lu, "ms": round(ms, 3), "GB_s": round(by / (ms / 1e3) / 1e9, 1),
+               "fp64_tflops": round(fl / (ms / 1e3) / 1e12, 3), "info": info, "orth": orth, "rel_res": res}
+        if tag == "fp64":
+            r64 = R.clone()
+        else:
+            ent["r_rel_diff_vs_fp64"] = float(torch.linalg.matrix_norm(R - r64) / torch.linalg.matrix_norm(r64))
+        out[tag] = ent
+        print("bench: mixed %s %.3f ms info=%s orth=%.2e" % (tag, ms, info, orth), file=sys.stderr, flush=True)
+        del Q, R
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_batched(lib, reps=2):
+    import torch
+    from gen import batch_manifest, make_svd_device
+    man = batch_manifest(0, 512)
+    print("bench: batched leg, generating %d problems" % len(man), file=sys.stderr, flush=True)
+    Xs = [make_svd_device(p["m"], p["n"], p["kappa"], p["input_seed"], orthonormal=False) for p in man]
+    seeds = [p["seed"] for p in man]
+    by = sum(tall_bytes(p["m"], p["n"])["total"] for p in man)
+    lib.qr_batched(Xs, alg="rclupp", seeds=seeds)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        Qs, Rs, info = lib.qr_batched(Xs, alg="rclupp", seeds=seeds)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    info = info.cpu()
+    worst_orth, worst_res = 0.0, 0.0
+    for i in range(0, len(man), 64):  # a sample of the results
+        o, r = gpu_accuracy(Xs[i], Qs[i], Rs[i])
+        worst_orth, worst_res = max(worst_orth, o), max(worst_res, r)
+    return {"problems": len(man), "ms": round(ms, 3), "qrs_per_s": round(len(man) / (ms / 1e3), 1),
+            "GB_s": round(by / (ms / 1e3) / 1e9, 1), "failed": int((info[:, 0] != 0).sum()),
+            "sample_worst_orth": worst_orth, "sample_worst_rel_res": worst_res,
+            "workload": "512 x RCLUPP, batch_manifest(seed 0), U = normalised Gaussian columns"}
+
+
+def bench_krylov(lib):
+    import torch
+    from gen import make_krylov_device
+    m, n, s = 16777216, 128, 256
+    print("bench: krylov leg, generating %dx%d" % (m, n), file=sys.stderr, flush=True)
+    X = make_krylov_device(m, n, 0)
+    ms, info, Q, R = time_qr(lib, X, "rcluppr", s, 0, 1)
+    orth, res = gpu_accuracy(X, Q, R)
+    return {"workload": "rcluppr m=%d n=%d s=%d Krylov-monomial (device-generated)" % (m, n, s), "ms": round(ms, 3),
+            "GB_s": round(tall_bytes(m, n)["total"] / (ms / 1e3) / 1e9, 1), "info": info, "orth": orth,
+            "rel_res": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,6 +343,16 @@ def main():
         out["other_methods_ms"] = extra
         step()
         torch.cuda.synchronize()
+        t_extra = time.time()
+        for key, fn in (("mixed", bench_mixed), ("batched", bench_batched), ("krylov", bench_krylov)):
+            if time.time() - t_extra > 150:
+                out[key] = {"skipped": "time budget of the extra legs spent"}
+                continue
+            try:
+                out[key] = fn(lib)
+            except Exception as e:  # a leg that cannot run is reported, not fatal
+                out[key] = {"error": repr(e)[:300]}
+            torch.cuda.empty_cache()
 
     if not args.no_cpu:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)

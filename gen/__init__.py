@@ -8,6 +8,8 @@ from .matrices import (  # noqa: F401
     make_lowtri,
     make_arrowhead,
     make_krylov,
+    make_svd_device,
+    make_krylov_device,
     batch_manifest,
     fortran,
 )

@@ -11,6 +11,8 @@ the layout the library and the oracle take (element (i, j) at X[i + j*ld]).
 * make_krylov   -- columns A^k v / ||A^k v|| with A diagonal, eigenvalues U(0,1)
                    and v Gaussian (a severely ill-conditioned family).
 * batch_manifest-- a seeded list of problem shapes for batched runs.
+* make_svd_device, make_krylov_device -- the same families drawn on the GPU with
+                   torch's generator, for benchmark-sized inputs.
 """
 from __future__ import annotations
 
@@ -122,3 +124,57 @@ def batch_manifest(seed: int = 0, count: int = 512, m_lo: int = 10000, m_hi: int
         out.append(dict(m=int(ms[i]), n=n, kappa=float(10.0 ** lk[i]), input_seed=1000 + i,
                         seed=i, s=2 * n))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Device-side versions for benchmark-sized inputs (gigabytes): the same
+# constructions drawn with torch's generator on the GPU, so the values differ
+# from the numpy versions above (which the parity tests use).
+# ---------------------------------------------------------------------------
+def _torch_colmajor(x):
+    import torch
+    out = torch.empty((x.shape[1], x.shape[0]), dtype=torch.float64, device=x.device).t()
+    out.copy_(x)
+    return out
+
+
+def make_svd_device(m: int, n: int, kappa: float, seed: int = 0, device="cuda", orthonormal: bool = True):
+    """X = U diag(sigma) V^T on the device, column-major, sigma as in make_svd.
+
+    orthonormal=True: U is the Q factor of a Gaussian (kappa_2(X) = kappa).
+    orthonormal=False: U is a Gaussian with unit columns, whose condition number
+    is 1 + O(sqrt(n/m)), so kappa_2(X) is kappa to within a few percent (cheap
+    enough for hundreds of matrices)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    u = torch.randn((m, n), generator=g, dtype=torch.float64, device=device)
+    if orthonormal:
+        u, _ = torch.linalg.qr(u, mode="reduced")
+    else:
+        u /= torch.linalg.vector_norm(u, dim=0, keepdim=True)
+    v, _ = torch.linalg.qr(torch.randn((n, n), generator=g, dtype=torch.float64, device=device))
+    if n == 1:
+        sig = torch.ones(1, dtype=torch.float64, device=device)
+    else:
+        sig = float(kappa) ** (-torch.arange(n, dtype=torch.float64, device=device) / (n - 1))
+    x = (u * sig) @ v.t()
+    del u
+    return _torch_colmajor(x)
+
+
+def make_krylov_device(m: int, n: int, seed: int = 0, device="cuda"):
+    """make_krylov's family on the device (torch's generator), column-major."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    lam = torch.rand(m, generator=g, dtype=torch.float64, device=device)
+    cur = torch.randn(m, generator=g, dtype=torch.float64, device=device)
+    out = torch.empty((n, m), dtype=torch.float64, device=device)
+    cur = cur / torch.linalg.vector_norm(cur)
+    out[0] = cur
+    for k in range(1, n):
+        cur = lam * cur
+        cur = cur / torch.linalg.vector_norm(cur)
+        out[k] = cur
+    return out.t()
