@@ -1,4 +1,4 @@
-// Register-resident small dense stages for n <= 64, one workgroup of 1024
+// Register-resident small dense stages for n <= 128, one workgroup of 1024
 // threads each (these steps are O(s n^2) and O(n^3): their time is the length
 // of the chain of dependent column steps, so the layout is chosen to make each
 // step short):
@@ -12,9 +12,10 @@
 //                   R = R_4 R_3; eqs. C4, C8) or an optional right factor with
 //                   the sign fix (LC2's R_1 = D S_c N, Algorithm 5).
 //
-// Layout: thread (wave w, lane l) owns column j = 4w + l/16 and the rows
-// i = l%16 + 16a, a < A. The 16 lanes of a DPP row therefore hold one whole
-// column: a column reduction is four DPP exchanges inside one wave. A column
+// Layout: thread (wave w, lane l) owns the columns j = 4w + l/16 + 64c
+// (c < CS, CS = 1 for n <= 64 and 2 for n <= 128) and the rows i = l%16 + 16a,
+// a < A. The 16 lanes of a DPP row therefore hold whole columns: a column
+// reduction is four DPP exchanges inside one wave. A column
 // step is: the wave owning column k reduces it (pivot search, or the
 // reflector's norm), publishes a vector of s values to LDS, one barrier, then
 // every thread applies a rank-1 update to the A values it holds. Rows are
@@ -32,8 +33,7 @@
 namespace rclupp {
 
 constexpr int DN_THREADS = 1024;
-constexpr int DN_NP = 64;          // largest n handled here
-constexpr int DN_LD = DN_NP + 1;   // row stride of the 64 x 64 LDS tables
+constexpr int DN_NP = 128;         // largest n handled here
 
 // ---- DPP exchanges within 16-lane rows ----------------------------------------
 constexpr int DPP_XOR1 = 0xB1;         // quad_perm [1,0,3,2]
@@ -105,41 +105,49 @@ __device__ __forceinline__ double dn_fma(double a, double b, double c) { return 
 __device__ __forceinline__ float dn_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
 // ---------------------------------------------------------------------------
-// Preconditioner. A = rows per thread / 16 (s <= 16 A). Dynamic LDS:
-// precond_reg_lds_bytes<T>(A).
+// Preconditioner. A = rows per thread / 16 (s <= 16 A), CS column sets
+// (n <= 64 CS). The n x n tables R_0 and N live in LDS for CS = 1 and in the
+// global scratch for CS = 2 (row stride 64 CS + 1 either way).
 // ---------------------------------------------------------------------------
-template <typename T>
-constexpr size_t precond_reg_lds(int A) {
-  return 2 * DN_NP * DN_LD * sizeof(double) + 2 * 16 * A * sizeof(T) + 2 * 16 * A * sizeof(int);
+template <int CS>
+constexpr int dn_ld() {
+  return 64 * CS + 1;
 }
+template <typename T, int A, int CS>
+constexpr size_t precond_reg_lds() {
+  return (CS == 1 ? 2 * 64 * dn_ld<1>() * sizeof(double) : 0) + 2 * 16 * A * sizeof(T) + 2 * 16 * A * sizeof(int);
+}
+size_t precond_reg_scratch_bytes() { return 2 * (size_t)128 * dn_ld<2>() * sizeof(double); }
 
-template <typename T, int A>
+template <typename T, int A, int CS>
 __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __restrict__ Y, int s, int n, int lu,
                                                             const double* __restrict__ Nin, int ldn, double* R1pad,
                                                             int np, double* R1out, int32_t* perm_out, double* Mout,
-                                                            int32_t* info, int32_t stage_qr) {
-  constexpr int SR = 16 * A;
+                                                            double* gtab, int32_t* info, int32_t stage_qr) {
+  constexpr int SR = 16 * A, LD = dn_ld<CS>(), NT = 64 * CS;
   extern __shared__ __align__(16) unsigned char dn_smem[];
-  double* R0l = (double*)dn_smem;         // R_0(i, j) at i*DN_LD + j
-  double* Nl = R0l + DN_NP * DN_LD;       // N(i, j) at i*DN_LD + j
-  T* vb = (T*)(Nl + DN_NP * DN_LD);       // [2][SR] step vectors, entry of row r at (r%16)*A + r/16
-  int* posl = (int*)(vb + 2 * SR);        // position of row r at (r%16)*A + r/16
-  int* rowl = posl + SR;                  // row at position p
+  double* R0l = (CS == 1) ? (double*)dn_smem : gtab;  // R_0(i, j) at i*LD + j
+  double* Nl = R0l + NT * LD;                           // N(i, j) at i*LD + j
+  T* vb = (T*)(dn_smem + (CS == 1 ? 2 * NT * LD * sizeof(double) : 0));  // [2][SR] step vectors
+  int* posl = (int*)(vb + 2 * SR);  // position of row r at (r%16)*A + r/16
+  int* rowl = posl + SR;            // row at position p
   __shared__ int bc_row[2];
   __shared__ T bc_tau[2];
   __shared__ int bc_fail, bc_min;
-  __shared__ double dsg[DN_NP];
+  __shared__ double dsg[NT];
   if (info_failed(info)) return;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tr = lane & 15, col = 4 * wave + (lane >> 4);
-  T x[A];
+  const int tr = lane & 15, col0 = 4 * wave + (lane >> 4);
+  T x[CS][A];
 #pragma unroll
-  for (int a = 0; a < A; ++a) {
-    const int row = tr + 16 * a;
-    x[a] = (row < s && col < n) ? (T)Y[row + (int64_t)col * s] : T(0);
-  }
-  for (int e = tid; e < 2 * DN_NP * DN_LD; e += DN_THREADS) R0l[e] = 0.0;  // R0l and Nl
+  for (int c = 0; c < CS; ++c)
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      const int row = tr + 16 * a, col = col0 + 64 * c;
+      x[c][a] = (row < s && col < n) ? (T)Y[row + (int64_t)col * s] : T(0);
+    }
+  for (int e = tid; e < 2 * NT * LD; e += DN_THREADS) R0l[e] = 0.0;  // R0l and Nl
   for (int r = tid; r < SR; r += DN_THREADS) {
     posl[(r & 15) * A + (r >> 4)] = r;
     rowl[r] = r;
@@ -151,86 +159,99 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
   __syncthreads();
 
   if (lu) {
-    for (int k = 0; k < n; ++k) {
-      const int buf = k & 1;
-      if (wave == (k >> 2)) {
-        // pivot search over the rows at positions >= k of column k
-        int pos[A];
 #pragma unroll
-        for (int a = 0; a < A; ++a) pos[a] = posl[tr * A + a];
-        T best = T(0);
-        int key = INT_MAX, bad = 0;
+    for (int kc = 0; kc < CS; ++kc) {
+      for (int kk = 0; kk < 64; ++kk) {
+        const int k = 64 * kc + kk;
+        if (k >= n) break;
+        const int buf = k & 1;
+        if (wave == (kk >> 2)) {
+          // pivot search over the rows at positions >= k of column k
+          int pos[A];
 #pragma unroll
-        for (int a = 0; a < A; ++a) {
-          const int row = tr + 16 * a;
-          if (row < s && pos[a] >= k) {
-            bad |= !is_finite((double)x[a]);
-            piv_take(best, key, x[a], (pos[a] << 12) | row);
-          }
-        }
-        row16_argmax(best, key);
-        const bool own = (col == k);
-        const bool anybad = __ballot(own && bad) != 0;
-        if (own) {
-          const int prow = key & 4095, ppos = key >> 12;
-          const int code = anybad ? INFO_NONFINITE : (dn_abs(best) > T(0) ? 0 : INFO_LU_ZERO_PIVOT);
-          if (code) {
-            if (tr == 0) {
-              info_set(info, code, STAGE_LU, k + 1);
-              bc_fail = 1;
-            }
-          } else {
-            // multipliers l_i = x_ik / pivot (true division) for the rows still to eliminate
+          for (int a = 0; a < A; ++a) pos[a] = posl[tr * A + a];
+          T best = T(0);
+          int key = INT_MAX, bad = 0;
 #pragma unroll
-            for (int a = 0; a < A; ++a) {
-              const int row = tr + 16 * a;
-              const bool live = row < s && pos[a] >= k && row != prow;
-              const T l = live ? x[a] / best : T(0);
-              if (live) x[a] = l;
-              vb[buf * SR + tr * A + a] = l;
-            }
-            if (tr == 0) {
-              // positions k and ppos trade rows
-              const int q = rowl[k];
-              rowl[k] = prow;
-              rowl[ppos] = q;
-              posl[(prow & 15) * A + (prow >> 4)] = k;
-              posl[(q & 15) * A + (q >> 4)] = ppos;
-              bc_row[buf] = prow;
+          for (int a = 0; a < A; ++a) {
+            const int row = tr + 16 * a;
+            if (row < s && pos[a] >= k) {
+              bad |= !is_finite((double)x[kc][a]);
+              piv_take(best, key, x[kc][a], (pos[a] << 12) | row);
             }
           }
+          row16_argmax(best, key);
+          const bool own = (col0 == kk);
+          const bool anybad = __ballot(own && bad) != 0;
+          if (own) {
+            const int prow = key & 4095, ppos = key >> 12;
+            const int code = anybad ? INFO_NONFINITE : (dn_abs(best) > T(0) ? 0 : INFO_LU_ZERO_PIVOT);
+            if (code) {
+              if (tr == 0) {
+                info_set(info, code, STAGE_LU, k + 1);
+                bc_fail = 1;
+              }
+            } else {
+              // multipliers l_i = x_ik / pivot (true division) for the rows still to eliminate
+#pragma unroll
+              for (int a = 0; a < A; ++a) {
+                const int row = tr + 16 * a;
+                const bool live = row < s && pos[a] >= k && row != prow;
+                const T l = live ? x[kc][a] / best : T(0);
+                if (live) x[kc][a] = l;
+                vb[buf * SR + tr * A + a] = l;
+              }
+              if (tr == 0) {
+                // positions k and ppos trade rows
+                const int q = rowl[k];
+                rowl[k] = prow;
+                rowl[ppos] = q;
+                posl[(prow & 15) * A + (prow >> 4)] = k;
+                posl[(q & 15) * A + (q >> 4)] = ppos;
+                bc_row[buf] = prow;
+              }
+            }
+          }
         }
-      }
-      __syncthreads();
-      if (bc_fail) return;
-      if (4 * wave + 3 > k) {
-        // rank-1 update of the columns j > k with the pivot row's entries
+        __syncthreads();
+        if (bc_fail) return;
         const int prow = __builtin_amdgcn_readfirstlane(bc_row[buf]);
-        const int ap = prow >> 4;
-        T u = x[0];
+        const int ap = prow >> 4, src = (lane & 48) | (prow & 15);
 #pragma unroll
-        for (int a = 1; a < A; ++a)
-          if (a == ap) u = x[a];
-        u = __shfl(u, (lane & 48) | (prow & 15));
-        // columns <= k are final: a zero factor leaves them unchanged
-        if (col <= k) u = T(0);
+        for (int c = kc; c < CS; ++c) {
+          if (4 * wave + 3 + 64 * c > k) {
+            // rank-1 update of the columns j > k with the pivot row's entries
+            T u = x[c][0];
 #pragma unroll
-        for (int a = 0; a < A; ++a) x[a] = dn_fma(-vb[buf * SR + tr * A + a], u, x[a]);
+            for (int a = 1; a < A; ++a)
+              if (a == ap) u = x[c][a];
+            u = __shfl(u, src);
+            // columns <= k are final: a zero factor leaves them unchanged
+            if (col0 + 64 * c <= k) u = T(0);
+#pragma unroll
+            for (int a = 0; a < A; ++a) x[c][a] = dn_fma(-vb[buf * SR + tr * A + a], u, x[c][a]);
+          }
+        }
       }
     }
     __syncthreads();
   }
 
+  {
   int pos[A];
 #pragma unroll
   for (int a = 0; a < A; ++a) pos[a] = posl[tr * A + a];
   if (lu) {
     // N = the rows at positions < n (upper part); M = unit lower trapezoid
 #pragma unroll
-    for (int a = 0; a < A; ++a) {
-      if (pos[a] < n) {
-        if (col < n && col >= pos[a]) Nl[pos[a] * DN_LD + col] = (double)x[a];
-        x[a] = (col < pos[a]) ? x[a] : (col == pos[a] ? T(1) : T(0));
+    for (int c = 0; c < CS; ++c) {
+      const int col = col0 + 64 * c;
+#pragma unroll
+      for (int a = 0; a < A; ++a) {
+        if (pos[a] < n) {
+          if (col < n && col >= pos[a]) Nl[pos[a] * LD + col] = (double)x[c][a];
+          x[c][a] = (col < pos[a]) ? x[c][a] : (col == pos[a] ? T(1) : T(0));
+        }
       }
     }
     if (perm_out)
@@ -239,11 +260,13 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
     // M = Y; N external (upper part) or the identity. Non-finite entries of M
     // are reported before the reflections (lowest column).
 #pragma unroll
-    for (int a = 0; a < A; ++a)
-      if (tr + 16 * a < s && col < n && !is_finite((double)x[a])) atomicMin(&bc_min, col);
+    for (int c = 0; c < CS; ++c)
+#pragma unroll
+      for (int a = 0; a < A; ++a)
+        if (tr + 16 * a < s && col0 + 64 * c < n && !is_finite((double)x[c][a])) atomicMin(&bc_min, col0 + 64 * c);
     for (int e = tid; e < n * n; e += DN_THREADS) {
       const int i = e % n, j = e / n;
-      Nl[i * DN_LD + j] = Nin ? ((i <= j) ? Nin[i + (int64_t)j * ldn] : 0.0) : (i == j ? 1.0 : 0.0);
+      Nl[i * LD + j] = Nin ? ((i <= j) ? Nin[i + (int64_t)j * ldn] : 0.0) : (i == j ? 1.0 : 0.0);
     }
     __syncthreads();
     if (bc_min != INT_MAX) {
@@ -253,72 +276,89 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
   }
   if (Mout) {
 #pragma unroll
-    for (int a = 0; a < A; ++a)
-      if (tr + 16 * a < s && col < n) Mout[pos[a] + (int64_t)col * s] = (double)x[a];
+    for (int c = 0; c < CS; ++c)
+#pragma unroll
+      for (int a = 0; a < A; ++a)
+        if (tr + 16 * a < s && col0 + 64 * c < n) Mout[pos[a] + (int64_t)(col0 + 64 * c) * s] = (double)x[c][a];
+  }
   }
 
   // Householder reflections (LAPACK dlarfg convention) on the rows in position order
-  for (int k = 0; k < n; ++k) {
-    const int buf = k & 1;
-    if (wave == (k >> 2)) {
-      T sq = T(0), al = T(0);
 #pragma unroll
-      for (int a = 0; a < A; ++a) {
-        if (pos[a] > k && tr + 16 * a < s) sq = dn_fma(x[a], x[a], sq);
-        if (pos[a] == k) al = x[a];
-      }
-      sq = row16_sum(sq);
-      al = row16_sum(al);  // one non-zero term: exact
-      if (col == k) {
-        const T xnorm = sqrt(sq);
-        T tau = T(0), scal = T(0), beta = al;
-        if (xnorm != T(0)) {
-          beta = -copysign(hypot(al, xnorm), al);
-          tau = (beta - al) / beta;
-          scal = T(1) / (al - beta);
-        }
+  for (int kc = 0; kc < CS; ++kc) {
+    for (int kk = 0; kk < 64; ++kk) {
+      const int k = 64 * kc + kk;
+      if (k >= n) break;
+      const int buf = k & 1;
+      if (wave == (kk >> 2)) {
+        int pos[A];
+#pragma unroll
+        for (int a = 0; a < A; ++a) pos[a] = posl[tr * A + a];
+        T sq = T(0), al = T(0);
 #pragma unroll
         for (int a = 0; a < A; ++a) {
-          const T v = (pos[a] > k && tr + 16 * a < s) ? x[a] * scal : (pos[a] == k ? T(1) : T(0));
-          if (tau != T(0)) {
-            if (pos[a] > k)
-              x[a] = v;
-            else if (pos[a] == k)
-              x[a] = beta;
-          }
-          vb[buf * SR + tr * A + a] = v;
+          if (pos[a] > k && tr + 16 * a < s) sq = dn_fma(x[kc][a], x[kc][a], sq);
+          if (pos[a] == k) al = x[kc][a];
         }
-        if (tr == 0) bc_tau[buf] = tau;
+        sq = row16_sum(sq);
+        al = row16_sum(al);  // one non-zero term: exact
+        if (col0 == kk) {
+          const T xnorm = sqrt(sq);
+          T tau = T(0), scal = T(0), beta = al;
+          if (xnorm != T(0)) {
+            beta = -copysign(hypot(al, xnorm), al);
+            tau = (beta - al) / beta;
+            scal = T(1) / (al - beta);
+          }
+#pragma unroll
+          for (int a = 0; a < A; ++a) {
+            const T v = (pos[a] > k && tr + 16 * a < s) ? x[kc][a] * scal : (pos[a] == k ? T(1) : T(0));
+            if (tau != T(0)) {
+              if (pos[a] > k)
+                x[kc][a] = v;
+              else if (pos[a] == k)
+                x[kc][a] = beta;
+            }
+            vb[buf * SR + tr * A + a] = v;
+          }
+          if (tr == 0) bc_tau[buf] = tau;
+        }
       }
-    }
-    __syncthreads();
-    if (4 * wave + 3 > k) {
+      __syncthreads();
       const T tau = bc_tau[buf];
       if (tau != T(0)) {
-        // w_j = v^T M(:, j); M(:, j) -= tau w_j v for the columns j > k
-        T v[A];
-        T p = T(0);
+        const T* vv = vb + buf * SR + tr * A;  // re-read from LDS: keeps registers for x
 #pragma unroll
-        for (int a = 0; a < A; ++a) {
-          v[a] = vb[buf * SR + tr * A + a];
-          p = dn_fma(v[a], x[a], p);
+        for (int c = kc; c < CS; ++c) {
+          if (4 * wave + 3 + 64 * c > k) {
+            // w_j = v^T M(:, j); M(:, j) -= tau w_j v for the columns j > k
+            T p = T(0);
+#pragma unroll
+            for (int a = 0; a < A; ++a) p = dn_fma(vv[a], x[c][a], p);
+            p = row16_sum(p);
+            const T t = (col0 + 64 * c > k) ? tau * p : T(0);
+#pragma unroll
+            for (int a = 0; a < A; ++a) x[c][a] = dn_fma(-t, vv[a], x[c][a]);
+          }
         }
-        p = row16_sum(p);
-        const T t = (col > k) ? tau * p : T(0);
-#pragma unroll
-        for (int a = 0; a < A; ++a) x[a] = dn_fma(-t, v[a], x[a]);
       }
     }
   }
 
   // R_0: the rows at positions < n, columns >= position
 #pragma unroll
-  for (int a = 0; a < A; ++a)
-    if (pos[a] < n && col < n && col >= pos[a]) R0l[pos[a] * DN_LD + col] = (double)x[a];
+  for (int c = 0; c < CS; ++c) {
+    const int col = col0 + 64 * c;
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      const int pa = posl[tr * A + a];
+      if (pa < n && col < n && col >= pa) R0l[pa * LD + col] = (double)x[c][a];
+    }
+  }
   __syncthreads();
   // diag(R_0 N) = diag(R_0) diag(N) (both triangular); D and the first failing index
   if (tid < n) {
-    const double d = R0l[tid * DN_LD + tid] * Nl[tid * DN_LD + tid];
+    const double d = R0l[tid * LD + tid] * Nl[tid * LD + tid];
     dsg[tid] = d;
     if (!is_finite(d) || d == 0.0) atomicMin(&bc_min, tid);
   }
@@ -327,20 +367,18 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
     if (tid == 0) info_set(info, is_finite(dsg[bc_min]) ? INFO_SINGULAR : INFO_NONFINITE, STAGE_PRECOND, bc_min + 1);
     return;
   }
-  // R_1 = D R_0 N on MFMA: wave w computes output block (w/4, w%4)
-  const int I = wave >> 2, J = wave & 3, nb = np / 16;
-  if (I < nb && J < nb) {
-    const int lr = lane & 15, lq = lane >> 4;
+  // R_1 = D R_0 N on MFMA: 16 x 16 output blocks, round robin over the waves
+  const int nb = np / 16, lr = lane & 15, lq = lane >> 4;
+  for (int blk = wave; blk < nb * nb; blk += DN_THREADS / 64) {
+    const int I = blk / nb, J = blk % nb;
     f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-    if (I <= J) {
-      for (int K = I; K <= J; ++K)
+    for (int K = I; K <= J; ++K)
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const double av = R0l[(16 * I + lr) * DN_LD + 16 * K + 4 * kk + lq];
-          const double bv = Nl[(16 * K + 4 * kk + lq) * DN_LD + 16 * J + lr];
-          acc = mfma_f64(av, bv, acc);
-        }
-    }
+      for (int kk = 0; kk < 4; ++kk) {
+        const double av = R0l[(16 * I + lr) * LD + 16 * K + 4 * kk + lq];
+        const double bv = Nl[(16 * K + 4 * kk + lq) * LD + 16 * J + lr];
+        acc = mfma_f64(av, bv, acc);
+      }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * I + lq + 4 * r, j = 16 * J + lr;
@@ -357,41 +395,55 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky, right-looking on the full symmetric matrix: thread (column j,
-// rows l%16 + 16a, a < 4). Step k: the owner of column k forms row k of R
-// (its column, by symmetry) into LDS; every column j > k subtracts
-// R(k, :)^T R(k, j).
+// Cholesky, right-looking on the full symmetric matrix: thread (columns
+// 4w + l/16 + 64c, rows l%16 + 16a, a < 4 CS). Step k: the owner of column k
+// forms row k of R (its column, by symmetry) into LDS; every column j > k
+// subtracts R(k, :)^T R(k, j). Dynamic LDS: the R table, 64 CS rows of stride
+// 64 CS + 1.
 // ---------------------------------------------------------------------------
+template <int CS>
+constexpr size_t chol_reg_lds() {
+  return (size_t)64 * CS * dn_ld<CS>() * sizeof(double);
+}
+
+template <int CS>
 __global__ __launch_bounds__(DN_THREADS) void k_chol_reg(const double* __restrict__ G, int ldg, int n, int64_t m,
                                                          int shift_mode, double* Rpad, int np, double* Rout,
                                                          int rout_user, const double* __restrict__ Rprev,
                                                          const double* __restrict__ Npost, int ldnp, int32_t* info,
                                                          int32_t stage) {
-  __shared__ double Rl[DN_NP * DN_LD];  // R(i, j) at i*DN_LD + j
-  __shared__ double dg[DN_NP];
+  constexpr int LD = dn_ld<CS>(), NT = 64 * CS, A = 4 * CS;
+  extern __shared__ __align__(16) unsigned char dn_smem[];
+  double* Rl = (double*)dn_smem;  // R(i, j) at i*LD + j
+  __shared__ double dg[NT];
   __shared__ int bc_fail, bc_min;
   if (info_failed(info)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tr = lane & 15, col = 4 * wave + (lane >> 4);
-  double x[4];
+  const int tr = lane & 15, col0 = 4 * wave + (lane >> 4);
+  double x[CS][A];
   // the upper triangle of G is read; the lower one is its mirror
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int row = tr + 16 * a;
-    x[a] = (row < n && col < n) ? (row <= col ? G[row + (int64_t)col * ldg] : G[col + (int64_t)row * ldg]) : 0.0;
-  }
-  for (int e = tid; e < DN_NP * DN_LD; e += DN_THREADS) Rl[e] = 0.0;
+  for (int c = 0; c < CS; ++c)
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      const int row = tr + 16 * a, col = col0 + 64 * c;
+      x[c][a] =
+          (row < n && col < n) ? (row <= col ? G[row + (int64_t)col * ldg] : G[col + (int64_t)row * ldg]) : 0.0;
+    }
+  for (int e = tid; e < NT * LD; e += DN_THREADS) Rl[e] = 0.0;
   if (tid == 0) {
     bc_fail = 0;
     bc_min = INT_MAX;
   }
   __syncthreads();
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int row = tr + 16 * a;
-    if (row <= col && col < n && !is_finite(x[a])) atomicMin(&bc_min, col);
-    if (row == col && col < n) dg[col] = x[a];
-  }
+  for (int c = 0; c < CS; ++c)
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      const int row = tr + 16 * a, col = col0 + 64 * c;
+      if (row <= col && col < n && !is_finite(x[c][a])) atomicMin(&bc_min, col);
+      if (row == col && col < n) dg[col] = x[c][a];
+    }
   __syncthreads();
   if (bc_min != INT_MAX) {
     if (tid == 0) info_set(info, INFO_NONFINITE, stage, bc_min + 1);
@@ -404,47 +456,57 @@ __global__ __launch_bounds__(DN_THREADS) void k_chol_reg(const double* __restric
     const double u = 0x1p-53;
     const double sigma = 11.0 * ((double)m * (double)n * u + (double)n * (double)(n + 1) * u) * gm;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-      if (tr + 16 * a == col && col < n) x[a] += sigma;
+    for (int c = 0; c < CS; ++c)
+#pragma unroll
+      for (int a = 0; a < A; ++a)
+        if (tr + 16 * a == col0 + 64 * c && col0 + 64 * c < n) x[c][a] += sigma;
   }
-  for (int k = 0; k < n; ++k) {
-    if (wave == (k >> 2)) {
-      double xs = x[0];
 #pragma unroll
-      for (int a = 1; a < 4; ++a)
-        if (a == (k >> 4)) xs = x[a];
-      const double d = __shfl(xs, (lane & 48) | (k & 15));
-      if (col == k) {
-        if (!(d > 0.0)) {
-          if (tr == 0) {
-            info_set(info, INFO_CHOL_BREAKDOWN, stage, k + 1);
-            bc_fail = 1;
-          }
-        } else {
-          const double rkk = sqrt(d);
+  for (int kc = 0; kc < CS; ++kc) {
+    for (int kk = 0; kk < 64; ++kk) {
+      const int k = 64 * kc + kk;
+      if (k >= n) break;
+      if (wave == (kk >> 2)) {
+        double xs = x[kc][0];
 #pragma unroll
-          for (int a = 0; a < 4; ++a) {
-            const int row = tr + 16 * a;
-            Rl[k * DN_LD + row] = (row > k) ? x[a] / rkk : (row == k ? rkk : 0.0);
+        for (int a = 1; a < A; ++a)
+          if (a == (k >> 4)) xs = x[kc][a];
+        const double d = __shfl(xs, (lane & 48) | (k & 15));
+        if (col0 == kk) {
+          if (!(d > 0.0)) {
+            if (tr == 0) {
+              info_set(info, INFO_CHOL_BREAKDOWN, stage, k + 1);
+              bc_fail = 1;
+            }
+          } else {
+            const double rkk = sqrt(d);
+#pragma unroll
+            for (int a = 0; a < A; ++a) {
+              const int row = tr + 16 * a;
+              Rl[k * LD + row] = (row > k) ? x[kc][a] / rkk : (row == k ? rkk : 0.0);
+            }
           }
         }
       }
-    }
-    __syncthreads();
-    if (bc_fail) return;
-    if (4 * wave + 3 > k) {
-      const double rkj = (col > k) ? Rl[k * DN_LD + col] : 0.0;
+      __syncthreads();
+      if (bc_fail) return;
 #pragma unroll
-      for (int a = 0; a < 4; ++a) x[a] = __builtin_fma(-Rl[k * DN_LD + tr + 16 * a], rkj, x[a]);
+      for (int c = kc; c < CS; ++c) {
+        if (4 * wave + 3 + 64 * c > k) {
+          const int col = col0 + 64 * c;
+          const double rkj = (col > k) ? Rl[k * LD + col] : 0.0;
+#pragma unroll
+          for (int a = 0; a < A; ++a) x[c][a] = __builtin_fma(-Rl[k * LD + tr + 16 * a], rkj, x[c][a]);
+        }
+      }
     }
   }
 
-  const int I = wave >> 2, J = wave & 3, nb = np / 16;
-  const int lr = lane & 15, lq = lane >> 4;
+  const int nb = np / 16, lr = lane & 15, lq = lane >> 4;
   if (Npost) {
     // Rpad = D R N (N upper, user layout): diag(R N) = diag(R) diag(N)
     if (tid < n) {
-      const double d = Rl[tid * DN_LD + tid] * Npost[tid + (int64_t)tid * ldnp];
+      const double d = Rl[tid * LD + tid] * Npost[tid + (int64_t)tid * ldnp];
       dg[tid] = d;
       if (!is_finite(d) || d == 0.0) atomicMin(&bc_min, tid);
     }
@@ -453,18 +515,17 @@ __global__ __launch_bounds__(DN_THREADS) void k_chol_reg(const double* __restric
       if (tid == 0) info_set(info, is_finite(dg[bc_min]) ? INFO_SINGULAR : INFO_NONFINITE, STAGE_PRECOND, bc_min + 1);
       return;
     }
-    if (I < nb && J < nb) {
+    for (int blk = wave; blk < nb * nb; blk += DN_THREADS / 64) {
+      const int I = blk / nb, J = blk % nb;
       f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-      if (I <= J) {
-        for (int K = I; K <= J; ++K)
+      for (int K = I; K <= J; ++K)
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) {
-            const int kr = 16 * K + 4 * kk + lq, j = 16 * J + lr;
-            const double av = Rl[(16 * I + lr) * DN_LD + 16 * K + 4 * kk + lq];
-            const double bv = (kr <= j && j < n) ? Npost[kr + (int64_t)j * ldnp] : 0.0;
-            acc = mfma_f64(av, bv, acc);
-          }
-      }
+        for (int kk = 0; kk < 4; ++kk) {
+          const int kr = 16 * K + 4 * kk + lq, j = 16 * J + lr;
+          const double av = Rl[(16 * I + lr) * LD + 16 * K + 4 * kk + lq];
+          const double bv = (kr <= j && j < n) ? Npost[kr + (int64_t)j * ldnp] : 0.0;
+          acc = mfma_f64(av, bv, acc);
+        }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = 16 * I + lq + 4 * r, j = 16 * J + lr;
@@ -482,29 +543,30 @@ __global__ __launch_bounds__(DN_THREADS) void k_chol_reg(const double* __restric
 
   for (int e = tid; e < np * np; e += DN_THREADS) {
     const int i = e / np, j = e % np;
-    Rpad[e] = (i < n && j < n) ? Rl[i * DN_LD + j] : (i == j ? 1.0 : 0.0);
+    Rpad[e] = (i < n && j < n) ? Rl[i * LD + j] : (i == j ? 1.0 : 0.0);
   }
-  if (tid < np) Rpad[np * np + tid] = (tid < n) ? 1.0 / Rl[tid * DN_LD + tid] : 1.0;
-  if (Rout && I < nb && J < nb) {
+  if (tid < np) Rpad[np * np + tid] = (tid < n) ? 1.0 / Rl[tid * LD + tid] : 1.0;
+  if (Rout) {
     // Rout = R Rprev, Rprev a padded triangle (row-major, identity padding)
-    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-    if (I <= J) {
+    for (int blk = wave; blk < nb * nb; blk += DN_THREADS / 64) {
+      const int I = blk / nb, J = blk % nb;
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
       for (int K = I; K <= J; ++K)
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
-          const double av = Rl[(16 * I + lr) * DN_LD + 16 * K + 4 * kk + lq];
+          const double av = Rl[(16 * I + lr) * LD + 16 * K + 4 * kk + lq];
           const double bv = Rprev[(int64_t)(16 * K + 4 * kk + lq) * np + 16 * J + lr];
           acc = mfma_f64(av, bv, acc);
         }
-    }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = 16 * I + lq + 4 * r, j = 16 * J + lr;
-      if (rout_user) {
-        if (i < n && j < n) Rout[i + (int64_t)j * n] = (i > j) ? 0.0 : acc[r];
-      } else {
-        Rout[i * np + j] = (i < n && j < n) ? ((i > j) ? 0.0 : acc[r]) : (i == j ? 1.0 : 0.0);
-        if (i == j) Rout[np * np + i] = (i < n) ? 1.0 / acc[r] : 1.0;
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * I + lq + 4 * r, j = 16 * J + lr;
+        if (rout_user) {
+          if (i < n && j < n) Rout[i + (int64_t)j * n] = (i > j) ? 0.0 : acc[r];
+        } else {
+          Rout[i * np + j] = (i < n && j < n) ? ((i > j) ? 0.0 : acc[r]) : (i == j ? 1.0 : 0.0);
+          if (i == j) Rout[np * np + i] = (i < n) ? 1.0 / acc[r] : 1.0;
+        }
       }
     }
   }
@@ -513,48 +575,69 @@ __global__ __launch_bounds__(DN_THREADS) void k_chol_reg(const double* __restric
 // ---------------------------------------------------------------------------
 bool precond_reg_fits(int64_t s, int64_t n) { return n >= 1 && n <= DN_NP && s >= n && s <= 256; }
 
-template <typename T, int A>
+template <typename F>
+static hipError_t set_lds(F* fn, size_t lds) {
+  if (lds <= 64 * 1024) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) (void)hipGetLastError();
+  return e;
+}
+
+template <typename T, int A, int CS>
 static hipError_t launch_pr(const double* Y, int64_t s, int64_t n, int lu, const double* Nin, int64_t ldn,
-                            double* R1pad, double* R1out, int32_t* perm, double* Mout, int32_t* info, int32_t stage_qr,
-                            hipStream_t st) {
-  const size_t lds = precond_reg_lds<T>(A);
-  static_assert(precond_reg_lds<double>(16) <= 96 * 1024, "LDS budget");
-  hipError_t e = hipFuncSetAttribute((const void*)k_precond_reg<T, A>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return e;
-  }
-  hipLaunchKernelGGL((k_precond_reg<T, A>), dim3(1), dim3(DN_THREADS), lds, st, Y, (int)s, (int)n, lu, Nin, (int)ldn,
-                     R1pad, pad_cols(n), R1out, perm, Mout, info, stage_qr);
+                            double* R1pad, double* R1out, int32_t* perm, double* Mout, double* scratch, int32_t* info,
+                            int32_t stage_qr, hipStream_t st) {
+  constexpr size_t lds = precond_reg_lds<T, A, CS>();
+  static_assert(lds <= 96 * 1024, "LDS budget");
+  hipError_t e = set_lds(k_precond_reg<T, A, CS>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_precond_reg<T, A, CS>), dim3(1), dim3(DN_THREADS), lds, st, Y, (int)s, (int)n, lu, Nin,
+                     (int)ldn, R1pad, pad_cols(n), R1out, perm, Mout, scratch, info, stage_qr);
   return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t launch_pr_t(const double* Y, int64_t s, int64_t n, int lu, const double* Nin, int64_t ldn,
-                              double* R1pad, double* R1out, int32_t* perm, double* Mout, int32_t* info,
-                              int32_t stage_qr, hipStream_t st) {
-  if (s <= 16) return launch_pr<T, 1>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, info, stage_qr, st);
-  if (s <= 32) return launch_pr<T, 2>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, info, stage_qr, st);
-  if (s <= 64) return launch_pr<T, 4>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, info, stage_qr, st);
-  if (s <= 128) return launch_pr<T, 8>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, info, stage_qr, st);
-  return launch_pr<T, 16>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, info, stage_qr, st);
+                              double* R1pad, double* R1out, int32_t* perm, double* Mout, double* scratch,
+                              int32_t* info, int32_t stage_qr, hipStream_t st) {
+#define PR_ARGS Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, scratch, info, stage_qr, st
+  if (n > 64) {
+    if (s <= 128) return launch_pr<T, 8, 2>(PR_ARGS);
+    return launch_pr<T, 16, 2>(PR_ARGS);
+  }
+  if (s <= 16) return launch_pr<T, 1, 1>(PR_ARGS);
+  if (s <= 32) return launch_pr<T, 2, 1>(PR_ARGS);
+  if (s <= 64) return launch_pr<T, 4, 1>(PR_ARGS);
+  if (s <= 128) return launch_pr<T, 8, 1>(PR_ARGS);
+  return launch_pr<T, 16, 1>(PR_ARGS);
+#undef PR_ARGS
 }
 
 hipError_t launch_precond_reg(const double* Y, int64_t s, int64_t n, int lu, int prec, const double* Nin, int64_t ldn,
-                              double* R1pad, double* R1out, int32_t* perm, double* Mout, int32_t* info,
-                              int32_t stage_qr, hipStream_t st) {
+                              double* R1pad, double* R1out, int32_t* perm, double* Mout, double* scratch,
+                              int32_t* info, int32_t stage_qr, hipStream_t st) {
   if (!precond_reg_fits(s, n)) return hipErrorInvalidValue;
-  if (prec == 1) return launch_pr_t<float>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, info, stage_qr, st);
-  return launch_pr_t<double>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, info, stage_qr, st);
+  if (n > 64 && scratch == nullptr) return hipErrorInvalidValue;
+  if (prec == 1)
+    return launch_pr_t<float>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, scratch, info, stage_qr, st);
+  return launch_pr_t<double>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, scratch, info, stage_qr, st);
 }
 
 hipError_t launch_chol_reg(const double* G, int ldg, int64_t n, int64_t m, int shift_mode, double* Rpad, double* Rout,
                            int rout_user, const double* Rprev, const double* Npost, int64_t ldnp, int32_t* info,
                            int32_t stage, hipStream_t st) {
   if (n < 1 || n > DN_NP || (Npost && Rout)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_chol_reg, dim3(1), dim3(DN_THREADS), 0, st, G, ldg, (int)n, m, shift_mode, Rpad, pad_cols(n),
-                     Rout, rout_user, Rprev, Npost, (int)ldnp, info, stage);
+  if (n <= 64) {
+    constexpr size_t lds = chol_reg_lds<1>();
+    hipLaunchKernelGGL(k_chol_reg<1>, dim3(1), dim3(DN_THREADS), lds, st, G, ldg, (int)n, m, shift_mode, Rpad,
+                       pad_cols(n), Rout, rout_user, Rprev, Npost, (int)ldnp, info, stage);
+    return hipGetLastError();
+  }
+  constexpr size_t lds = chol_reg_lds<2>();
+  hipError_t e = set_lds(k_chol_reg<2>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_chol_reg<2>, dim3(1), dim3(DN_THREADS), lds, st, G, ldg, (int)n, m, shift_mode, Rpad,
+                     pad_cols(n), Rout, rout_user, Rprev, Npost, (int)ldnp, info, stage);
   return hipGetLastError();
 }
 

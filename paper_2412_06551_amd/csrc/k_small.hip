@@ -453,10 +453,12 @@ __global__ void k_pad(const double* __restrict__ R, int n, int np, double* __res
 // register-resident kernels of k_dense.hip.
 // ---------------------------------------------------------------------------
 size_t precond_scratch_bytes(int64_t s, int64_t n) {
-  // A (s*n) + wv (n) + N (n*n) + R (n*n) in doubles, + perm (s ints), aligned
+  // generic kernel: A (s*n) + wv (n) + N (n*n) + R (n*n) in doubles, + perm
+  // (s ints), aligned; the register-resident kernel for n > 64: its two tables
   size_t b = ((size_t)s * n + n + 2 * (size_t)n * n) * sizeof(double);
   b = (b + 255) / 256 * 256;
   b += ((size_t)s * sizeof(int32_t) + 255) / 256 * 256;
+  if (n > 64 && precond_reg_fits(s, n) && b < precond_reg_scratch_bytes()) b = precond_reg_scratch_bytes();
   return b;
 }
 
@@ -491,7 +493,7 @@ hipError_t launch_precond(const double* Y, int64_t s, int64_t n, int lu, int pre
                           int32_t stage_qr, hipStream_t st) {
   if (s < n || n < 1 || n > 256) return hipErrorInvalidValue;
   if (precond_reg_fits(s, n))
-    return launch_precond_reg(Y, s, n, lu, prec, Nin, ldn, R1pad, R1out, perm, Mout, info, stage_qr, st);
+    return launch_precond_reg(Y, s, n, lu, prec, Nin, ldn, R1pad, R1out, perm, Mout, scratch, info, stage_qr, st);
   if (prec == 1) return launch_pc<float>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, scratch, info, stage_qr, st);
   return launch_pc<double>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, scratch, info, stage_qr, st);
 }
@@ -503,7 +505,7 @@ hipError_t launch_chol(const double* G, int ldg, int64_t n, int64_t m, int shift
                        int32_t* info, int32_t stage, hipStream_t st) {
   if (n < 1 || n > 256) return hipErrorInvalidValue;
   const int np = pad_cols(n);
-  if (n <= 64 && !(Npost && Rout))
+  if (n <= 128 && !(Npost && Rout))
     return launch_chol_reg(G, ldg, n, m, shift_mode, Rpad, Rout, rout_user, Rprev, Npost, ldnp, info, stage, st);
   const size_t lds = (size_t)n * n * sizeof(double);
   const int use_lds = lds <= SD_LDS_LIMIT;

@@ -80,12 +80,14 @@ size_t chol_scratch_bytes(int64_t n);
 hipError_t launch_chol(const double* G, int ldg, int64_t n, int64_t m, int shift_mode, double* Rpad, double* Rout,
                        int rout_user, const double* Rprev, const double* Npost, int64_t ldnp, double* scratch,
                        int32_t* info, int32_t stage, hipStream_t st);
-// Register-resident forms for n <= 64 (k_dense.hip); launch_precond and
-// launch_chol route to them.
+// Register-resident forms for n <= 128 (k_dense.hip); launch_precond and
+// launch_chol route to them. For n > 64 the preconditioner keeps its two n x n
+// tables in `scratch` (precond_reg_scratch_bytes()).
 bool precond_reg_fits(int64_t s, int64_t n);
+size_t precond_reg_scratch_bytes();
 hipError_t launch_precond_reg(const double* Y, int64_t s, int64_t n, int lu, int prec, const double* Nin, int64_t ldn,
-                              double* R1pad, double* R1out, int32_t* perm, double* Mout, int32_t* info,
-                              int32_t stage_qr, hipStream_t st);
+                              double* R1pad, double* R1out, int32_t* perm, double* Mout, double* scratch,
+                              int32_t* info, int32_t stage_qr, hipStream_t st);
 hipError_t launch_chol_reg(const double* G, int ldg, int64_t n, int64_t m, int shift_mode, double* Rpad, double* Rout,
                            int rout_user, const double* Rprev, const double* Npost, int64_t ldnp, int32_t* info,
                            int32_t stage, hipStream_t st);
