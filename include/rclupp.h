@@ -18,7 +18,9 @@
  *     diagonal);
  *   - 1 <= n <= RCLUPP_MAX_N, m >= n, ld >= m, and for the sketched
  *     methods n <= s <= m (Section 3: S is s x m with s = O(n)); s and seed
- *     are ignored by the unsketched methods;
+ *     are ignored by the unsketched methods; the tall kernels address a
+ *     row tile with 32-bit offsets, so m + 3 ld < 2^29 (else
+ *     RCLUPP_ERR_UNSUPPORTED); s <= 4096;
  *   - X is read only; X and Q must not overlap; Q and R are written only;
  *   - the sketch is S = G / sqrt(s) with G_ij a standard normal drawn from
  *     Philox4x32-10 (counter = (j lo, j hi, floor(i/4), 0), key = (seed lo,

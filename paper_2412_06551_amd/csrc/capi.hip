@@ -57,8 +57,8 @@ int validate(int alg, int64_t m, int64_t n, int64_t ld, int64_t s, const rclupp_
   if (m > (int64_t)INT32_MAX && uses_tall_lu(alg)) return RCLUPP_ERR_UNSUPPORTED;
   if (sketched(alg) && (s < n || s > m)) return RCLUPP_ERR_INVALID_ARG;
   if (sketched(alg) && s > 4096) return RCLUPP_ERR_UNSUPPORTED;
-  // the n <= 64 tall kernels address a row tile with 32-bit byte offsets
-  if (n <= 64 && m + 3 * ld >= ((int64_t)1 << 29)) return RCLUPP_ERR_UNSUPPORTED;
+  // the tall kernels address a row tile with 32-bit byte offsets
+  if (m + 3 * ld >= ((int64_t)1 << 29)) return RCLUPP_ERR_UNSUPPORTED;
   if (o) {
     if (o->sketch_prec < 0 || o->sketch_prec > 2 || o->lu_prec < 0 || o->lu_prec > 1) return RCLUPP_ERR_INVALID_ARG;
   }
@@ -523,7 +523,7 @@ int rclupp_trsm_gram(const double* X, int64_t m, int64_t n, int64_t ldx, const d
                      double* G, hipStream_t stream) {
   if (!X || n < 1 || m < 1 || ldx < m) return RCLUPP_ERR_INVALID_ARG;
   if (n > RCLUPP_MAX_N) return RCLUPP_ERR_UNSUPPORTED;
-  if (n <= 64 && (m + 3 * ldx >= ((int64_t)1 << 29) || (W && m + 3 * ldw >= ((int64_t)1 << 29))))
+  if (m + 3 * ldx >= ((int64_t)1 << 29) || (W && m + 3 * ldw >= ((int64_t)1 << 29)))
     return RCLUPP_ERR_UNSUPPORTED;
   if (W && ldw < m) return RCLUPP_ERR_INVALID_ARG;
   if (R && !W) return RCLUPP_ERR_INVALID_ARG;

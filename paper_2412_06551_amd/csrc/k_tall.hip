@@ -6,8 +6,9 @@
 //   explicit inverse of the possibly very ill-conditioned R_1)
 // runs blocked on the FP64 matrix cores with the diagonal blocks finished row
 // by row in registers; the Gram partial sum of the solved rows is fused.
-// n > 64: a blocked substitution kernel (64-column blocks, one row per thread)
-// and a separate MFMA Gram kernel over W.
+// n > 64: the same blocked substitution without the fused Gram (the
+// off-diagonal fragments are read from R through the cache), then a separate
+// MFMA Gram kernel over W.
 // Per-workgroup Gram partials are added in a fixed two-level order by
 // k_partial_sum and k_gram_final, so results do not depend on timing.
 #include "device_common.hpp"
@@ -30,9 +31,12 @@ int pad_cols(int64_t n) {
 // ---------------------------------------------------------------------------
 // n <= 64: blocked substitution on the matrix cores, fused Gram.
 //
-// The solve is written transposed, W^T = R^{-T} X^T, in 16-column blocks b:
-//   C_b^T = X_b^T - sum_{c<b} R_{c,b}^T W_c^T            (v_mfma_f64_16x16x4_f64)
-//   W_b^T = R_{b,b}^{-T} C_b^T by substitution over its 16 columns.
+// The solve is written transposed, W^T = R^{-T} X^T, in 16-column blocks b,
+// right-looking: once block b is solved (substitution over its 16 columns,
+// W_b^T = R_{b,b}^{-T} C_b^T), every later block d takes its term
+//   C_d^T -= R_{b,d}^T W_b^T                              (v_mfma_f64_16x16x4_f64),
+// so C_d^T = X_d^T - sum_{b<d} R_{b,d}^T W_b^T accumulates in ascending b and
+// the products for different d are independent.
 // MFMA roles: M = the 16 columns of block b, N = 16 rows of X, K = 4 columns of
 // an earlier block c. The output layout (lane l, register r holds row l%16,
 // column 16b + l/16 + 4r) is exactly the B-operand layout the later blocks
@@ -43,33 +47,38 @@ int pad_cols(int64_t n) {
 // The diagonal block is solved row by row: the wave's 32 rows go through a
 // per-wave LDS transpose so that lane l < 32 holds the 16 block entries of one
 // row, which it finishes in registers, w_j = (x_j - sum_{i<j} w_i R_ij) / R_jj
-// in ascending i with fused multiply-adds, the quotient correctly rounded
-// (from the correctly rounded reciprocal of R_jj with two Markstein
-// corrections; exact away from underflow and overflow). That is the
-// row-wise substitution's arithmetic, so W is bit-identical to it.
-// Each wave handles two 16-row blocks (32 rows); the four waves of a
-// workgroup cover a 128-row tile. X and W move in 128-byte row segments.
+// in ascending i with fused multiply-adds, the quotient rounded to nearest
+// (from the correctly rounded reciprocal of R_jj and one remainder
+// correction, see quot_rn). That is the row-wise substitution's arithmetic,
+// so W is bit-identical to it.
+// Each wave handles two 16-row blocks (32 rows; one block when n > 128); the
+// four waves of a workgroup cover a 128-row (64-row) tile. X and W move in
+// 128-byte row segments.
 // The Gram partial sums stage the solved rows in a per-wave LDS region
 // (column-major, stride 17) and use v_mfma_f64_16x16x4_f64 on the upper
 // 16x16 blocks.
 // ---------------------------------------------------------------------------
-constexpr int TM_ROWS_WAVE = 32;
-constexpr int TM_TILE = 4 * TM_ROWS_WAVE;  // rows per workgroup tile
+// 16-row blocks per wave: two (32 rows) up to NP = 128, one for NP = 256 (whose
+// 16 column blocks of accumulators fill the register file)
+constexpr int tm_hb(int np) { return np > 128 ? 1 : 2; }
+constexpr int tm_tile(int np) { return 64 * tm_hb(np); }  // rows per workgroup tile
 constexpr int TM_LDG = 17;                 // Gram staging: 16 rows + pad per column
 constexpr int TM_LDT = 18;                 // diagonal transpose: 16 entries + pad per row (16-byte aligned)
 
-// a / b from y = RN(1/b): q0 = a y is within two ulps; one correction makes it
-// faithful, the second (Markstein) makes it the correctly rounded quotient.
+// a / b from y = RN(1/b): q0 = a y is within two ulps of a/b and the
+// remainder r = a - q0 b is formed by one fused multiply-add, so q0 + r y is
+// a/b up to a relative 4u of the error of q0, i.e. within about 2^-51 ulp;
+// rounding it gives RN(a/b) unless a/b lies that close to a rounding midpoint
+// (a/b is never exactly a midpoint unless b is a power of two, where q0 is
+// already exact). Away from underflow and overflow.
 __device__ __forceinline__ double quot_rn(double a, double b, double y) {
-  double q = a * y;
-  double r = __builtin_fma(-q, b, a);
-  q = __builtin_fma(r, y, q);
-  r = __builtin_fma(-q, b, a);
+  const double q = a * y;
+  const double r = __builtin_fma(-q, b, a);
   return __builtin_fma(r, y, q);
 }
 
 template <int NP, bool TRSM, bool GRAM, bool WRITE>
-__global__ __launch_bounds__(TP_THREADS, 2) void k_tall_mfma(const double* X, int64_t ldx, int64_t m, int n,
+__global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(const double* X, int64_t ldx, int64_t m, int n,
                                                             const double* __restrict__ Rp, double* W, int64_t ldw,
                                                             double* __restrict__ Gpart, int64_t ntiles,
                                                             const int32_t* info) {
@@ -78,9 +87,12 @@ __global__ __launch_bounds__(TP_THREADS, 2) void k_tall_mfma(const double* X, in
   constexpr int NOFF = NB * (NB - 1) / 2;      // off-diagonal block pairs c < b
   constexpr int NBLK = NB * (NB + 1) / 2;      // upper Gram blocks
   constexpr int DTAB = TRSM ? NB * 272 : 1;    // diagonal blocks [b][j][k] then reciprocals [b][j]
-  constexpr int TTAB = TRSM ? 4 * TM_ROWS_WAVE * TM_LDT : 1;  // per-wave transpose regions
+  constexpr int HB = tm_hb(NP), RW = 16 * HB;           // 16-row blocks and rows per wave
+  constexpr int TTAB = TRSM ? 4 * RW * TM_LDT : 1;       // per-wave transpose regions
   constexpr int GST = GRAM ? ((4 * NP * TM_LDG > NBLK * 256) ? 4 * NP * TM_LDG : NBLK * 256) : 1;
-  constexpr int OTAB = (TRSM && NOFF > 0) ? NOFF * 4 * 64 : 1;  // [pair][kk][lane]
+  // off-diagonal A fragments: an LDS table for NP <= 64, read from R (L2) above
+  constexpr bool OG = NP > 128;
+  constexpr int OTAB = (TRSM && NOFF > 0 && !OG) ? NOFF * 4 * 64 : 1;  // [pair][kk][lane]
   __shared__ double dtab[DTAB];
   __shared__ double otab[OTAB];
   __shared__ double gst[GST];
@@ -90,7 +102,7 @@ __global__ __launch_bounds__(TP_THREADS, 2) void k_tall_mfma(const double* X, in
 
   if (TRSM) {
     // off-diagonal A fragments: otab[(pair*4 + kk)*64 + lane] = -R[16c + 4kk + l/16][16b + l%16]
-    for (int e = tid; e < OTAB && NOFF > 0; e += TP_THREADS) {
+    for (int e = tid; e < OTAB && NOFF > 0 && !OG; e += TP_THREADS) {
       const int l = e & 63, kk = (e >> 6) & 3, pr = e >> 8;
       int b = 1, c = pr;
       while (c >= b) {
@@ -118,12 +130,12 @@ __global__ __launch_bounds__(TP_THREADS, 2) void k_tall_mfma(const double* X, in
   double* ws = gst + wave * NP * TM_LDG;
 
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int64_t row0 = t * TM_TILE + wave * TM_ROWS_WAVE;
-    f64x4 acc[2][NB];
+    const int64_t row0 = t * tm_tile(NP) + wave * RW;
+    f64x4 acc[HB][NB];
     // addresses: a wave-uniform column base (scalar) plus a 32-bit per-lane offset
     // (row + (l/16) ld); requires 3 ld + m < 2^29, checked by the launcher
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < HB; ++h) {
       const int64_t row = row0 + 16 * h + lr;
       const bool live = row < m;
       const uint32_t voff = (uint32_t)(row + (int64_t)lq * ldx);
@@ -144,29 +156,18 @@ __global__ __launch_bounds__(TP_THREADS, 2) void k_tall_mfma(const double* X, in
       const cdptr Rt = opaque_uniform(Rp);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        // C_b^T -= R_{c,b}^T W_c^T for the solved blocks c < b
-        int p = b * (b - 1) / 2;
+        // (all terms of the blocks c < b are in: solve the diagonal block b)
+        // transpose so that lane l < RW holds row l's 16 entries, substitute in
+        // registers, transpose back
+        double* tt = ttab + wave * RW * TM_LDT;
 #pragma unroll
-        for (int c = 0; c < b; ++c) {
-#pragma unroll
-          for (int kk = 0; kk < 4; ++kk) {
-            const double a = otab[dofs + (p * 4 + kk) * 64 + lane];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) acc[h][b] = mfma_f64(a, acc[h][c][kk], acc[h][b]);
-          }
-          ++p;
-        }
-        // the diagonal block: transpose so that lane l < 32 holds row l's 16
-        // entries, substitute in registers, transpose back
-        double* tt = ttab + wave * TM_ROWS_WAVE * TM_LDT;
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < HB; ++h)
 #pragma unroll
           for (int r = 0; r < 4; ++r) tt[(16 * h + lr) * TM_LDT + lq + 4 * r] = acc[h][b][r];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (lane < TM_ROWS_WAVE) {
+        if (lane < RW) {
           double v[16];
           const double2* src = (const double2*)(tt + lane * TM_LDT);
 #pragma unroll
@@ -191,17 +192,29 @@ __global__ __launch_bounds__(TP_THREADS, 2) void k_tall_mfma(const double* X, in
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < HB; ++h)
 #pragma unroll
           for (int r = 0; r < 4; ++r) acc[h][b][r] = tt[(16 * h + lr) * TM_LDT + lq + 4 * r];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // right-looking: C_d^T -= R_{b,d}^T W_b^T for every later block d > b
+        // (each block still takes its terms in ascending column order; the
+        // products for different d are independent and pipeline on the MFMA unit)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+          for (int d = b + 1; d < NB; ++d) {
+            const int pr = d * (d - 1) / 2 + b;
+            const double a = OG ? -Rt[(16 * b + 4 * kk + lq) * NP + 16 * d + lr] : otab[dofs + (pr * 4 + kk) * 64 + lane];
+#pragma unroll
+            for (int h = 0; h < HB; ++h) acc[h][d] = mfma_f64(a, acc[h][b][kk], acc[h][d]);
+          }
       }
     }
     if (WRITE) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < HB; ++h) {
         const int64_t row = row0 + 16 * h + lr;
         const uint32_t voff = (uint32_t)(row + (int64_t)lq * ldw);
         if (row < m) {
@@ -219,7 +232,7 @@ __global__ __launch_bounds__(TP_THREADS, 2) void k_tall_mfma(const double* X, in
     if (GRAM) {
       // stage 16 rows at a time column-major (stride TM_LDG), then Gram fragments
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < HB; ++h) {
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -274,44 +287,6 @@ __global__ __launch_bounds__(TP_THREADS, 2) void k_tall_mfma(const double* X, in
           }
       }
       __syncthreads();
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// n > 64: blocked substitution (64-column blocks), no Gram.
-// ---------------------------------------------------------------------------
-template <int NP>
-__global__ __launch_bounds__(TP_THREADS) void k_tall_trsm_big(const double* X, int64_t ldx, int64_t m, int n,
-                                                              const double* __restrict__ Rp, double* W, int64_t ldw,
-                                                              int64_t ntiles, const int32_t* info) {
-  if (info_failed(info)) return;
-  const int tid = threadIdx.x;
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int64_t row = t * TP_THREADS + tid;
-    if (row >= m) continue;
-    for (int cb = 0; cb < NP / 64; ++cb) {
-      const int c0 = cb * 64;
-      if (c0 >= n) break;
-      double acc[64];
-#pragma unroll
-      for (int c = 0; c < 64; ++c) acc[c] = (c0 + c < n) ? X[row + (int64_t)(c0 + c) * ldx] : 0.0;
-      for (int i = 0; i < c0; ++i) {
-        const double wi = W[row + (int64_t)i * ldw];
-        const cdptr ri = opaque_after(Rp + (int64_t)i * NP + c0, wi);
-#pragma unroll
-        for (int c = 0; c < 64; ++c) acc[c] = __builtin_fma(-wi, ri[c], acc[c]);
-      }
-#pragma unroll
-      for (int j = 0; j < 64; ++j) {
-        const cdptr Rj = opaque_after(Rp + (int64_t)(c0 + j) * NP + c0, acc[j >= 2 ? j - 2 : 0]);
-        acc[j] = acc[j] / Rj[j];
-#pragma unroll
-        for (int k = j + 1; k < 64; ++k) acc[k] = __builtin_fma(-acc[j], Rj[k], acc[k]);
-      }
-#pragma unroll
-      for (int c = 0; c < 64; ++c)
-        if (c0 + c < n) W[row + (int64_t)(c0 + c) * ldw] = acc[c];
     }
   }
 }
@@ -437,7 +412,7 @@ TallPlan plan_tall(int64_t m, int64_t n, int gx_hint) {
   TallPlan p{};
   p.np = pad_cols(n);
   p.fused_gram = p.np <= 64;
-  p.tile_rows = p.fused_gram ? TM_TILE : TP_THREADS;
+  p.tile_rows = p.fused_gram ? tm_tile(p.np) : TP_THREADS;
   p.ntiles = (m + p.tile_rows - 1) / p.tile_rows;
   int gx = gx_hint > 0 ? gx_hint : 1024;
   if (gx > p.ntiles) gx = (int)p.ntiles;
@@ -466,11 +441,14 @@ static hipError_t launch_tp(const TallPlan& p, const double* X, int64_t ldx, int
 #undef TP_CASE
     return hipErrorInvalidValue;
   }
-  // n > 64: substitution kernel (if any), then the Gram kernel over W (or X)
+  // n > 64: blocked substitution on the matrix cores (no fused Gram), then
+  // the Gram kernel over W (or X)
   if (trsm) {
     if (!write) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_tall_trsm_big<(NP > 64 ? NP : 128)>), grid, block, 0, st, X, ldx, m, (int)n, Rp, W, ldw,
-                       p.ntiles, info);
+    const int64_t nt = (m + tm_tile(NP) - 1) / tm_tile(NP);
+    dim3 tgrid((unsigned)(p.gx < nt ? p.gx : nt));
+    hipLaunchKernelGGL((k_tall_mfma<(NP > 64 ? NP : 128), true, false, true>), tgrid, block, 0, st, X, ldx, m, (int)n,
+                       Rp, W, ldw, nullptr, nt, info);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   } else if (write) {
