@@ -101,8 +101,20 @@ typedef enum { RCLUPP_PREC_FP64 = 0, RCLUPP_PREC_FP32 = 1, RCLUPP_PREC_BF16 = 2 
 typedef struct {
   int32_t sketch_prec;
   int32_t lu_prec;
-  int32_t reserved[6];
+  int32_t batch_flags; /* rclupp_qr_batched only: RCLUPP_BATCH_* bits       */
+  int32_t reserved[5];
 } rclupp_opts;
+
+/* batch_flags:
+ *   RCLUPP_BATCH_GRAPH: capture the batch's launch sequence into a hipGraph
+ *     on first use (keyed by every argument of the call) and replay it;
+ *   RCLUPP_BATCH_AUTOTUNE: on the first call for a batch shape (n, s and m
+ *     per problem, in 4096-row buckets), time the candidate rows-per-workgroup
+ *     of the tall and sketch passes once (synchronizing the stream) and keep
+ *     the fastest. Results are deterministic for a given choice; two choices
+ *     differ by summation order only. */
+#define RCLUPP_BATCH_GRAPH 1
+#define RCLUPP_BATCH_AUTOTUNE 2
 
 typedef enum {
   RCLUPP_ALG_RCLUPP = 0,   /* Algorithm 2 */
@@ -159,11 +171,19 @@ int rclupp_qr_ex(int alg, const double* X, int64_t m, int64_t n, int64_t ld, int
                  hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
- * Batched form: many independent problems, one graph-captured launch
- * sequence. h_probs is a HOST array of `batch` descriptors whose matrix
- * pointers are device pointers; d_info (device, nullable) receives one
- * rclupp_info per problem. A failure in one problem does not affect the
- * others. The workspace size depends on the whole batch.
+ * Batched form: many independent problems in one call. h_probs is a HOST
+ * array of `batch` descriptors whose matrix pointers are device pointers;
+ * d_info (device, nullable) receives one rclupp_info per problem. A failure
+ * in one problem does not affect the others. The workspace size depends on
+ * the whole batch (rclupp_batched_workspace_size).
+ * RCLUPP batches whose problems fit the register-resident small kernels
+ * (n <= 128, s <= 256) run grouped: problems with equal (n, s) share one
+ * launch per pipeline stage (tall and sketch passes split every problem into
+ * row chunks, one workgroup each; small stages take one workgroup per
+ * problem), optionally graph-captured and autotuned (opts->batch_flags).
+ * Other batches run problem after problem with the single-problem pipeline.
+ * Without RCLUPP_BATCH_GRAPH the call waits for the upload of its job tables
+ * (a short host synchronization of `stream`).
  * ------------------------------------------------------------------------- */
 typedef struct {
   const double* X;

@@ -15,6 +15,7 @@ from .api import (  # noqa: F401
     precond,
     qr,
     qr_batched,
+    Batch,
     qr_simple,
     sketch,
     tall_lu,
@@ -22,5 +23,5 @@ from .api import (  # noqa: F401
     workspace_size,
 )
 
-__all__ = ["qr", "qr_simple", "qr_batched", "workspace_size", "sketch", "omega", "philox", "precond",
+__all__ = ["qr", "qr_simple", "qr_batched", "Batch", "workspace_size", "sketch", "omega", "philox", "precond",
            "trsm_gram", "chol", "tall_lu", "colmajor", "new_colmajor", "QRResult"]

@@ -37,8 +37,13 @@ class Info(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+BATCH_GRAPH = 1
+BATCH_AUTOTUNE = 2
+
+
 class Opts(ctypes.Structure):
-    _fields_ = [("sketch_prec", ctypes.c_int32), ("lu_prec", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+    _fields_ = [("sketch_prec", ctypes.c_int32), ("lu_prec", ctypes.c_int32), ("batch_flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class Problem(ctypes.Structure):

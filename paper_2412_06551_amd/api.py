@@ -140,34 +140,55 @@ def qr_simple(X: torch.Tensor, alg: str = "rclupp", s: Optional[int] = None, see
     return Q, R, [inf.code, inf.stage, inf.index, inf.reserved]
 
 
+class Batch:
+    """A reusable batched QR (rclupp_qr_batched) over fixed input matrices: Q, R,
+    the workspace and the outcome records are allocated once, so repeated run()
+    calls hit the library's captured graph when graph=True."""
+
+    def __init__(self, Xs: Sequence[torch.Tensor], alg: str = "rclupp", s: Optional[Sequence[int]] = None,
+                 seeds: Optional[Sequence[int]] = None, sketch_prec="fp64", lu_prec="fp64", graph: bool = False,
+                 autotune: bool = False):
+        _require_device()
+        b = len(Xs)
+        self.alg = alg
+        self.count = b
+        self.Xs = list(Xs)
+        self.probs = (nat.Problem * max(b, 1))()
+        self.Qs, self.Rs = [], []
+        for i, X in enumerate(Xs):
+            m, n = X.shape
+            ld = _ld(X)
+            si = _default_s(alg, n, m, None if s is None else s[i])
+            Q = new_colmajor(m, n, device=X.device, ld=ld)
+            R = torch.empty((n, n), dtype=torch.float64, device=X.device).t()
+            self.Qs.append(Q)
+            self.Rs.append(R)
+            p = self.probs[i]
+            p.X, p.Q, p.R = X.data_ptr(), Q.data_ptr(), R.data_ptr()
+            p.m, p.n, p.ld, p.s = m, n, ld, si
+            p.seed = i if seeds is None else seeds[i]
+        self.opts = _opts(sketch_prec, lu_prec)
+        self.opts.batch_flags = (nat.BATCH_GRAPH if graph else 0) | (nat.BATCH_AUTOTUNE if autotune else 0)
+        lib = nat.load()
+        nb = ctypes.c_size_t()
+        nat.check(lib.rclupp_batched_workspace_size(nat.ALG[alg], self.probs, b, ctypes.byref(self.opts),
+                                                    ctypes.byref(nb)), "rclupp_batched_workspace_size")
+        self.ws = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device="cuda")
+        self.info = torch.zeros((max(b, 1), 4), dtype=torch.int32, device="cuda")
+
+    def run(self, stream=None):
+        lib = nat.load()
+        nat.check(lib.rclupp_qr_batched(nat.ALG[self.alg], self.probs, self.count, ctypes.byref(self.opts),
+                                        _ptr(self.ws), self.ws.numel(), _ptr(self.info), _stream(stream)),
+                  "rclupp_qr_batched")
+        return self.Qs, self.Rs, self.info[:self.count]
+
+
 def qr_batched(Xs: Sequence[torch.Tensor], alg: str = "rclupp", s: Optional[Sequence[int]] = None,
-               seeds: Optional[Sequence[int]] = None, sketch_prec="fp64", lu_prec="fp64", stream=None):
+               seeds: Optional[Sequence[int]] = None, sketch_prec="fp64", lu_prec="fp64", graph: bool = False,
+               autotune: bool = False, stream=None):
     """Many independent QRs in one call (rclupp_qr_batched). Returns (Qs, Rs, info[batch, 4])."""
-    _require_device()
-    b = len(Xs)
-    probs = (nat.Problem * max(b, 1))()
-    Qs, Rs = [], []
-    for i, X in enumerate(Xs):
-        m, n = X.shape
-        ld = _ld(X)
-        si = _default_s(alg, n, m, None if s is None else s[i])
-        Q = new_colmajor(m, n, device=X.device, ld=ld)
-        R = torch.empty((n, n), dtype=torch.float64, device=X.device).t()
-        Qs.append(Q)
-        Rs.append(R)
-        probs[i].X, probs[i].Q, probs[i].R = X.data_ptr(), Q.data_ptr(), R.data_ptr()
-        probs[i].m, probs[i].n, probs[i].ld, probs[i].s = m, n, ld, si
-        probs[i].seed = i if seeds is None else seeds[i]
-    o = _opts(sketch_prec, lu_prec)
-    lib = nat.load()
-    nb = ctypes.c_size_t()
-    nat.check(lib.rclupp_batched_workspace_size(nat.ALG[alg], probs, b, ctypes.byref(o), ctypes.byref(nb)),
-              "rclupp_batched_workspace_size")
-    ws = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device="cuda")
-    info = torch.zeros((max(b, 1), 4), dtype=torch.int32, device="cuda")
-    nat.check(lib.rclupp_qr_batched(nat.ALG[alg], probs, b, ctypes.byref(o), _ptr(ws), ws.numel(), _ptr(info),
-                                    _stream(stream)), "rclupp_qr_batched")
-    return Qs, Rs, info[:b]
+    return Batch(Xs, alg, s, seeds, sketch_prec, lu_prec, graph, autotune).run(stream)
 
 
 # ---------------------------------------------------------------------- steps

@@ -443,7 +443,423 @@ int rclupp_last_info(hipStream_t stream, rclupp_info* h_info) {
   return RCLUPP_OK;
 }
 
-// ---- batched: one problem after another on the stream (same kernels) ------------
+}  // extern "C"
+
+namespace {
+
+// ---- batched ----------------------------------------------------------------------
+// RCLUPP problems are grouped by (n, s). Every stage of the pipeline is one
+// launch per group over all its problems (workgroup -> (problem, chunk) items;
+// the small stages take one workgroup per problem), so a batch of any size is a
+// fixed, short launch sequence. With RCLUPP_BATCH_GRAPH that sequence is
+// captured once into a hipGraph (keyed by the call's arguments) and replayed;
+// with RCLUPP_BATCH_AUTOTUNE the rows per workgroup of the tall and sketch
+// passes are chosen per batch shape by timing the candidates once. Other
+// methods, and shapes beyond the register-resident small kernels, run one
+// problem after another with the single-problem pipeline.
+constexpr int kTuneTpw[] = {4, 8, 16};  // tall tiles per workgroup (sketch: twice as many)
+constexpr int kDefaultTpw = 8;
+
+struct BatchProbPlan {
+  int b;             // index in the caller's array
+  SketchPlan sk;     // this problem's sketch partition
+  int64_t tiles;     // tall tiles
+  int tall_wg;       // tall workgroups
+  size_t ypart, y, r1, r2, r3, r4, gpart, g, scratch;  // workspace offsets
+};
+struct BatchGroupPlan {
+  int64_t n, s;
+  int np;
+  std::vector<BatchProbPlan> probs;
+};
+struct BatchPlan {
+  std::vector<BatchGroupPlan> groups;
+  size_t table_off = 0, table_bytes = 0, info_off = 0, total = 0;
+  bool grouped = false;
+};
+
+bool batch_groupable(int alg, const rclupp_problem* h, int batch, const rclupp_opts* o) {
+  if (alg != RCLUPP_ALG_RCLUPP || batch <= 0) return false;
+  for (int b = 0; b < batch; ++b)
+    if (!precond_reg_fits(h[b].s, h[b].n)) return false;
+  (void)o;
+  return true;
+}
+
+int64_t tall_tiles(int64_t m, int np) { return (m + (np > 128 ? 64 : 128) - 1) / (np > 128 ? 64 : 128); }
+
+BatchPlan make_batch_plan(const rclupp_problem* h, int batch, const rclupp_opts* o, int tpw) {
+  BatchPlan P;
+  const int prec = o ? o->sketch_prec : 0;
+  std::map<std::pair<int64_t, int64_t>, int> gi;
+  for (int b = 0; b < batch; ++b) {
+    auto key = std::make_pair(h[b].n, h[b].s);
+    auto it = gi.find(key);
+    if (it == gi.end()) {
+      gi[key] = (int)P.groups.size();
+      BatchGroupPlan g;
+      g.n = h[b].n;
+      g.s = h[b].s;
+      g.np = pad_cols(h[b].n);
+      P.groups.push_back(g);
+      it = gi.find(key);
+    }
+    BatchProbPlan pp{};
+    pp.b = b;
+    pp.sk = plan_sketch(h[b].m, h[b].n, h[b].s, prec, 0);
+    int64_t skw = (pp.sk.ntiles + 2 * tpw - 1) / (2 * tpw);
+    if (skw > 1024) skw = 1024;
+    pp.sk.gx = (int)(skw < 1 ? 1 : skw);
+    pp.sk.part_bytes = ((size_t)pp.sk.gx + reduce_splits(pp.sk.gx)) * pp.sk.s_pad * pp.sk.n_pad * sizeof(double);
+    pp.tiles = tall_tiles(h[b].m, P.groups[it->second].np);
+    int64_t tw = (pp.tiles + tpw - 1) / tpw;
+    if (tw > 1024) tw = 1024;
+    pp.tall_wg = (int)(tw < 1 ? 1 : tw);
+    P.groups[it->second].probs.push_back(pp);
+  }
+  // workspace: per-problem regions, then the per-problem info records (when
+  // the caller passes none), then the job tables
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += align_up(bytes);
+    return at;
+  };
+  for (auto& g : P.groups) {
+    const size_t rb = padded_r_doubles(g.np) * sizeof(double);
+    for (auto& pp : g.probs) {
+      pp.ypart = take(pp.sk.part_bytes);
+      pp.y = take((size_t)g.s * g.n * sizeof(double));
+      pp.r1 = take(rb);
+      pp.r2 = take(rb);
+      pp.r3 = take(rb);
+      pp.r4 = take(rb);
+      pp.gpart = take(((size_t)pp.tall_wg + reduce_splits(pp.tall_wg)) * g.np * g.np * sizeof(double));
+      pp.g = take((size_t)g.np * g.np * sizeof(double));
+      pp.scratch = g.n > 64 ? take(precond_reg_scratch_bytes()) : 0;
+    }
+  }
+  P.info_off = take((size_t)batch * sizeof(rclupp_info));
+  // tables (upper bound: every group's arrays, see build_tables)
+  size_t tb = 0;
+  for (auto& g : P.groups) {
+    size_t items = 0, cnt = g.probs.size();
+    for (auto& pp : g.probs) items += 2 * (size_t)pp.sk.gx + 2 * (size_t)pp.tall_wg + 64 * 4;
+    tb += items * sizeof(BatchItem) + cnt * (sizeof(SketchJob) + 3 * sizeof(ReduceJob) + sizeof(PrecondJob) +
+                                             3 * sizeof(TallJob) + 2 * sizeof(CholJob)) + 16 * kAlign;
+  }
+  P.table_bytes = tb;
+  P.table_off = take(tb);
+  P.total = off;
+  P.grouped = true;
+  return P;
+}
+
+// Host image of the job tables of one group, at its offsets in the table area.
+struct GroupTables {
+  size_t sk_jobs, sk_items, ysum_jobs, ysum_items, pc_jobs, t1, t2, t3, t_items, g_jobs, g_items, c1, c2;
+  int n_sk_items, n_ysum_items, n_t_items, n_g_items;
+};
+
+template <typename T>
+size_t put(std::vector<unsigned char>& img, size_t& at, const std::vector<T>& v) {
+  const size_t o = at;
+  const size_t bytes = v.size() * sizeof(T);
+  if (o + bytes > img.size()) img.resize(o + bytes);
+  if (bytes) std::memcpy(img.data() + o, v.data(), bytes);
+  at = align_up(o + bytes);
+  return o;
+}
+
+std::vector<GroupTables> build_tables(const BatchPlan& P, const rclupp_problem* h, char* ws, rclupp_info* infos,
+                                      std::vector<unsigned char>& img) {
+  std::vector<GroupTables> out;
+  size_t at = 0;
+  for (const auto& g : P.groups) {
+    GroupTables T{};
+    std::vector<SketchJob> skj;
+    std::vector<BatchItem> ski, ysi, ti, gii;
+    std::vector<ReduceJob> ysj, gj;
+    std::vector<PrecondJob> pcj;
+    std::vector<TallJob> t1, t2, t3;
+    std::vector<CholJob> c1, c2;
+    const int64_t sz = g.np;
+    for (size_t k = 0; k < g.probs.size(); ++k) {
+      const BatchProbPlan& pp = g.probs[k];
+      const rclupp_problem& p = h[pp.b];
+      int32_t* info = (int32_t*)(infos + pp.b);
+      double* ypart = (double*)(ws + pp.ypart);
+      double* y = (double*)(ws + pp.y);
+      double* r1 = (double*)(ws + pp.r1);
+      double* r2 = (double*)(ws + pp.r2);
+      double* r3 = (double*)(ws + pp.r3);
+      double* r4 = (double*)(ws + pp.r4);
+      double* gpart = (double*)(ws + pp.gpart);
+      double* gm = (double*)(ws + pp.g);
+      double* scr = pp.scratch ? (double*)(ws + pp.scratch) : nullptr;
+      const int pk = (int)k;
+      skj.push_back({p.X, p.m, p.ld, pp.sk.ntiles, p.seed, ypart, info});
+      for (int w = 0; w < pp.sk.gx; ++w) ski.push_back({pk, w, pp.sk.gx, 0});
+      const int ysp = reduce_splits(pp.sk.gx);
+      const int64_t ystride = pp.sk.s_pad * pp.sk.n_pad;
+      ysj.push_back({ypart, ypart + (int64_t)pp.sk.gx * ystride, y, pp.sk.gx, ysp, info});
+      for (int w = 0; w < ysp; ++w) ysi.push_back({pk, w, ysp, 0});
+      pcj.push_back({y, r1, scr, info});
+      t1.push_back({p.X, p.ld, p.m, pp.tiles, r1, p.Q, p.ld, gpart, info});
+      t2.push_back({p.Q, p.ld, p.m, pp.tiles, r2, p.Q, p.ld, gpart, info});
+      t3.push_back({p.Q, p.ld, p.m, pp.tiles, r4, p.Q, p.ld, nullptr, info});
+      for (int w = 0; w < pp.tall_wg; ++w) ti.push_back({pk, w, pp.tall_wg, 0});
+      const int gsp = reduce_splits(pp.tall_wg);
+      gj.push_back({gpart, gpart + (int64_t)pp.tall_wg * sz * sz, gm, pp.tall_wg, gsp, info});
+      for (int w = 0; w < gsp; ++w) gii.push_back({pk, w, gsp, 0});
+      c1.push_back({gm, r2, r3, r1, info, p.m});
+      c2.push_back({gm, r4, p.R, r3, info, p.m});
+    }
+    T.sk_jobs = put(img, at, skj);
+    T.sk_items = put(img, at, ski);
+    T.ysum_jobs = put(img, at, ysj);
+    T.ysum_items = put(img, at, ysi);
+    T.pc_jobs = put(img, at, pcj);
+    T.t1 = put(img, at, t1);
+    T.t2 = put(img, at, t2);
+    T.t3 = put(img, at, t3);
+    T.t_items = put(img, at, ti);
+    T.g_jobs = put(img, at, gj);
+    T.g_items = put(img, at, gii);
+    T.c1 = put(img, at, c1);
+    T.c2 = put(img, at, c2);
+    T.n_sk_items = (int)ski.size();
+    T.n_ysum_items = (int)ysi.size();
+    T.n_t_items = (int)ti.size();
+    T.n_g_items = (int)gii.size();
+    out.push_back(T);
+  }
+  img.resize(at);
+  return out;
+}
+
+__global__ void k_zero_infos(rclupp_info* info, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) info[i] = rclupp_info{0, 0, 0, 0};
+}
+
+// The launch sequence of a grouped batch (tables already in place on `st`).
+int batch_launch(const BatchPlan& P, const std::vector<GroupTables>& GT, char* tab, rclupp_info* infos, int batch,
+                 const rclupp_opts* o, hipStream_t st) {
+  const int sk_prec = o ? o->sketch_prec : 0;
+  const int lu_prec = o ? o->lu_prec : 0;
+  hipLaunchKernelGGL(k_zero_infos, dim3((batch + 255) / 256), dim3(256), 0, st, infos, batch);
+  HIPCHK(hipGetLastError());
+  for (size_t gi = 0; gi < P.groups.size(); ++gi) {
+    const BatchGroupPlan& g = P.groups[gi];
+    const GroupTables& T = GT[gi];
+    const int cnt = (int)g.probs.size();
+    const SketchPlan& shape = g.probs[0].sk;
+    const int64_t ystride = shape.s_pad * shape.n_pad, gstride = (int64_t)g.np * g.np;
+    auto J = [&](size_t off) { return (void*)(tab + off); };
+    HIPCHK(launch_sketch_batch(shape, g.n, sk_prec, (const SketchJob*)J(T.sk_jobs), (const BatchItem*)J(T.sk_items),
+                               T.n_sk_items, st));
+    HIPCHK(launch_partial_sum_batch(ystride, (const ReduceJob*)J(T.ysum_jobs), (const BatchItem*)J(T.ysum_items),
+                                    T.n_ysum_items, st));
+    HIPCHK(launch_sketch_final_batch(shape, g.s, g.n, 1.0 / std::sqrt((double)g.s), (const ReduceJob*)J(T.ysum_jobs),
+                                     cnt, st));
+    HIPCHK(launch_precond_batch(g.s, g.n, lu_prec, (const PrecondJob*)J(T.pc_jobs), cnt, RCLUPP_STAGE_QR, st));
+    const BatchItem* ti = (const BatchItem*)J(T.t_items);
+    const ReduceJob* gj = (const ReduceJob*)J(T.g_jobs);
+    const BatchItem* gii = (const BatchItem*)J(T.g_items);
+    HIPCHK(launch_tall_batch(g.np, (int)g.n, true, true, true, (const TallJob*)J(T.t1), ti, T.n_t_items, st));
+    HIPCHK(launch_partial_sum_batch(gstride, gj, gii, T.n_g_items, st));
+    HIPCHK(launch_gram_final_batch(g.np, g.n, gj, cnt, st));
+    HIPCHK(launch_chol_batch(g.n, g.np, 0, (const CholJob*)J(T.c1), cnt, RCLUPP_STAGE_CHOL_A, st));
+    HIPCHK(launch_tall_batch(g.np, (int)g.n, true, true, true, (const TallJob*)J(T.t2), ti, T.n_t_items, st));
+    HIPCHK(launch_partial_sum_batch(gstride, gj, gii, T.n_g_items, st));
+    HIPCHK(launch_gram_final_batch(g.np, g.n, gj, cnt, st));
+    HIPCHK(launch_chol_batch(g.n, g.np, 1, (const CholJob*)J(T.c2), cnt, RCLUPP_STAGE_CHOL_B, st));
+    HIPCHK(launch_tall_batch(g.np, (int)g.n, true, false, true, (const TallJob*)J(T.t3), ti, T.n_t_items, st));
+  }
+  return RCLUPP_OK;
+}
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+  const unsigned char* c = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= c[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  void* host_tables = nullptr;  // pinned image the captured copy reads on every replay
+};
+std::mutex g_batch_mu;
+std::map<uint64_t, GraphEntry> g_graphs;
+std::map<uint64_t, int> g_tuned;  // batch shape -> tall tiles per workgroup
+std::map<int, hipStream_t> g_capture_stream;
+
+uint64_t shape_key(const rclupp_problem* h, int batch, const rclupp_opts* o) {
+  uint64_t k = 1469598103934665603ull;
+  for (int b = 0; b < batch; ++b) {
+    const int64_t v[3] = {h[b].n, h[b].s, (h[b].m + 4095) / 4096};
+    k = fnv1a(k, v, sizeof(v));
+  }
+  const int32_t pr[2] = {o ? o->sketch_prec : 0, o ? o->lu_prec : 0};
+  return fnv1a(k, pr, sizeof(pr));
+}
+
+// Host side of a grouped run: the job tables and their pinned image (the
+// upload's source, which must outlive the copy; a captured graph re-reads it
+// on every replay).
+struct BatchPrep {
+  std::vector<GroupTables> gt;
+  void* pinned = nullptr;
+  size_t bytes = 0;
+};
+
+int batch_prepare(const BatchPlan& P, const rclupp_problem* h, char* ws, rclupp_info* infos, BatchPrep* out) {
+  std::vector<unsigned char> img;
+  out->gt = build_tables(P, h, ws, infos, img);
+  if (img.size() > P.table_bytes) return RCLUPP_ERR_WORKSPACE;
+  out->bytes = img.size() ? img.size() : 1;
+  if (hipHostMalloc(&out->pinned, out->bytes, hipHostMallocDefault) != hipSuccess) return RCLUPP_ERR_ALLOC;
+  if (!img.empty()) std::memcpy(out->pinned, img.data(), img.size());
+  return RCLUPP_OK;
+}
+
+// Stream part of a grouped run: the table upload, then the launch sequence.
+int batch_enqueue(const BatchPlan& P, const BatchPrep& prep, int batch, const rclupp_opts* o, char* ws,
+                  rclupp_info* infos, hipStream_t st, hipEvent_t copied) {
+  if (hipMemcpyAsync(ws + P.table_off, prep.pinned, prep.bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+    return RCLUPP_ERR_HIP;
+  if (copied && hipEventRecord(copied, st) != hipSuccess) return RCLUPP_ERR_HIP;
+  return batch_launch(P, prep.gt, ws + P.table_off, infos, batch, o, st);
+}
+
+int batched_grouped(int alg, const rclupp_problem* h, int batch, const rclupp_opts* o, void* ws_v, size_t ws_bytes,
+                    rclupp_info* d_info, hipStream_t stream) {
+  (void)alg;
+  char* ws = (char*)ws_v;
+  const int flags = o ? o->batch_flags : 0;
+  int tpw = kDefaultTpw;
+  const uint64_t skey = shape_key(h, batch, o);
+  if (flags & RCLUPP_BATCH_AUTOTUNE) {
+    std::unique_lock<std::mutex> lk(g_batch_mu);
+    auto it = g_tuned.find(skey);
+    if (it != g_tuned.end()) {
+      tpw = it->second;
+    } else {
+      lk.unlock();
+      // time every candidate once (each run is a complete batch) and keep the fastest
+      float best = 0.f;
+      int best_tpw = kDefaultTpw;
+      hipEvent_t e0, e1;
+      if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return RCLUPP_ERR_HIP;
+      for (int cand : kTuneTpw) {
+        BatchPlan P = make_batch_plan(h, batch, o, cand);
+        if (P.total > ws_bytes) continue;
+        rclupp_info* infos = d_info ? d_info : (rclupp_info*)(ws + P.info_off);
+        BatchPrep prep;
+        int rc = batch_prepare(P, h, ws, infos, &prep);
+        if (rc == RCLUPP_OK) {
+          (void)hipEventRecord(e0, stream);
+          rc = batch_enqueue(P, prep, batch, o, ws, infos, stream, nullptr);
+          (void)hipEventRecord(e1, stream);
+          (void)hipEventSynchronize(e1);
+        }
+        if (prep.pinned) (void)hipHostFree(prep.pinned);
+        if (rc) return rc;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (best == 0.f || ms < best) {
+          best = ms;
+          best_tpw = cand;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      tpw = best_tpw;
+      std::lock_guard<std::mutex> lk2(g_batch_mu);
+      g_tuned[skey] = tpw;
+    }
+  }
+  BatchPlan P = make_batch_plan(h, batch, o, tpw);
+  if (P.total > ws_bytes) return RCLUPP_ERR_WORKSPACE;
+  rclupp_info* infos = d_info ? d_info : (rclupp_info*)(ws + P.info_off);
+  if (!(flags & RCLUPP_BATCH_GRAPH)) {
+    BatchPrep prep;
+    int rc = batch_prepare(P, h, ws, infos, &prep);
+    if (rc == RCLUPP_OK) {
+      hipEvent_t copied;
+      if (hipEventCreateWithFlags(&copied, hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(prep.pinned);
+        return RCLUPP_ERR_HIP;
+      }
+      rc = batch_enqueue(P, prep, batch, o, ws, infos, stream, copied);
+      // the table upload must finish before its pinned source goes away
+      (void)hipEventSynchronize(copied);
+      (void)hipEventDestroy(copied);
+    }
+    if (prep.pinned) (void)hipHostFree(prep.pinned);
+    return rc;
+  }
+  // graph: key = every argument that the captured sequence depends on
+  uint64_t key = fnv1a(skey, h, sizeof(rclupp_problem) * (size_t)batch);
+  const void* ptrs[3] = {ws_v, (const void*)d_info, nullptr};
+  key = fnv1a(key, ptrs, sizeof(ptrs));
+  key = fnv1a(key, &tpw, sizeof(tpw));
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  auto it = g_graphs.find(key);
+  if (it == g_graphs.end()) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return RCLUPP_ERR_HIP;
+    hipStream_t cs = g_capture_stream[dev];
+    if (!cs) {
+      if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return RCLUPP_ERR_HIP;
+      g_capture_stream[dev] = cs;
+    }
+    BatchPrep prep;
+    int rc = batch_prepare(P, h, ws, infos, &prep);
+    if (rc) {
+      if (prep.pinned) (void)hipHostFree(prep.pinned);
+      return rc;
+    }
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipHostFree(prep.pinned);
+      return RCLUPP_ERR_HIP;
+    }
+    rc = batch_enqueue(P, prep, batch, o, ws, infos, cs, nullptr);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    if (rc || ec != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipHostFree(prep.pinned);
+      return rc ? rc : RCLUPP_ERR_HIP;
+    }
+    GraphEntry e;
+    e.host_tables = prep.pinned;
+    void* keep = prep.pinned;
+    const hipError_t ei = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      (void)hipHostFree(keep);
+      return RCLUPP_ERR_HIP;
+    }
+    if (g_graphs.size() >= 16) {  // bounded cache: drop the oldest key
+      auto old = g_graphs.begin();
+      (void)hipGraphExecDestroy(old->second.exec);
+      (void)hipHostFree(old->second.host_tables);
+      g_graphs.erase(old);
+    }
+    it = g_graphs.emplace(key, e).first;
+  }
+  return hipGraphLaunch(it->second.exec, stream) == hipSuccess ? RCLUPP_OK : RCLUPP_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
 int rclupp_batched_workspace_size(int alg, const rclupp_problem* h_probs, int batch, const rclupp_opts* opts,
                                   size_t* bytes) {
   if (!bytes || batch < 0 || (batch > 0 && !h_probs)) return RCLUPP_ERR_INVALID_ARG;
@@ -452,8 +868,16 @@ int rclupp_batched_workspace_size(int alg, const rclupp_problem* h_probs, int ba
     const rclupp_problem& p = h_probs[b];
     int rc = validate(alg, p.m, p.n, p.ld, p.s, opts);
     if (rc) return rc;
+    if (!p.X || !p.Q || !p.R) return RCLUPP_ERR_INVALID_ARG;
     const size_t t = make_layout(alg, p.m, p.n, p.s, opts).total;
     if (t > mx) mx = t;
+  }
+  if (batch_groupable(alg, h_probs, batch, opts)) {
+    // the largest plan among the tuning candidates (fewest rows per workgroup)
+    for (int cand : kTuneTpw) {
+      const size_t t = make_batch_plan(h_probs, batch, opts, cand).total;
+      if (t > mx) mx = t;
+    }
   }
   *bytes = mx > 0 ? mx : kAlign;
   return RCLUPP_OK;
@@ -466,6 +890,8 @@ int rclupp_qr_batched(int alg, const rclupp_problem* h_probs, int batch, const r
   if (rc) return rc;
   if (!ws) return RCLUPP_ERR_INVALID_ARG;
   if (ws_bytes < need) return RCLUPP_ERR_WORKSPACE;
+  if (batch_groupable(alg, h_probs, batch, opts))
+    return batched_grouped(alg, h_probs, batch, opts, ws, ws_bytes, d_info, stream);
   for (int b = 0; b < batch; ++b) {
     const rclupp_problem& p = h_probs[b];
     rc = rclupp_qr_ex(alg, p.X, p.m, p.n, p.ld, p.s, p.seed, p.Q, p.R, opts, ws, ws_bytes,

@@ -123,7 +123,12 @@ template <typename T, int A, int CS>
 __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __restrict__ Y, int s, int n, int lu,
                                                             const double* __restrict__ Nin, int ldn, double* R1pad,
                                                             int np, double* R1out, int32_t* perm_out, double* Mout,
-                                                            double* gtab, int32_t* info, int32_t stage_qr) {
+                                                            double* gtab, int32_t* info, int32_t stage_qr,
+                                                            const PrecondJob* __restrict__ jobs) {
+  if (jobs) {  // batched: one workgroup per problem
+    const PrecondJob j = jobs[blockIdx.x];
+    Y = j.Y, R1pad = j.R1pad, gtab = j.scratch, info = j.info;
+  }
   constexpr int SR = 16 * A, LD = dn_ld<CS>(), NT = 64 * CS;
   extern __shared__ __align__(16) unsigned char dn_smem[];
   double* R0l = (CS == 1) ? (double*)dn_smem : gtab;  // R_0(i, j) at i*LD + j
@@ -411,7 +416,11 @@ __global__ __launch_bounds__(DN_THREADS) void k_chol_reg(const double* __restric
                                                          int shift_mode, double* Rpad, int np, double* Rout,
                                                          int rout_user, const double* __restrict__ Rprev,
                                                          const double* __restrict__ Npost, int ldnp, int32_t* info,
-                                                         int32_t stage) {
+                                                         int32_t stage, const CholJob* __restrict__ jobs) {
+  if (jobs) {  // batched: one workgroup per problem
+    const CholJob j = jobs[blockIdx.x];
+    G = j.G, Rpad = j.Rpad, Rout = j.Rout, Rprev = j.Rprev, info = j.info, m = j.m;
+  }
   constexpr int LD = dn_ld<CS>(), NT = 64 * CS, A = 4 * CS;
   extern __shared__ __align__(16) unsigned char dn_smem[];
   double* Rl = (double*)dn_smem;  // R(i, j) at i*LD + j
@@ -592,8 +601,43 @@ static hipError_t launch_pr(const double* Y, int64_t s, int64_t n, int lu, const
   hipError_t e = set_lds(k_precond_reg<T, A, CS>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_precond_reg<T, A, CS>), dim3(1), dim3(DN_THREADS), lds, st, Y, (int)s, (int)n, lu, Nin,
-                     (int)ldn, R1pad, pad_cols(n), R1out, perm, Mout, scratch, info, stage_qr);
+                     (int)ldn, R1pad, pad_cols(n), R1out, perm, Mout, scratch, info, stage_qr, nullptr);
   return hipGetLastError();
+}
+
+template <typename T, int A, int CS>
+static hipError_t launch_pr_batch(int64_t s, int64_t n, const PrecondJob* jobs, int count, int32_t stage_qr,
+                                  hipStream_t st) {
+  constexpr size_t lds = precond_reg_lds<T, A, CS>();
+  hipError_t e = set_lds(k_precond_reg<T, A, CS>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_precond_reg<T, A, CS>), dim3((unsigned)count), dim3(DN_THREADS), lds, st, nullptr, (int)s,
+                     (int)n, 1, nullptr, 0, nullptr, pad_cols(n), nullptr, nullptr, nullptr, nullptr, nullptr,
+                     stage_qr, jobs);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_pr_batch_t(int64_t s, int64_t n, const PrecondJob* jobs, int count, int32_t stage_qr,
+                                    hipStream_t st) {
+  if (n > 64) {
+    if (s <= 128) return launch_pr_batch<T, 8, 2>(s, n, jobs, count, stage_qr, st);
+    return launch_pr_batch<T, 16, 2>(s, n, jobs, count, stage_qr, st);
+  }
+  if (s <= 16) return launch_pr_batch<T, 1, 1>(s, n, jobs, count, stage_qr, st);
+  if (s <= 32) return launch_pr_batch<T, 2, 1>(s, n, jobs, count, stage_qr, st);
+  if (s <= 64) return launch_pr_batch<T, 4, 1>(s, n, jobs, count, stage_qr, st);
+  if (s <= 128) return launch_pr_batch<T, 8, 1>(s, n, jobs, count, stage_qr, st);
+  return launch_pr_batch<T, 16, 1>(s, n, jobs, count, stage_qr, st);
+}
+
+// Batched LU + Householder preconditioner (RCLUPP), one workgroup per problem.
+hipError_t launch_precond_batch(int64_t s, int64_t n, int prec, const PrecondJob* jobs, int count, int32_t stage_qr,
+                                hipStream_t st) {
+  if (!precond_reg_fits(s, n)) return hipErrorInvalidValue;
+  if (count <= 0) return hipSuccess;
+  if (prec == 1) return launch_pr_batch_t<float>(s, n, jobs, count, stage_qr, st);
+  return launch_pr_batch_t<double>(s, n, jobs, count, stage_qr, st);
 }
 
 template <typename T>
@@ -630,14 +674,33 @@ hipError_t launch_chol_reg(const double* G, int ldg, int64_t n, int64_t m, int s
   if (n <= 64) {
     constexpr size_t lds = chol_reg_lds<1>();
     hipLaunchKernelGGL(k_chol_reg<1>, dim3(1), dim3(DN_THREADS), lds, st, G, ldg, (int)n, m, shift_mode, Rpad,
-                       pad_cols(n), Rout, rout_user, Rprev, Npost, (int)ldnp, info, stage);
+                       pad_cols(n), Rout, rout_user, Rprev, Npost, (int)ldnp, info, stage, nullptr);
     return hipGetLastError();
   }
   constexpr size_t lds = chol_reg_lds<2>();
   hipError_t e = set_lds(k_chol_reg<2>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_chol_reg<2>, dim3(1), dim3(DN_THREADS), lds, st, G, ldg, (int)n, m, shift_mode, Rpad,
-                     pad_cols(n), Rout, rout_user, Rprev, Npost, (int)ldnp, info, stage);
+                     pad_cols(n), Rout, rout_user, Rprev, Npost, (int)ldnp, info, stage, nullptr);
+  return hipGetLastError();
+}
+
+// Batched Cholesky (+ product with an earlier factor), one workgroup per problem.
+hipError_t launch_chol_batch(int64_t n, int ldg, int rout_user, const CholJob* jobs, int count, int32_t stage,
+                             hipStream_t st) {
+  if (n < 1 || n > DN_NP) return hipErrorInvalidValue;
+  if (count <= 0) return hipSuccess;
+  if (n <= 64) {
+    constexpr size_t lds = chol_reg_lds<1>();
+    hipLaunchKernelGGL(k_chol_reg<1>, dim3((unsigned)count), dim3(DN_THREADS), lds, st, nullptr, ldg, (int)n, 0, 0,
+                       nullptr, pad_cols(n), nullptr, rout_user, nullptr, nullptr, 0, nullptr, stage, jobs);
+    return hipGetLastError();
+  }
+  constexpr size_t lds = chol_reg_lds<2>();
+  hipError_t e = set_lds(k_chol_reg<2>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_chol_reg<2>, dim3((unsigned)count), dim3(DN_THREADS), lds, st, nullptr, ldg, (int)n, 0, 0,
+                     nullptr, pad_cols(n), nullptr, rout_user, nullptr, nullptr, 0, nullptr, stage, jobs);
   return hipGetLastError();
 }
 

@@ -34,7 +34,16 @@ struct SketchLds {
 template <int SM, int NN>
 __global__ __launch_bounds__(SK_THREADS) void k_sketch_f64(const double* __restrict__ X, int64_t m, int n, int64_t ld,
                                                            int64_t ntiles, uint64_t seed, double* __restrict__ Ypart,
-                                                           int64_t s_pad, int64_t n_pad, const int32_t* info) {
+                                                           int64_t s_pad, int64_t n_pad, const int32_t* info,
+                                                           const SketchJob* __restrict__ jobs,
+                                                           const BatchItem* __restrict__ items) {
+  int64_t wg = blockIdx.x, nwg = gridDim.x;
+  if (items) {  // batched launch: this workgroup's problem and its place in it
+    const BatchItem it = items[blockIdx.x];
+    const SketchJob j = jobs[it.prob];
+    X = j.X, m = j.m, ld = j.ld, ntiles = j.ntiles, seed = j.seed, Ypart = j.Ypart, info = j.info;
+    wg = it.wg, nwg = it.nwg;
+  }
   if (info_failed(info)) return;
   constexpr int MB = SM / 16, NB = NN / 16, LDX = SketchLds<SM, NN>::LDX, TILE = SketchLds<SM, NN>::TILE;
   constexpr int CPT = NN / 4;  // tile columns loaded per thread
@@ -68,15 +77,15 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch_f64(const double* __restr
   const int ai = lane & 15, ak = lane >> 4;
   const uint32_t qbase = (uint32_t)((sg * SM) / 4 + 4 * (ai >> 2) + (ai & 3));
 
-  int64_t t = blockIdx.x;
+  int64_t t = wg;
   int buf = 0;
   if (t < ntiles) {
     load_tile(t);
     store_tile(0);
   }
   __syncthreads();
-  for (; t < ntiles; t += gridDim.x) {
-    const int64_t tn = t + gridDim.x;
+  for (; t < ntiles; t += nwg) {
+    const int64_t tn = t + nwg;
     if (tn < ntiles) load_tile(tn);
     const double* xs = lds + buf * TILE;
 #pragma unroll 1
@@ -121,7 +130,7 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch_f64(const double* __restr
               // slot row l/16 + 4r of M-block a -> sketch row
               const int64_t srow = (int64_t)sg * SM + 64 * (a >> 2) + 16 * r + 4 * (lane >> 4) + (a & 3);
               const int64_t col = col0 + 16 * nb + (lane & 15);
-              Ypart[(int64_t)blockIdx.x * s_pad * n_pad + srow + col * s_pad] = v;
+              Ypart[wg * s_pad * n_pad + srow + col * s_pad] = v;
             }
           }
     }
@@ -161,7 +170,16 @@ struct SketchLpLds {
 template <int SM, int NN, bool BF>
 __global__ __launch_bounds__(SK_THREADS) void k_sketch_lp(const double* __restrict__ X, int64_t m, int n, int64_t ld,
                                                           int64_t ntiles, uint64_t seed, double* __restrict__ Ypart,
-                                                          int64_t s_pad, int64_t n_pad, const int32_t* info) {
+                                                          int64_t s_pad, int64_t n_pad, const int32_t* info,
+                                                          const SketchJob* __restrict__ jobs,
+                                                          const BatchItem* __restrict__ items) {
+  int64_t wg = blockIdx.x, nwg = gridDim.x;
+  if (items) {  // batched launch: this workgroup's problem and its place in it
+    const BatchItem it = items[blockIdx.x];
+    const SketchJob j = jobs[it.prob];
+    X = j.X, m = j.m, ld = j.ld, ntiles = j.ntiles, seed = j.seed, Ypart = j.Ypart, info = j.info;
+    wg = it.wg, nwg = it.nwg;
+  }
   if (info_failed(info)) return;
   using L = SketchLpLds<SM, NN, BF>;
   constexpr int MB = SM / 16, NB = NN / 16, TK = L::TK, LD = L::LD;
@@ -215,15 +233,15 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch_lp(const double* __restri
   const int ai = lane & 15, ag = lane >> 4;
   const uint32_t qbase = (uint32_t)((sg * SM) / 4 + 4 * (ai >> 2) + (ai & 3));
 
-  int64_t t = blockIdx.x;
+  int64_t t = wg;
   int buf = 0;
   if (t < ntiles) {
     load_tile(t);
     store_tile(0);
   }
   __syncthreads();
-  for (; t < ntiles; t += gridDim.x) {
-    const int64_t tn = t + gridDim.x;
+  for (; t < ntiles; t += nwg) {
+    const int64_t tn = t + nwg;
     if (tn < ntiles) load_tile(tn);
     if constexpr (BF) {
       const unsigned short* xs = (const unsigned short*)(lds_raw + buf * L::TILE_BYTES);
@@ -302,7 +320,7 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch_lp(const double* __restri
               const int slot = 4 * (lane >> 4) + r;
               const int64_t srow = (int64_t)sg * SM + 64 * (a >> 2) + 16 * (slot >> 2) + 4 * (slot & 3) + (a & 3);
               const int64_t col = col0 + 16 * nb + (lane & 15);
-              Ypart[(int64_t)blockIdx.x * s_pad * n_pad + srow + col * s_pad] = v;
+              Ypart[wg * s_pad * n_pad + srow + col * s_pad] = v;
             }
           }
     }
@@ -313,7 +331,12 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch_lp(const double* __restri
 // Y[i + j*s] = scale * sum_y lvl[y][i + j*s_pad] (the level-1 sums of the
 // per-workgroup partials, added in split order).
 __global__ void k_sketch_final(const double* __restrict__ lvl, int splits, int64_t s, int64_t n, int64_t s_pad,
-                               int64_t n_pad, double scale, double* __restrict__ Y, const int32_t* info) {
+                               int64_t n_pad, double scale, double* __restrict__ Y, const int32_t* info,
+                               const ReduceJob* __restrict__ jobs) {
+  if (jobs) {  // batched: blockIdx.y = problem
+    const ReduceJob j = jobs[blockIdx.y];
+    lvl = j.lvl, splits = j.splits, Y = j.out, info = j.info;
+  }
   if (info_failed(info)) return;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= s * n) return;
@@ -383,26 +406,28 @@ SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int gx_hint) {
 
 template <int SM, int NN>
 static hipError_t launch_sk(const SketchPlan& p, const double* X, int64_t m, int64_t n, int64_t ld, uint64_t seed,
-                            int prec, double* Ypart, const int32_t* info, hipStream_t st) {
-  dim3 grid(p.gx, p.gy, p.gz);
+                            int prec, double* Ypart, const int32_t* info, const SketchJob* jobs,
+                            const BatchItem* items, int nitems, hipStream_t st) {
+  dim3 grid(items ? (unsigned)nitems : (unsigned)p.gx, p.gy, p.gz);
   if (prec == 0)
     hipLaunchKernelGGL((k_sketch_f64<SM, NN>), grid, dim3(SK_THREADS), 0, st, X, m, (int)n, ld, p.ntiles, seed, Ypart,
-                       p.s_pad, p.n_pad, info);
+                       p.s_pad, p.n_pad, info, jobs, items);
   else if (prec == 1)
     hipLaunchKernelGGL((k_sketch_lp<SM, NN, false>), grid, dim3(SK_THREADS), 0, st, X, m, (int)n, ld, p.ntiles, seed,
-                       Ypart, p.s_pad, p.n_pad, info);
+                       Ypart, p.s_pad, p.n_pad, info, jobs, items);
   else
     hipLaunchKernelGGL((k_sketch_lp<SM, NN, true>), grid, dim3(SK_THREADS), 0, st, X, m, (int)n, ld, p.ntiles, seed,
-                       Ypart, p.s_pad, p.n_pad, info);
+                       Ypart, p.s_pad, p.n_pad, info, jobs, items);
   return hipGetLastError();
 }
 
-hipError_t launch_sketch_partials(const SketchPlan& p, const double* X, int64_t m, int64_t n, int64_t ld, uint64_t seed,
-                                  int prec, double* Ypart, const int32_t* info, hipStream_t st) {
+static hipError_t sketch_dispatch(const SketchPlan& p, const double* X, int64_t m, int64_t n, int64_t ld,
+                                  uint64_t seed, int prec, double* Ypart, const int32_t* info, const SketchJob* jobs,
+                                  const BatchItem* items, int nitems, hipStream_t st) {
   if (prec < 0 || prec > 2) return hipErrorInvalidValue;
-  if (p.gx < 1 || p.ntiles < 1) return hipErrorInvalidValue;
-#define SK_CASE(SMV, NNV) \
-  if (p.sm == SMV && p.nn == NNV) return launch_sk<SMV, NNV>(p, X, m, n, ld, seed, prec, Ypart, info, st);
+#define SK_CASE(SMV, NNV)        \
+  if (p.sm == SMV && p.nn == NNV) \
+    return launch_sk<SMV, NNV>(p, X, m, n, ld, seed, prec, Ypart, info, jobs, items, nitems, st);
   SK_CASE(64, 16)
   SK_CASE(128, 16)
   SK_CASE(256, 16)
@@ -416,6 +441,30 @@ hipError_t launch_sketch_partials(const SketchPlan& p, const double* X, int64_t 
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_sketch_partials(const SketchPlan& p, const double* X, int64_t m, int64_t n, int64_t ld, uint64_t seed,
+                                  int prec, double* Ypart, const int32_t* info, hipStream_t st) {
+  if (p.gx < 1 || p.ntiles < 1) return hipErrorInvalidValue;
+  return sketch_dispatch(p, X, m, n, ld, seed, prec, Ypart, info, nullptr, nullptr, 0, st);
+}
+
+// Batched: `p` supplies the shape (sm, nn, gy, gz, s_pad, n_pad) shared by the
+// problems; items/jobs the per-problem row chunks.
+hipError_t launch_sketch_batch(const SketchPlan& p, int64_t n, int prec, const SketchJob* jobs, const BatchItem* items,
+                               int nitems, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  return sketch_dispatch(p, nullptr, 0, n, 0, 0, prec, nullptr, nullptr, jobs, items, nitems, st);
+}
+
+hipError_t launch_sketch_final_batch(const SketchPlan& p, int64_t s, int64_t n, double scale, const ReduceJob* jobs,
+                                     int count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int threads = 256;
+  dim3 grid((unsigned)((s * n + threads - 1) / threads), (unsigned)count);
+  hipLaunchKernelGGL(k_sketch_final, grid, dim3(threads), 0, st, nullptr, 1, s, n, p.s_pad, p.n_pad, scale, nullptr,
+                     nullptr, jobs);
+  return hipGetLastError();
+}
+
 hipError_t launch_sketch_reduce(const SketchPlan& p, const double* Ypart, int64_t s, int64_t n, double scale, double* Y,
                                 const int32_t* info, hipStream_t st) {
   const int64_t stride = p.s_pad * p.n_pad;
@@ -427,7 +476,7 @@ hipError_t launch_sketch_reduce(const SketchPlan& p, const double* Ypart, int64_
   const int threads = 256;
   const int64_t blocks = (total + threads - 1) / threads;
   hipLaunchKernelGGL(k_sketch_final, dim3((unsigned)blocks), dim3(threads), 0, st, lvl, splits, s, n, p.s_pad,
-                     p.n_pad, scale, Y, info);
+                     p.n_pad, scale, Y, info, nullptr);
   return hipGetLastError();
 }
 

@@ -81,7 +81,15 @@ template <int NP, bool TRSM, bool GRAM, bool WRITE>
 __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(const double* X, int64_t ldx, int64_t m, int n,
                                                             const double* __restrict__ Rp, double* W, int64_t ldw,
                                                             double* __restrict__ Gpart, int64_t ntiles,
-                                                            const int32_t* info) {
+                                                            const int32_t* info, const TallJob* __restrict__ jobs,
+                                                            const BatchItem* __restrict__ items) {
+  int64_t wg = blockIdx.x, nwg = gridDim.x;
+  if (items) {  // batched launch: this workgroup's problem and its place in it
+    const BatchItem it = items[blockIdx.x];
+    const TallJob j = jobs[it.prob];
+    X = j.X, ldx = j.ldx, m = j.m, ntiles = j.ntiles, Rp = j.Rp, W = j.W, ldw = j.ldw, Gpart = j.Gpart;
+    info = j.info, wg = it.wg, nwg = it.nwg;
+  }
   if (info_failed(info)) return;
   constexpr int NB = NP / 16;                  // column blocks
   constexpr int NOFF = NB * (NB - 1) / 2;      // off-diagonal block pairs c < b
@@ -129,7 +137,7 @@ __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(co
   for (int g = 0; g < (GRAM ? NBLK : 1); ++g) gacc[g] = f64x4{0.0, 0.0, 0.0, 0.0};
   double* ws = gst + wave * NP * TM_LDG;
 
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  for (int64_t t = wg; t < ntiles; t += nwg) {
     const int64_t row0 = t * tm_tile(NP) + wave * RW;
     f64x4 acc[HB][NB];
     // addresses: a wave-uniform column base (scalar) plus a 32-bit per-lane offset
@@ -280,7 +288,7 @@ __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(co
                 red[idx] = v;
               } else {
                 const int gi = 16 * ib + lq + 4 * r, gj = 16 * jb + lr;
-                Gpart[(int64_t)blockIdx.x * NP * NP + gi + gj * NP] = v;
+                Gpart[wg * NP * NP + gi + gj * NP] = v;
               }
             }
             ++g;
@@ -300,7 +308,15 @@ __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(co
 template <int NP>
 __global__ __launch_bounds__(TP_THREADS) void k_gram_big(const double* __restrict__ W, int64_t ldw, int64_t m, int n,
                                                          double* __restrict__ Gpart, int64_t ntiles32,
-                                                         const int32_t* info) {
+                                                         const int32_t* info, const TallJob* __restrict__ jobs,
+                                                         const BatchItem* __restrict__ items) {
+  int64_t wg = blockIdx.x, nwg = gridDim.x;
+  if (items) {  // batched: the Gram of the job's W (its X when it has no solve)
+    const BatchItem it = items[blockIdx.x];
+    const TallJob j = jobs[it.prob];
+    W = j.W ? j.W : j.X, ldw = j.W ? j.ldw : j.ldx, m = j.m, ntiles32 = (j.m + 31) / 32, Gpart = j.Gpart;
+    info = j.info, wg = it.wg, nwg = it.nwg;
+  }
   if (info_failed(info)) return;
   constexpr int NBK = NP / 16;
   constexpr int JPW = 2;
@@ -312,7 +328,7 @@ __global__ __launch_bounds__(TP_THREADS) void k_gram_big(const double* __restric
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-  for (int64_t t = blockIdx.x; t < ntiles32; t += gridDim.x) {
+  for (int64_t t = wg; t < ntiles32; t += nwg) {
     // load 32 rows x NP columns: thread -> row (tid % 32), columns tid/32 + 8 k
     const int lr = tid & 31, lc = tid >> 5;
     const int64_t row = t * 32 + lr;
@@ -350,7 +366,7 @@ __global__ __launch_bounds__(TP_THREADS) void k_gram_big(const double* __restric
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gi = 16 * ib + (lane >> 4) + 4 * r, gj = 16 * jb + (lane & 15);
-        Gpart[(int64_t)blockIdx.x * NP * NP + gi + gj * NP] = acc[jj * NBK + ib][r];
+        Gpart[wg * NP * NP + gi + gj * NP] = acc[jj * NBK + ib][r];
       }
     }
   }
@@ -360,11 +376,17 @@ __global__ __launch_bounds__(TP_THREADS) void k_gram_big(const double* __restric
 // part[b][e] over the contiguous chunk of workgroups b assigned to split y
 // (in b order). Consecutive threads read consecutive e (coalesced).
 __global__ void k_partial_sum(const double* __restrict__ part, int nparts, int64_t stride, int splits,
-                              double* __restrict__ lvl, const int32_t* info) {
+                              double* __restrict__ lvl, const int32_t* info, const ReduceJob* __restrict__ jobs,
+                              const BatchItem* __restrict__ items) {
+  int y = blockIdx.y;
+  if (items) {  // batched: item = (problem, split index, splits of that problem)
+    const BatchItem it = items[blockIdx.y];
+    const ReduceJob j = jobs[it.prob];
+    part = j.part, nparts = j.nparts, splits = j.splits, lvl = j.lvl, info = j.info, y = it.wg;
+  }
   if (info_failed(info)) return;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= stride) return;
-  const int y = blockIdx.y;
   const int per = (nparts + splits - 1) / splits;
   const int b0 = y * per, b1 = (b0 + per < nparts) ? b0 + per : nparts;
   double acc = 0.0;
@@ -375,7 +397,11 @@ __global__ void k_partial_sum(const double* __restrict__ part, int nparts, int64
 // G[i + j*np] = sum_y lvl[y][i + j*np] for i <= j (mirrored), padded with the
 // identity beyond n (so a padded Cholesky stays the identity there).
 __global__ void k_gram_final(const double* __restrict__ lvl, int splits, int np, int64_t n, double* __restrict__ G,
-                             const int32_t* info) {
+                             const int32_t* info, const ReduceJob* __restrict__ jobs) {
+  if (jobs) {  // batched: blockIdx.y = problem
+    const ReduceJob j = jobs[blockIdx.y];
+    lvl = j.lvl, splits = j.splits, G = j.out, info = j.info;
+  }
   if (info_failed(info)) return;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)np * np) return;
@@ -404,7 +430,8 @@ hipError_t launch_partial_sum(const double* part, int nparts, int64_t stride, in
                               const int32_t* info, hipStream_t st) {
   const int threads = 256;
   dim3 grid((unsigned)((stride + threads - 1) / threads), (unsigned)splits);
-  hipLaunchKernelGGL(k_partial_sum, grid, dim3(threads), 0, st, part, nparts, stride, splits, lvl, info);
+  hipLaunchKernelGGL(k_partial_sum, grid, dim3(threads), 0, st, part, nparts, stride, splits, lvl, info, nullptr,
+                     nullptr);
   return hipGetLastError();
 }
 
@@ -432,7 +459,7 @@ static hipError_t launch_tp(const TallPlan& p, const double* X, int64_t ldx, int
 #define TP_CASE(T, G, Wr)                                                                                          \
   if (trsm == T && gram == G && write == Wr) {                                                                     \
     hipLaunchKernelGGL((k_tall_mfma<(NP <= 64 ? NP : 64), T, G, Wr>), grid, block, 0, st, X, ldx, m, (int)n, Rp, W, \
-                       ldw, Gpart, p.ntiles, info);                                                                 \
+                       ldw, Gpart, p.ntiles, info, nullptr, nullptr);                                               \
     return hipGetLastError();                                                                                       \
   }
     TP_CASE(true, true, true)
@@ -448,7 +475,7 @@ static hipError_t launch_tp(const TallPlan& p, const double* X, int64_t ldx, int
     const int64_t nt = (m + tm_tile(NP) - 1) / tm_tile(NP);
     dim3 tgrid((unsigned)(p.gx < nt ? p.gx : nt));
     hipLaunchKernelGGL((k_tall_mfma<(NP > 64 ? NP : 128), true, false, true>), tgrid, block, 0, st, X, ldx, m, (int)n,
-                       Rp, W, ldw, nullptr, nt, info);
+                       Rp, W, ldw, nullptr, nt, info, nullptr, nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   } else if (write) {
@@ -460,7 +487,7 @@ static hipError_t launch_tp(const TallPlan& p, const double* X, int64_t ldx, int
     const int64_t nt32 = (m + 31) / 32;
     dim3 ggrid(p.gx, NP / 128);
     hipLaunchKernelGGL((k_gram_big<(NP > 64 ? NP : 128)>), ggrid, block, 0, st, src, lds_, m, (int)n, Gpart, nt32,
-                       info);
+                       info, nullptr, nullptr);
     return hipGetLastError();
   }
   return hipSuccess;
@@ -489,7 +516,78 @@ hipError_t launch_gram_reduce(const TallPlan& p, const double* Gpart, int64_t n,
   if (e != hipSuccess) return e;
   const int threads = 256;
   hipLaunchKernelGGL(k_gram_final, dim3((unsigned)((stride + threads - 1) / threads)), dim3(threads), 0, st, lvl,
-                     splits, p.np, n, G, info);
+                     splits, p.np, n, G, info, nullptr);
+  return hipGetLastError();
+}
+
+// ---- batched launches (one stage for many problems of the same n) ---------------
+// items: one entry per workgroup (problem, its workgroup index and count);
+// the same list drives the solve and, for n > 64, the separate Gram kernel,
+// so the Gram partials of problem p are its nwg workgroups' sums.
+template <int NP>
+static hipError_t launch_tall_batch_np(int n, bool trsm, bool gram, bool write, const TallJob* jobs,
+                                       const BatchItem* items, int nitems, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  dim3 grid((unsigned)nitems), block(TP_THREADS);
+  if (NP <= 64) {
+    constexpr int NPS = NP <= 64 ? NP : 64;
+    if (trsm && gram && write)
+      hipLaunchKernelGGL((k_tall_mfma<NPS, true, true, true>), grid, block, 0, st, nullptr, 0, 0, n, nullptr, nullptr, 0,
+                         nullptr, 0, nullptr, jobs, items);
+    else if (trsm && !gram && write)
+      hipLaunchKernelGGL((k_tall_mfma<NPS, true, false, true>), grid, block, 0, st, nullptr, 0, 0, n, nullptr, nullptr,
+                         0, nullptr, 0, nullptr, jobs, items);
+    else if (!trsm && gram && !write)
+      hipLaunchKernelGGL((k_tall_mfma<NPS, false, true, false>), grid, block, 0, st, nullptr, 0, 0, n, nullptr, nullptr,
+                         0, nullptr, 0, nullptr, jobs, items);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
+  constexpr int NPB = NP > 64 ? NP : 128;
+  if (trsm) {
+    if (!write) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_tall_mfma<NPB, true, false, true>), grid, block, 0, st, nullptr, 0, 0, n, nullptr, nullptr, 0,
+                       nullptr, 0, nullptr, jobs, items);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (gram) {
+    dim3 ggrid((unsigned)nitems, NPB / 128);
+    hipLaunchKernelGGL((k_gram_big<NPB>), ggrid, block, 0, st, nullptr, 0, 0, n, nullptr, 0, nullptr, jobs, items);
+    return hipGetLastError();
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_tall_batch(int np, int n, bool trsm, bool gram, bool write, const TallJob* jobs,
+                             const BatchItem* items, int nitems, hipStream_t st) {
+  switch (np) {
+    case 16: return launch_tall_batch_np<16>(n, trsm, gram, write, jobs, items, nitems, st);
+    case 32: return launch_tall_batch_np<32>(n, trsm, gram, write, jobs, items, nitems, st);
+    case 64: return launch_tall_batch_np<64>(n, trsm, gram, write, jobs, items, nitems, st);
+    case 128: return launch_tall_batch_np<128>(n, trsm, gram, write, jobs, items, nitems, st);
+    case 256: return launch_tall_batch_np<256>(n, trsm, gram, write, jobs, items, nitems, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Level-1 sums for many problems: items = (problem, split y, splits).
+hipError_t launch_partial_sum_batch(int64_t stride, const ReduceJob* jobs, const BatchItem* items, int nitems,
+                                    hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  const int threads = 256;
+  dim3 grid((unsigned)((stride + threads - 1) / threads), (unsigned)nitems);
+  hipLaunchKernelGGL(k_partial_sum, grid, dim3(threads), 0, st, nullptr, 0, stride, 1, nullptr, nullptr, jobs, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_final_batch(int np, int64_t n, const ReduceJob* jobs, int count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int threads = 256;
+  const int64_t stride = (int64_t)np * np;
+  dim3 grid((unsigned)((stride + threads - 1) / threads), (unsigned)count);
+  hipLaunchKernelGGL(k_gram_final, grid, dim3(threads), 0, st, nullptr, 1, np, n, nullptr, nullptr, jobs);
   return hipGetLastError();
 }
 

@@ -9,6 +9,52 @@
 
 namespace rclupp {
 
+// ---- batched (grouped) launches ----------------------------------------------
+// A batched launch runs one stage for many problems of the same n and s. Each
+// workgroup reads an item (problem index, its workgroup index and count within
+// that problem) and the problem's job record; the per-problem partition of the
+// work is the same as a single launch with `nwg` workgroups.
+struct BatchItem {
+  int32_t prob, wg, nwg, pad;
+};
+struct TallJob {
+  const double* X;
+  int64_t ldx, m, ntiles;
+  const double* Rp;
+  double* W;
+  int64_t ldw;
+  double* Gpart;
+  const int32_t* info;
+};
+struct SketchJob {
+  const double* X;
+  int64_t m, ld, ntiles;
+  uint64_t seed;
+  double* Ypart;
+  const int32_t* info;
+};
+struct ReduceJob {
+  const double* part;  // per-workgroup partials
+  double* lvl;         // level-1 sums
+  double* out;         // final result (Y or G)
+  int32_t nparts, splits;
+  const int32_t* info;
+};
+struct PrecondJob {
+  const double* Y;
+  double* R1pad;
+  double* scratch;
+  int32_t* info;
+};
+struct CholJob {
+  const double* G;
+  double* Rpad;
+  double* Rout;
+  const double* Rprev;
+  int32_t* info;
+  int64_t m;
+};
+
 // Padded column count used by the tall kernels: 16, 32, 64, 128 or 256.
 int pad_cols(int64_t n);
 // Padded sketch rows used by the sketch kernels (multiple of 64).
@@ -106,5 +152,20 @@ hipError_t launch_tall_lu(const double* X, int64_t m, int64_t n, int64_t ldx, do
                           double* Nout, double* scratch, int32_t* info, hipStream_t st);
 // M <- unit lower trapezoid of the packed LU (zero above, one on the diagonal).
 hipError_t launch_unit_lower(double* M, int64_t m, int64_t n, int64_t ldm, const int32_t* info, hipStream_t st);
+
+// ---- batched launchers ---------------------------------------------------------
+hipError_t launch_sketch_batch(const SketchPlan& p, int64_t n, int prec, const SketchJob* jobs, const BatchItem* items,
+                               int nitems, hipStream_t st);
+hipError_t launch_sketch_final_batch(const SketchPlan& p, int64_t s, int64_t n, double scale, const ReduceJob* jobs,
+                                     int count, hipStream_t st);
+hipError_t launch_tall_batch(int np, int n, bool trsm, bool gram, bool write, const TallJob* jobs,
+                             const BatchItem* items, int nitems, hipStream_t st);
+hipError_t launch_partial_sum_batch(int64_t stride, const ReduceJob* jobs, const BatchItem* items, int nitems,
+                                    hipStream_t st);
+hipError_t launch_gram_final_batch(int np, int64_t n, const ReduceJob* jobs, int count, hipStream_t st);
+hipError_t launch_precond_batch(int64_t s, int64_t n, int prec, const PrecondJob* jobs, int count, int32_t stage_qr,
+                                hipStream_t st);
+hipError_t launch_chol_batch(int64_t n, int ldg, int rout_user, const CholJob* jobs, int count, int32_t stage,
+                             hipStream_t st);
 
 }  // namespace rclupp

@@ -193,20 +193,94 @@ def test_krylov_rcluppr_invariants():
     assert np.all(np.diag(r) > 0) and np.all(np.tril(r, -1) == 0)
 
 
-def test_batched_matches_single():
+def _batch_inputs(shapes, seed0=100):
     rng = np.random.default_rng(0)
-    shapes = [(3000, 16), (5000, 32), (2000, 64), (7000, 24), (4000, 128)]
-    xs = [make_svd(m, n, 10 ** rng.uniform(2, 12), seed=100 + i) for i, (m, n) in enumerate(shapes)]
-    xs[2][5, 5] = np.nan  # one poisoned problem must not affect the others
+    kap = [10 ** rng.uniform(2, 12) for _ in shapes]
+    xs = [make_svd(m, n, kap[i], seed=seed0 + i) for i, (m, n) in enumerate(shapes)]
+    return xs, kap
+
+
+def test_batched_grouped_parity_and_isolation():
+    # RCLUPP problems of uneven m and n in one call, grouped by (n, s): each result
+    # meets the parity bar, and a poisoned problem does not affect the others
+    shapes = [(3000, 16), (5000, 32), (2000, 64), (7000, 24), (4000, 128), (9001, 64), (2500, 16), (6100, 128)]
+    xs, kap = _batch_inputs(shapes)
+    xs[2][5, 5] = np.nan
     Xs = [to_dev(x) for x in xs]
     Qs, Rs, info = _lib().qr_batched(Xs, alg="rclupp", seeds=list(range(len(xs))))
     info = info.cpu().numpy()
     for i, x in enumerate(xs):
-        one = _lib().qr(Xs[i], alg="rclupp", seed=i)
-        assert info[i].tolist() == one.info_host()
         if i == 2:
             assert info[i][0] == oracle.NONFINITE
             continue
+        assert info[i][0] == 0, (i, info[i])
+        n = x.shape[1]
+
+        class _R:
+            pass
+        r = _R()
+        r.Q, r.R = Qs[i], Rs[i]
+        r.info_host = lambda i=i: info[i].tolist()
+        method_parity(x, "rclupp", 2 * n, i, kap[i], r)
+        # the single-problem call differs only in how rows are split among workgroups
+        one = _lib().qr(Xs[i], alg="rclupp", seed=i)
+        d = np.linalg.norm(to_host(one.R) - to_host(Rs[i])) / np.linalg.norm(to_host(one.R))
+        assert d <= 1e-14 * kap[i]
+
+
+def test_batched_deterministic_and_graph_replays():
+    shapes = [(3000, 16), (5000, 32), (2000, 64), (4000, 128), (6100, 128), (1200, 48)]
+    xs, _ = _batch_inputs(shapes, seed0=300)
+    Xs = [to_dev(x) for x in xs]
+    eager = _lib().Batch(Xs, alg="rclupp")
+    q0, r0, i0 = eager.run()
+    ref_q = [to_host(q) for q in q0]
+    ref_r = [to_host(r) for r in r0]
+    ref_i = i0.cpu().numpy().copy()
+    q1, r1, _ = eager.run()
+    for k in range(len(xs)):
+        np.testing.assert_array_equal(to_host(q1[k]), ref_q[k])
+        np.testing.assert_array_equal(to_host(r1[k]), ref_r[k])
+    g = _lib().Batch(Xs, alg="rclupp", graph=True)
+    for rep in range(3):
+        # the program's own eager work between the replays
+        other = _lib().qr(Xs[1], alg="rclupp", seed=7)
+        torch.cuda.synchronize()
+        for q in g.Qs:
+            q.fill_(-1.0)
+        qg, rg, ig = g.run()
+        torch.cuda.synchronize()
+        assert np.array_equal(ig.cpu().numpy(), ref_i), rep
+        for k in range(len(xs)):
+            np.testing.assert_array_equal(to_host(qg[k]), ref_q[k])
+            np.testing.assert_array_equal(to_host(rg[k]), ref_r[k])
+        del other
+
+
+def test_batched_autotune_parity():
+    shapes = [(20000, 16), (15000, 32), (9000, 64), (12000, 128)]
+    xs, kap = _batch_inputs(shapes, seed0=500)
+    Xs = [to_dev(x) for x in xs]
+    b = _lib().Batch(Xs, alg="rclupp", autotune=True)
+    for _ in range(2):  # the first call tunes, the second reuses the choice
+        Qs, Rs, info = b.run()
+        torch.cuda.synchronize()
+        for i, x in enumerate(xs):
+            assert info[i].cpu().tolist()[0] == 0
+            m = oracle.metrics(x, to_host(Qs[i]), to_host(Rs[i]))
+            assert m["orth"] <= TOL_ORTH and m["rel_res"] <= TOL_RES
+
+
+def test_batched_sequential_fallback_matches_single():
+    # a problem beyond the grouped kernels (n = 200) sends the batch down the
+    # single-problem pipeline: identical to separate calls
+    shapes = [(3000, 16), (4000, 200), (2000, 64)]
+    xs, _ = _batch_inputs(shapes, seed0=700)
+    Xs = [to_dev(x) for x in xs]
+    Qs, Rs, info = _lib().qr_batched(Xs, alg="rclupp", seeds=[0, 1, 2])
+    for i in range(len(xs)):
+        one = _lib().qr(Xs[i], alg="rclupp", seed=i)
+        assert info[i].cpu().tolist() == one.info_host()
         np.testing.assert_array_equal(to_host(Qs[i]), to_host(one.Q))
         np.testing.assert_array_equal(to_host(Rs[i]), to_host(one.R))
 
