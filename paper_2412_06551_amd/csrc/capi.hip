@@ -163,7 +163,7 @@ int tail_cholqr2(const Layout& L, char* ws, const double* X, int64_t m, int64_t 
   STAGE("chol");
   HIPCHK(launch_chol(g, np, n, m, 0, r4, R, 1, r3, nullptr, 0, small, info, RCLUPP_STAGE_CHOL_B, st));
   STAGE("trsm_final");
-  HIPCHK(launch_tall_pass(L.tp, Q, ld, m, n, r4, Q, ld, gpart, info, st));  // Gram unused
+  HIPCHK(launch_tall_pass(L.tp, Q, ld, m, n, r4, Q, ld, nullptr, info, st));
   return RCLUPP_OK;
 }
 
@@ -183,7 +183,7 @@ int tail_cholqr1(const Layout& L, char* ws, const double* X, int64_t m, int64_t 
   STAGE("chol");
   HIPCHK(launch_chol(g, np, n, m, 0, r2, R, 1, r1, nullptr, 0, small, info, RCLUPP_STAGE_CHOL_A, st));
   STAGE("trsm_final");
-  HIPCHK(launch_tall_pass(L.tp, Q, ld, m, n, r2, Q, ld, gpart, info, st));  // Gram unused
+  HIPCHK(launch_tall_pass(L.tp, Q, ld, m, n, r2, Q, ld, nullptr, info, st));
   return RCLUPP_OK;
 }
 
