@@ -344,6 +344,7 @@ __global__ void k_sketch_final(const double* __restrict__ lvl, int splits, int64
   const double* p = lvl + i + j * s_pad;
   const int64_t stride = s_pad * n_pad;
   double acc = 0.0;
+  #pragma unroll 16
   for (int y = 0; y < splits; ++y) acc += p[(int64_t)y * stride];
   Y[i + j * s] = acc * scale;
 }

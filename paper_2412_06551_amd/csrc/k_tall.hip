@@ -2,8 +2,8 @@
 // triangular R:  W = X R^{-1}  and  G = W^T W.
 //
 // n <= 64: one fused kernel per pass (k_tall_mfma). The substitution
-//   w_j = (x_j - sum_{i<j} w_i R_ij) / R_jj   (backward stable, eq. ewy; no
-//   explicit inverse of the possibly very ill-conditioned R_1)
+//   w_j = (x_j - sum_{i<j} w_i R_ij) / R_jj   (row-wise backward stable, eq. ewy
+//   and eqs. C3, C7; no explicit inverse of the possibly very ill-conditioned R_1)
 // runs blocked on the FP64 matrix cores with the diagonal blocks finished row
 // by row in registers; the Gram partial sum of the solved rows is fused.
 // n > 64: the same blocked substitution without the fused Gram (the
@@ -46,11 +46,14 @@ int pad_cols(int64_t n) {
 // built in LDS once per workgroup.
 // The diagonal block is solved row by row: the wave's 32 rows go through a
 // per-wave LDS transpose so that lane l < 32 holds the 16 block entries of one
-// row, which it finishes in registers, w_j = (x_j - sum_{i<j} w_i R_ij) / R_jj
-// in ascending i with fused multiply-adds, the quotient rounded to nearest
-// (from the correctly rounded reciprocal of R_jj and one remainder
-// correction, see quot_rn). That is the row-wise substitution's arithmetic,
-// so W is bit-identical to it.
+// row, which it finishes in registers with the columns of the block scaled by
+// y_j = RN(1/R_jj):  R_bb = U D  with U unit upper triangular, U_ij = R_ij y_j,
+// so  w_j = c_j y_j - sum_{i<j} w_i U_ij  (fused multiply-adds in ascending i,
+// right-looking: each finished w_i is sent to all later columns at once).
+// The dependent chain per column is one multiply-add instead of a quotient
+// after the last term, and the rounding of U and of c_j y_j perturbs every
+// entry of R by at most 2u relative, so the row-wise bound of eq. ewy holds
+// with gamma_{n+3} in place of gamma_n.
 // Each wave handles two 16-row blocks (32 rows; one block when n > 128); the
 // four waves of a workgroup cover a 128-row (64-row) tile. X and W move in
 // 128-byte row segments.
@@ -64,18 +67,6 @@ constexpr int tm_hb(int np) { return np > 128 ? 1 : 2; }
 constexpr int tm_tile(int np) { return 64 * tm_hb(np); }  // rows per workgroup tile
 constexpr int TM_LDG = 17;                 // Gram staging: 16 rows + pad per column
 constexpr int TM_LDT = 18;                 // diagonal transpose: 16 entries + pad per row (16-byte aligned)
-
-// a / b from y = RN(1/b): q0 = a y is within two ulps of a/b and the
-// remainder r = a - q0 b is formed by one fused multiply-add, so q0 + r y is
-// a/b up to a relative 4u of the error of q0, i.e. within about 2^-51 ulp;
-// rounding it gives RN(a/b) unless a/b lies that close to a rounding midpoint
-// (a/b is never exactly a midpoint unless b is a power of two, where q0 is
-// already exact). Away from underflow and overflow.
-__device__ __forceinline__ double quot_rn(double a, double b, double y) {
-  const double q = a * y;
-  const double r = __builtin_fma(-q, b, a);
-  return __builtin_fma(r, y, q);
-}
 
 template <int NP, bool TRSM, bool GRAM, bool WRITE>
 __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(const double* X, int64_t ldx, int64_t m, int n,
@@ -119,12 +110,13 @@ __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(co
       }
       otab[e] = -Rp[(16 * c + 4 * kk + (l >> 4)) * NP + 16 * b + (l & 15)];
     }
-    // diagonal blocks dtab[b*256 + j*16 + k] = R[16b+j][16b+k] (zero below the
-    // diagonal), then dtab[NB*256 + 16b + j] = RN(1 / R[16b+j][16b+j])
+    // diagonal blocks with scaled columns, dtab[b*256 + j*16 + k] = U_jk =
+    // R[16b+j][16b+k] * y_k for k > j (zero elsewhere), then the reciprocals
+    // dtab[NB*256 + 16b + j] = y_j = RN(1 / R[16b+j][16b+j])
     for (int e = tid; e < DTAB; e += TP_THREADS) {
       if (e < NB * 256) {
         const int k = e & 15, j = (e >> 4) & 15, b = e >> 8;
-        dtab[e] = (k >= j) ? Rp[(16 * b + j) * NP + 16 * b + k] : 0.0;
+        dtab[e] = (k > j) ? Rp[(16 * b + j) * NP + 16 * b + k] * Rp[NP * NP + 16 * b + k] : 0.0;
       } else {
         dtab[e] = Rp[NP * NP + (e - NB * 256)];
       }
@@ -184,14 +176,14 @@ __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(co
             v[2 * e] = q.x;
             v[2 * e + 1] = q.y;
           }
-          const double* rb = dtab + dofs + b * 256;
+          const double* ub = dtab + dofs + b * 256;
           const double* yb = dtab + dofs + NB * 256 + 16 * b;
 #pragma unroll
-          for (int j = 0; j < 16; ++j) {
-            v[j] = quot_rn(v[j], rb[j * 16 + j], yb[j]);
+          for (int j = 0; j < 16; ++j) v[j] *= yb[j];
 #pragma unroll
-            for (int k = j + 1; k < 16; ++k) v[k] = __builtin_fma(-v[j], rb[j * 16 + k], v[k]);
-          }
+          for (int j = 0; j < 15; ++j)
+#pragma unroll
+            for (int k = j + 1; k < 16; ++k) v[k] = __builtin_fma(-v[j], ub[j * 16 + k], v[k]);
           double2* dst = (double2*)(tt + lane * TM_LDT);
 #pragma unroll
           for (int e = 0; e < 8; ++e) dst[e] = double2{v[2 * e], v[2 * e + 1]};
@@ -390,6 +382,7 @@ __global__ void k_partial_sum(const double* __restrict__ part, int nparts, int64
   const int per = (nparts + splits - 1) / splits;
   const int b0 = y * per, b1 = (b0 + per < nparts) ? b0 + per : nparts;
   double acc = 0.0;
+  #pragma unroll 16
   for (int b = b0; b < b1; ++b) acc += part[(int64_t)b * stride + e];
   lvl[(int64_t)y * stride + e] = acc;
 }
@@ -413,6 +406,7 @@ __global__ void k_gram_final(const double* __restrict__ lvl, int splits, int np,
   } else {
     const int64_t stride = (int64_t)np * np;
     v = 0.0;
+    #pragma unroll 16
     for (int y = 0; y < splits; ++y) v += lvl[(int64_t)y * stride + e];
   }
   G[i + (int64_t)j * np] = v;
