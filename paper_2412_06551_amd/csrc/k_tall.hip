@@ -46,14 +46,14 @@ int pad_cols(int64_t n) {
 // built in LDS once per workgroup.
 // The diagonal block is solved row by row: the wave's 32 rows go through a
 // per-wave LDS transpose so that lane l < 32 holds the 16 block entries of one
-// row, which it finishes in registers with the columns of the block scaled by
-// y_j = RN(1/R_jj):  R_bb = U D  with U unit upper triangular, U_ij = R_ij y_j,
-// so  w_j = c_j y_j - sum_{i<j} w_i U_ij  (fused multiply-adds in ascending i,
-// right-looking: each finished w_i is sent to all later columns at once).
-// The dependent chain per column is one multiply-add instead of a quotient
-// after the last term, and the rounding of U and of c_j y_j perturbs every
-// entry of R by at most 2u relative, so the row-wise bound of eq. ewy holds
-// with gamma_{n+3} in place of gamma_n.
+// row, which it finishes in registers,
+//   w_j = (c_j - sum_{i<j} w_i R_ij) * y_j,   y_j = RN(1/R_jj),
+// with fused multiply-adds in ascending i, right-looking (each finished w_i is
+// sent to all later columns at once), so the dependent chain per column is one
+// multiply-add and one multiply. Multiplying by the rounded reciprocal instead
+// of dividing perturbs R_jj by at most 2u relative, so the row-wise bound of
+// eq. ewy holds with gamma_{n+1} in place of gamma_n. The R entries and the
+// reciprocals are wave-uniform and come through the scalar cache.
 // Each wave handles two 16-row blocks (32 rows; one block when n > 128); the
 // four waves of a workgroup cover a 128-row (64-row) tile. X and W move in
 // 128-byte row segments.
@@ -85,14 +85,12 @@ __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(co
   constexpr int NB = NP / 16;                  // column blocks
   constexpr int NOFF = NB * (NB - 1) / 2;      // off-diagonal block pairs c < b
   constexpr int NBLK = NB * (NB + 1) / 2;      // upper Gram blocks
-  constexpr int DTAB = TRSM ? NB * 272 : 1;    // diagonal blocks [b][j][k] then reciprocals [b][j]
   constexpr int HB = tm_hb(NP), RW = 16 * HB;           // 16-row blocks and rows per wave
   constexpr int TTAB = TRSM ? 4 * RW * TM_LDT : 1;       // per-wave transpose regions
   constexpr int GST = GRAM ? ((4 * NP * TM_LDG > NBLK * 256) ? 4 * NP * TM_LDG : NBLK * 256) : 1;
   // off-diagonal A fragments: an LDS table for NP <= 64, read from R (L2) above
   constexpr bool OG = NP > 128;
   constexpr int OTAB = (TRSM && NOFF > 0 && !OG) ? NOFF * 4 * 64 : 1;  // [pair][kk][lane]
-  __shared__ double dtab[DTAB];
   __shared__ double otab[OTAB];
   __shared__ double gst[GST];
   __shared__ __align__(16) double ttab[TTAB];
@@ -109,17 +107,6 @@ __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(co
         ++b;
       }
       otab[e] = -Rp[(16 * c + 4 * kk + (l >> 4)) * NP + 16 * b + (l & 15)];
-    }
-    // diagonal blocks with scaled columns, dtab[b*256 + j*16 + k] = U_jk =
-    // R[16b+j][16b+k] * y_k for k > j (zero elsewhere), then the reciprocals
-    // dtab[NB*256 + 16b + j] = y_j = RN(1 / R[16b+j][16b+j])
-    for (int e = tid; e < DTAB; e += TP_THREADS) {
-      if (e < NB * 256) {
-        const int k = e & 15, j = (e >> 4) & 15, b = e >> 8;
-        dtab[e] = (k > j) ? Rp[(16 * b + j) * NP + 16 * b + k] * Rp[NP * NP + 16 * b + k] : 0.0;
-      } else {
-        dtab[e] = Rp[NP * NP + (e - NB * 256)];
-      }
     }
   }
   __syncthreads();
@@ -176,14 +163,15 @@ __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(co
             v[2 * e] = q.x;
             v[2 * e + 1] = q.y;
           }
-          const double* ub = dtab + dofs + b * 256;
-          const double* yb = dtab + dofs + NB * 256 + 16 * b;
 #pragma unroll
-          for (int j = 0; j < 16; ++j) v[j] *= yb[j];
+          for (int j = 0; j < 16; ++j) {
+            // the scalar loads of row j run at most two rows ahead of the
+            // substitution (all of them at once would not fit the SGPRs)
+            const cdptr Rj = (j < 2) ? Rt : opaque_after(Rp, v[j - 2]);
+            v[j] *= Rj[NP * NP + 16 * b + j];
 #pragma unroll
-          for (int j = 0; j < 15; ++j)
-#pragma unroll
-            for (int k = j + 1; k < 16; ++k) v[k] = __builtin_fma(-v[j], ub[j * 16 + k], v[k]);
+            for (int k = j + 1; k < 16; ++k) v[k] = __builtin_fma(-v[j], Rj[(16 * b + j) * NP + 16 * b + k], v[k]);
+          }
           double2* dst = (double2*)(tt + lane * TM_LDT);
 #pragma unroll
           for (int e = 0; e < 8; ++e) dst[e] = double2{v[2 * e], v[2 * e + 1]};

@@ -168,7 +168,7 @@ def _check_trsm(w, wo, x, R):
     """W from the kernel against the oracle's row-wise substitution W_o.
     Row-wise backward error (eq. ewy): |W R - X| <= gamma |W| |R| with
     gamma = 2 (n + 3) u, covering the substitution's gamma_n and the 2u
-    perturbation of R from the column scaling of the diagonal blocks.
+    perturbation of R_jj from multiplying by its rounded reciprocal.
     Forward: both solutions satisfy such a bound, so
     |W - W_o| <= 2 gamma |W| |R| |R^{-1}| (first order)."""
     n = R.shape[0]
