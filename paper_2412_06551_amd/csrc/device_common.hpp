@@ -67,16 +67,18 @@ __device__ __forceinline__ f32x4 normals4(uint64_t seed, uint64_t j, uint32_t q)
   const philox_out w = philox4x32_10((uint32_t)j, (uint32_t)(j >> 32), q, 0u, (uint32_t)seed, (uint32_t)(seed >> 32));
   const float u0 = word_to_uniform(w.w0), u1 = word_to_uniform(w.w1);
   const float u2 = word_to_uniform(w.w2), u3 = word_to_uniform(w.w3);
-  const float r0 = sqrtf(-2.0f * logf(u0));
-  const float r1 = sqrtf(-2.0f * logf(u2));
-  float s0, c0, s1, c1;
-  sincospif(2.0f * u1, &s0, &c0);
-  sincospif(2.0f * u3, &s1, &c1);
+  // Box-Muller on the hardware transcendentals: log2, square root, and sine
+  // and cosine of 2 pi x taken in revolutions (one instruction each; within
+  // 8 float32 ulps of max(|z|, 1) of the correctly rounded transform, checked
+  // against the library functions on 2^24 draws)
+  const float k = -2.0f * 0.693147180559945309f;  // -2 ln 2: ln u = ln 2 log2 u
+  const float r0 = __builtin_amdgcn_sqrtf(k * __builtin_amdgcn_logf(u0));
+  const float r1 = __builtin_amdgcn_sqrtf(k * __builtin_amdgcn_logf(u2));
   f32x4 z;
-  z[0] = r0 * c0;
-  z[1] = r0 * s0;
-  z[2] = r1 * c1;
-  z[3] = r1 * s1;
+  z[0] = r0 * __builtin_amdgcn_cosf(u1);
+  z[1] = r0 * __builtin_amdgcn_sinf(u1);
+  z[2] = r1 * __builtin_amdgcn_cosf(u3);
+  z[3] = r1 * __builtin_amdgcn_sinf(u3);
   return z;
 }
 

@@ -132,7 +132,9 @@ __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(co
         for (int r = 0; r < 4; ++r) {
           const int col = 16 * b + lq + 4 * r;
           const double* cb = X + (int64_t)(16 * b + 4 * r) * ldx;
-          acc[h][b][r] = (live && col < n) ? cb[voff] : 0.0;
+          // streamed once: nontemporal, so X and W do not evict R, the tables
+          // and the partials from the caches
+          acc[h][b][r] = (live && col < n) ? __builtin_nontemporal_load(cb + voff) : 0.0;
         }
     }
     if (TRSM) {
@@ -212,7 +214,7 @@ __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(co
             for (int r = 0; r < 4; ++r) {
               const int col = 16 * b + lq + 4 * r;
               double* cb = W + (int64_t)(16 * b + 4 * r) * ldw;
-              if (col < n) cb[voff] = acc[h][b][r];
+              if (col < n) __builtin_nontemporal_store(acc[h][b][r], cb + voff);
             }
         }
       }
@@ -423,10 +425,13 @@ TallPlan plan_tall(int64_t m, int64_t n, int gx_hint) {
   p.fused_gram = p.np <= 64;
   p.tile_rows = p.fused_gram ? tm_tile(p.np) : TP_THREADS;
   p.ntiles = (m + p.tile_rows - 1) / p.tile_rows;
-  int gx = gx_hint > 0 ? gx_hint : 1024;
-  if (gx > p.ntiles) gx = (int)p.ntiles;
-  if (gx < 1) gx = 1;
-  p.gx = gx;
+  // Gram passes: one round of resident workgroups for n <= 64 (two per CU on
+  // 256 CUs: register bound), which also keeps the partials few; passes
+  // without the Gram (lighter kernel, four per CU) use two rounds
+  auto clampg = [&](int g) { return (int)(g > p.ntiles ? p.ntiles : (g < 1 ? 1 : g)); };
+  p.gx = clampg(gx_hint > 0 ? gx_hint : (p.np == 64 ? 512 : 1024));
+  p.gx_solve = clampg(gx_hint > 0 ? gx_hint : (p.fused_gram ? 2048 : 1024));
+  const int gx = p.gx;
   // per-workgroup partials followed by the level-1 sums of the reduction
   p.part_bytes = ((size_t)gx + reduce_splits(gx)) * p.np * p.np * sizeof(double);
   return p;
@@ -435,8 +440,8 @@ TallPlan plan_tall(int64_t m, int64_t n, int gx_hint) {
 template <int NP>
 static hipError_t launch_tp(const TallPlan& p, const double* X, int64_t ldx, int64_t m, int64_t n, const double* Rp,
                             double* W, int64_t ldw, double* Gpart, const int32_t* info, hipStream_t st) {
-  dim3 grid(p.gx), block(TP_THREADS);
   const bool trsm = Rp != nullptr, gram = Gpart != nullptr, write = W != nullptr;
+  dim3 grid(gram ? p.gx : p.gx_solve), block(TP_THREADS);
   if (NP <= 64) {
 #define TP_CASE(T, G, Wr)                                                                                          \
   if (trsm == T && gram == G && write == Wr) {                                                                     \

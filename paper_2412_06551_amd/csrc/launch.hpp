@@ -95,7 +95,8 @@ inline size_t padded_r_doubles(int np) { return (size_t)np * np + np; }
 
 struct TallPlan {
   int np;          // padded columns
-  int gx;          // workgroups
+  int gx;          // workgroups of the passes with a Gram (= Gram partials)
+  int gx_solve;    // workgroups of the passes without one
   int64_t ntiles;  // row tiles
   int tile_rows;   // rows per tile
   bool fused_gram; // Gram computed inside the TRSM kernel (np <= 64)
