@@ -12,6 +12,13 @@
 //   M-block mb = 4a + u, slot i = 4c + t  ->  sketch row 64a + 16c + 4t + u,
 // i.e. group q = 16a + 4c + t and output u of Philox(j, q). Every G entry is
 // therefore generated exactly once per (workgroup column group).
+// Two ways to share a workgroup's tile among its four waves:
+//   WM = false: the waves take 16 rows of the tile each and own the same SM
+//     sketch rows (summed over the waves at the end); one workgroup column
+//     covers SM sketch rows.
+//   WM = true (many sketch rows, s >= 4 SM): each wave owns its own SM sketch
+//     rows and walks all rows of the tile, so one workgroup covers 4 SM sketch
+//     rows and X is read by 4 times fewer workgroup groups.
 // Each workgroup writes its partial sum (fixed order over its tiles and
 // waves); a second kernel adds the partials in workgroup order and scales by
 // 1/sqrt(s), so the result is deterministic.
@@ -31,7 +38,7 @@ struct SketchLds {
   static constexpr int SIZE = (2 * TILE > RED) ? 2 * TILE : RED;
 };
 
-template <int SM, int NN>
+template <int SM, int NN, bool WM>
 __global__ __launch_bounds__(SK_THREADS) void k_sketch_f64(const double* __restrict__ X, int64_t m, int n, int64_t ld,
                                                            int64_t ntiles, uint64_t seed, double* __restrict__ Ypart,
                                                            int64_t s_pad, int64_t n_pad, const int32_t* info,
@@ -75,7 +82,8 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch_f64(const double* __restr
 
   // A-operand slot of this lane: i = lane % 16 = 4c + t, K row = lane / 16
   const int ai = lane & 15, ak = lane >> 4;
-  const uint32_t qbase = (uint32_t)((sg * SM) / 4 + 4 * (ai >> 2) + (ai & 3));
+  const int grp = WM ? 4 * sg + wave : sg;  // this wave's group of SM sketch rows
+  const uint32_t qbase = (uint32_t)((grp * SM) / 4 + 4 * (ai >> 2) + (ai & 3));
 
   int64_t t = wg;
   int buf = 0;
@@ -89,8 +97,8 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch_f64(const double* __restr
     if (tn < ntiles) load_tile(tn);
     const double* xs = lds + buf * TILE;
 #pragma unroll 1
-    for (int ks = 0; ks < 4; ++ks) {
-      const int rloc = 16 * wave + 4 * ks + ak;
+    for (int ks = 0; ks < (WM ? 16 : 4); ++ks) {
+      const int rloc = (WM ? 0 : 16 * wave) + 4 * ks + ak;
       const int64_t j = t * SK_TK + rloc;
       double b[NB];
 #pragma unroll
@@ -112,6 +120,19 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch_f64(const double* __restr
     buf ^= 1;
   }
 
+  if (WM) {  // each wave owns its rows: store them
+#pragma unroll
+    for (int a = 0; a < MB; ++a)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t srow = (int64_t)grp * SM + 64 * (a >> 2) + 16 * r + 4 * (lane >> 4) + (a & 3);
+          const int64_t col = col0 + 16 * nb + (lane & 15);
+          Ypart[wg * s_pad * n_pad + srow + col * s_pad] = acc[a][nb][r];
+        }
+    return;
+  }
   // Sum the four waves' partials in wave order through LDS, then store.
   double* red = lds;
   for (int w = 0; w < 4; ++w) {
@@ -167,7 +188,7 @@ struct SketchLpLds {
   static constexpr int BYTES = (2 * TILE_BYTES > RED_BYTES) ? 2 * TILE_BYTES : RED_BYTES;
 };
 
-template <int SM, int NN, bool BF>
+template <int SM, int NN, bool BF, bool WM>
 __global__ __launch_bounds__(SK_THREADS) void k_sketch_lp(const double* __restrict__ X, int64_t m, int n, int64_t ld,
                                                           int64_t ntiles, uint64_t seed, double* __restrict__ Ypart,
                                                           int64_t s_pad, int64_t n_pad, const int32_t* info,
@@ -231,7 +252,8 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch_lp(const double* __restri
   };
 
   const int ai = lane & 15, ag = lane >> 4;
-  const uint32_t qbase = (uint32_t)((sg * SM) / 4 + 4 * (ai >> 2) + (ai & 3));
+  const int grp = WM ? 4 * sg + wave : sg;  // this wave's group of SM sketch rows
+  const uint32_t qbase = (uint32_t)((grp * SM) / 4 + 4 * (ai >> 2) + (ai & 3));
 
   int64_t t = wg;
   int buf = 0;
@@ -245,7 +267,9 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch_lp(const double* __restri
     if (tn < ntiles) load_tile(tn);
     if constexpr (BF) {
       const unsigned short* xs = (const unsigned short*)(lds_raw + buf * L::TILE_BYTES);
-      const int r0 = 32 * wave + 8 * ag;  // this lane's 8 tall rows within the tile
+#pragma unroll 1
+      for (int ks = 0; ks < (WM ? 4 : 1); ++ks) {
+      const int r0 = (WM ? 32 * ks : 32 * wave) + 8 * ag;  // this lane's 8 tall rows within the tile
       bf16x8 b[NB];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
@@ -275,11 +299,12 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch_lp(const double* __restri
             acc[4 * a + u][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, b[nb], acc[4 * a + u][nb], 0, 0, 0);
         }
       }
+      }
     } else {
       const float* xs = (const float*)(lds_raw + buf * L::TILE_BYTES);
 #pragma unroll 1
-      for (int ks = 0; ks < 4; ++ks) {
-        const int rloc = 16 * wave + 4 * ks + ag;
+      for (int ks = 0; ks < (WM ? 16 : 4); ++ks) {
+        const int rloc = (WM ? 0 : 16 * wave) + 4 * ks + ag;
         const int64_t j = t * TK + rloc;
         float b[NB];
 #pragma unroll
@@ -301,6 +326,20 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch_lp(const double* __restri
     buf ^= 1;
   }
 
+  if (WM) {  // each wave owns its rows: store them (FP64)
+#pragma unroll
+    for (int a = 0; a < MB; ++a)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int slot = 4 * (lane >> 4) + r;
+          const int64_t srow = (int64_t)grp * SM + 64 * (a >> 2) + 16 * (slot >> 2) + 4 * (slot & 3) + (a & 3);
+          const int64_t col = col0 + 16 * nb + (lane & 15);
+          Ypart[wg * s_pad * n_pad + srow + col * s_pad] = (double)acc[a][nb][r];
+        }
+    return;
+  }
   // Sum the four waves' partials in wave order (FP64) through LDS, then store.
   double* red = (double*)lds_raw;
   for (int w = 0; w < 4; ++w) {
@@ -389,7 +428,9 @@ SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int gx_hint) {
   const int max_sm = (p.nn == 16) ? 256 : (p.nn == 32) ? 256 : (p.nn == 64) ? 128 : 64;
   p.sm = 64;
   while (p.sm * 2 <= max_sm && p.s_pad % (p.sm * 2) == 0) p.sm *= 2;
-  p.gy = (int)(p.s_pad / p.sm);
+  // four or more row groups: give each wave its own group (X read 4x less)
+  p.wm = p.s_pad % (4 * p.sm) == 0;
+  p.gy = (int)(p.s_pad / (p.wm ? 4 * p.sm : p.sm));
   p.gz = (int)((n + p.nn - 1) / p.nn);
   p.n_pad = (int64_t)p.gz * p.nn;
   const int tk = (prec == 2) ? 128 : SK_TK;  // BF16 tiles are 128 rows
@@ -405,21 +446,29 @@ SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int gx_hint) {
   return p;
 }
 
+template <int SM, int NN, bool WM>
+static hipError_t launch_sk_wm(const SketchPlan& p, const double* X, int64_t m, int64_t n, int64_t ld, uint64_t seed,
+                               int prec, double* Ypart, const int32_t* info, const SketchJob* jobs,
+                               const BatchItem* items, int nitems, hipStream_t st) {
+  dim3 grid(items ? (unsigned)nitems : (unsigned)p.gx, p.gy, p.gz);
+  if (prec == 0)
+    hipLaunchKernelGGL((k_sketch_f64<SM, NN, WM>), grid, dim3(SK_THREADS), 0, st, X, m, (int)n, ld, p.ntiles, seed,
+                       Ypart, p.s_pad, p.n_pad, info, jobs, items);
+  else if (prec == 1)
+    hipLaunchKernelGGL((k_sketch_lp<SM, NN, false, WM>), grid, dim3(SK_THREADS), 0, st, X, m, (int)n, ld, p.ntiles,
+                       seed, Ypart, p.s_pad, p.n_pad, info, jobs, items);
+  else
+    hipLaunchKernelGGL((k_sketch_lp<SM, NN, true, WM>), grid, dim3(SK_THREADS), 0, st, X, m, (int)n, ld, p.ntiles,
+                       seed, Ypart, p.s_pad, p.n_pad, info, jobs, items);
+  return hipGetLastError();
+}
+
 template <int SM, int NN>
 static hipError_t launch_sk(const SketchPlan& p, const double* X, int64_t m, int64_t n, int64_t ld, uint64_t seed,
                             int prec, double* Ypart, const int32_t* info, const SketchJob* jobs,
                             const BatchItem* items, int nitems, hipStream_t st) {
-  dim3 grid(items ? (unsigned)nitems : (unsigned)p.gx, p.gy, p.gz);
-  if (prec == 0)
-    hipLaunchKernelGGL((k_sketch_f64<SM, NN>), grid, dim3(SK_THREADS), 0, st, X, m, (int)n, ld, p.ntiles, seed, Ypart,
-                       p.s_pad, p.n_pad, info, jobs, items);
-  else if (prec == 1)
-    hipLaunchKernelGGL((k_sketch_lp<SM, NN, false>), grid, dim3(SK_THREADS), 0, st, X, m, (int)n, ld, p.ntiles, seed,
-                       Ypart, p.s_pad, p.n_pad, info, jobs, items);
-  else
-    hipLaunchKernelGGL((k_sketch_lp<SM, NN, true>), grid, dim3(SK_THREADS), 0, st, X, m, (int)n, ld, p.ntiles, seed,
-                       Ypart, p.s_pad, p.n_pad, info, jobs, items);
-  return hipGetLastError();
+  if (p.wm) return launch_sk_wm<SM, NN, true>(p, X, m, n, ld, seed, prec, Ypart, info, jobs, items, nitems, st);
+  return launch_sk_wm<SM, NN, false>(p, X, m, n, ld, seed, prec, Ypart, info, jobs, items, nitems, st);
 }
 
 static hipError_t sketch_dispatch(const SketchPlan& p, const double* X, int64_t m, int64_t n, int64_t ld,

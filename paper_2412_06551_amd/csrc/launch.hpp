@@ -72,7 +72,8 @@ struct SketchPlan {
   int nn;          // columns per workgroup (16, 32, 64 or 128)
   int gx;          // row-chunk workgroups
   int gy, gz;      // sketch-row groups, column groups
-  int64_t s_pad;   // padded sketch rows (gy * sm)
+  bool wm;         // each wave owns its own sm sketch rows (a workgroup covers 4 sm)
+  int64_t s_pad;   // padded sketch rows (gy * sm, times 4 when wm)
   int64_t n_pad;   // padded columns (gz * nn)
   int64_t ntiles;  // 64-row tiles of the tall operand
   size_t part_bytes;  // bytes of the per-workgroup partial sums

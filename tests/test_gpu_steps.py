@@ -53,7 +53,7 @@ def test_omega_normals_match(s, cols, j0, seed):
 
 # ---------------------------------------------------------------- sketch
 @pytest.mark.parametrize("m,n,s,seed", [(2048, 32, 64, 0), (5000 + 37, 64, 128, 3), (700, 16, 40, 1),
-                                        (3000, 100, 200, 2), (1025, 5, 5, 4)])
+                                        (3000, 100, 200, 2), (1025, 5, 5, 4), (3001, 16, 1000, 6)])
 def test_sketch_matches_oracle(m, n, s, seed):
     x = make_svd(m, n, 1e6, seed=seed)
     y = to_host(_lib().sketch(to_dev(x), s, seed))
