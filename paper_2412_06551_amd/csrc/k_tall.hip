@@ -68,7 +68,11 @@ constexpr int tm_tile(int np) { return 64 * tm_hb(np); }  // rows per workgroup 
 constexpr int TM_LDG = 17;                 // Gram staging: 16 rows + pad per column
 constexpr int TM_LDT = 18;                 // diagonal transpose: 16 entries + pad per row (16-byte aligned)
 
-template <int NP, bool TRSM, bool GRAM, bool WRITE>
+// RS, ROFF: R is the ROFF x ROFF-offset NP x NP diagonal block of a padded
+// triangle with row stride RS (Rp points at its first entry; the reciprocals
+// of its diagonal then sit RS (RS - ROFF) entries further on). The defaults
+// are the whole padded triangle.
+template <int NP, bool TRSM, bool GRAM, bool WRITE, int RS = NP, int ROFF = 0>
 __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(const double* X, int64_t ldx, int64_t m, int n,
                                                             const double* __restrict__ Rp, double* W, int64_t ldw,
                                                             double* __restrict__ Gpart, int64_t ntiles,
@@ -106,7 +110,7 @@ __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(co
         c -= b;
         ++b;
       }
-      otab[e] = -Rp[(16 * c + 4 * kk + (l >> 4)) * NP + 16 * b + (l & 15)];
+      otab[e] = -Rp[(16 * c + 4 * kk + (l >> 4)) * RS + 16 * b + (l & 15)];
     }
   }
   __syncthreads();
@@ -143,6 +147,11 @@ __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(co
       int dofs = 0;
       asm volatile("" : "+s"(dofs));
       const cdptr Rt = opaque_uniform(Rp);
+      // per-lane base of the off-diagonal fragments read from R (NP = 256):
+      // kept in VGPRs, so each fragment address is this base plus a constant
+      // rather than a scalar base register per (b, kk, d)
+      const double* Rl = Rp + lq * RS + lr;
+      if (OG) asm volatile("" : "+v"(Rl));
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         // (all terms of the blocks c < b are in: solve the diagonal block b)
@@ -170,9 +179,9 @@ __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(co
             // the scalar loads of row j run at most two rows ahead of the
             // substitution (all of them at once would not fit the SGPRs)
             const cdptr Rj = (j < 2) ? Rt : opaque_after(Rp, v[j - 2]);
-            v[j] *= Rj[NP * NP + 16 * b + j];
+            v[j] *= Rj[RS * (RS - ROFF) + 16 * b + j];
 #pragma unroll
-            for (int k = j + 1; k < 16; ++k) v[k] = __builtin_fma(-v[j], Rj[(16 * b + j) * NP + 16 * b + k], v[k]);
+            for (int k = j + 1; k < 16; ++k) v[k] = __builtin_fma(-v[j], Rj[(16 * b + j) * RS + 16 * b + k], v[k]);
           }
           double2* dst = (double2*)(tt + lane * TM_LDT);
 #pragma unroll
@@ -196,7 +205,7 @@ __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(co
 #pragma unroll
           for (int d = b + 1; d < NB; ++d) {
             const int pr = d * (d - 1) / 2 + b;
-            const double a = OG ? -Rt[(16 * b + 4 * kk + lq) * NP + 16 * d + lr] : otab[dofs + (pr * 4 + kk) * 64 + lane];
+            const double a = OG ? -Rl[(16 * b + 4 * kk) * RS + 16 * d] : otab[dofs + (pr * 4 + kk) * 64 + lane];
 #pragma unroll
             for (int h = 0; h < HB; ++h) acc[h][d] = mfma_f64(a, acc[h][b][kk], acc[h][d]);
           }
@@ -277,6 +286,97 @@ __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(co
           }
       }
       __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// n in (128, 256]: the solve is split at column 128,
+//   W_1 = X_1 R_11^{-1},   W_2 = (X_2 - W_1 R_12) R_22^{-1},
+// the two solves on the 128-column kernel (R_11 and R_22 addressed inside the
+// 256 padded triangle) and the product between them here:
+//   C_2 = X_2 - W_1 R_12  on v_mfma_f64_16x16x4_f64, written as
+//   C_2^T = X_2^T - R_12^T W_1^T, with -R_12^T in LDS as A fragments and W_1^T
+//   streamed in the B layout; each entry takes its 128 terms in ascending
+//   order. 512 threads, 32 rows per wave, 256-row tiles.
+// (Splitting keeps the off-diagonal fragments of the solves in LDS and the
+// diagonal substitutions on 32 lanes; the one-kernel 256-column form had to
+// read them through the cache one wave-fragment at a time.)
+// ---------------------------------------------------------------------------
+constexpr int GS_THREADS = 512;
+constexpr int GS_TILE = 256;
+
+template <int ND>
+constexpr size_t gemm_sub_lds() {
+  return (size_t)32 * ND * 64 * sizeof(double);
+}
+
+template <int ND>
+__global__ __launch_bounds__(GS_THREADS) void k_tall_gemm_sub(const double* X2, int64_t ldx, int64_t m, int n2,
+                                                              const double* W1, int64_t ldw1,
+                                                              const double* __restrict__ R12, int ldr, double* W2,
+                                                              int64_t ldw2, int64_t ntiles, const int32_t* info) {
+  if (info_failed(info)) return;
+  extern __shared__ __align__(16) unsigned char gs_smem[];
+  double* atab = (double*)gs_smem;  // [kk][d][lane] = -R12[4 kk + l/16][16 d + l%16]
+  constexpr int HB = 2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  for (int e = tid; e < 32 * ND * 64; e += GS_THREADS) {
+    const int l = e & 63, d = (e >> 6) % ND, kk = (e >> 6) / ND;
+    const int col = 16 * d + (l & 15);
+    atab[e] = (col < n2) ? -R12[(int64_t)(4 * kk + (l >> 4)) * ldr + col] : 0.0;
+  }
+  __syncthreads();
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t row0 = t * GS_TILE + wave * 32;
+    f64x4 acc[HB][ND];
+    // C = X_2 in the output layout: lane l, register r holds row l%16, column 16 d + l/16 + 4 r
+#pragma unroll
+    for (int h = 0; h < HB; ++h) {
+      const int64_t row = row0 + 16 * h + lr;
+      const bool live = row < m;
+      const uint32_t voff = (uint32_t)(row + (int64_t)lq * ldx);
+#pragma unroll
+      for (int d = 0; d < ND; ++d)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int col = 16 * d + lq + 4 * r;
+          const double* cb = X2 + (int64_t)(16 * d + 4 * r) * ldx;
+          acc[h][d][r] = (live && col < n2) ? __builtin_nontemporal_load(cb + voff) : 0.0;
+        }
+    }
+#pragma unroll 2
+    for (int kk = 0; kk < 32; ++kk) {
+      // B fragment: lane l holds W_1[row l%16][4 kk + l/16]
+      double b[HB];
+      const double* wb = W1 + (int64_t)(4 * kk) * ldw1;
+#pragma unroll
+      for (int h = 0; h < HB; ++h) {
+        const int64_t row = row0 + 16 * h + lr;
+        b[h] = (row < m) ? __builtin_nontemporal_load(wb + (uint32_t)(row + (int64_t)lq * ldw1)) : 0.0;
+      }
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        const double a = atab[(kk * ND + d) * 64 + lane];
+#pragma unroll
+        for (int h = 0; h < HB; ++h) acc[h][d] = mfma_f64(a, b[h], acc[h][d]);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < HB; ++h) {
+      const int64_t row = row0 + 16 * h + lr;
+      if (row < m) {
+        const uint32_t voff = (uint32_t)(row + (int64_t)lq * ldw2);
+#pragma unroll
+        for (int d = 0; d < ND; ++d)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int col = 16 * d + lq + 4 * r;
+            double* cb = W2 + (int64_t)(16 * d + 4 * r) * ldw2;
+            if (col < n2) __builtin_nontemporal_store(acc[h][d][r], cb + voff);
+          }
+      }
     }
   }
 }
@@ -457,7 +557,30 @@ static hipError_t launch_tp(const TallPlan& p, const double* X, int64_t ldx, int
   }
   // n > 64: blocked substitution on the matrix cores (no fused Gram), then
   // the Gram kernel over W (or X)
-  if (trsm) {
+  if (trsm && NP == 256) {
+    if (!write) return hipErrorInvalidValue;
+    // split at column 128: W_1 = X_1 R_11^{-1}; C_2 = X_2 - W_1 R_12; W_2 = C_2 R_22^{-1}
+    const int64_t nt = (m + tm_tile(128) - 1) / tm_tile(128);
+    dim3 tgrid((unsigned)(p.gx_solve < nt ? p.gx_solve : nt));
+    const int n2 = (int)n - 128;
+    hipLaunchKernelGGL((k_tall_mfma<128, true, false, true, 256, 0>), tgrid, block, 0, st, X, ldx, m, 128, Rp, W, ldw,
+                       nullptr, nt, info, nullptr, nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    constexpr size_t glds = gemm_sub_lds<8>();
+    e = hipFuncSetAttribute((const void*)k_tall_gemm_sub<8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)glds);
+    if (e != hipSuccess) return e;
+    const int64_t ntg = (m + GS_TILE - 1) / GS_TILE;
+    dim3 ggrid((unsigned)(ntg < 256 ? ntg : 256));
+    hipLaunchKernelGGL(k_tall_gemm_sub<8>, ggrid, dim3(GS_THREADS), glds, st, X + 128 * ldx, ldx, m, n2, W, ldw,
+                       Rp + 128, 256, W + 128 * ldw, ldw, ntg, info);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_tall_mfma<128, true, false, true, 256, 128>), tgrid, block, 0, st, W + 128 * ldw, ldw, m, n2,
+                       Rp + 128 * 256 + 128, W + 128 * ldw, ldw, nullptr, nt, info, nullptr, nullptr);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  } else if (trsm) {
     if (!write) return hipErrorInvalidValue;
     const int64_t nt = (m + tm_tile(NP) - 1) / tm_tile(NP);
     dim3 tgrid((unsigned)(p.gx < nt ? p.gx : nt));
