@@ -382,16 +382,28 @@ __global__ __launch_bounds__(GS_THREADS) void k_tall_gemm_sub(const double* X2, 
 }
 
 // ---------------------------------------------------------------------------
-// n > 64: Gram partials of W over 32-row LDS tiles. The upper 16x16 blocks
-// are split by block column: workgroup row y and wave w own block columns
-// jb = 8 y + w + 4 jj (jj = 0, 1), so each wave keeps at most 2 NP/16
-// accumulators; gridDim.y = NP / 128.
+// n > 64: Gram partials of W on the FP64 matrix cores. The NB (NB + 1) / 2
+// upper 16 x 16 blocks are dealt round-robin to the NW waves of a workgroup
+// (wave w owns blocks w, w + NW, ...), so each block lives in one wave's
+// accumulators and the waves' loads are balanced; 32-row tiles of all NP
+// columns are double-buffered through LDS (column-major, stride 33). NW = 4
+// for NP = 128 (9 blocks per wave), NW = 8 for NP = 256 (17 blocks).
 // ---------------------------------------------------------------------------
 template <int NP>
-__global__ __launch_bounds__(TP_THREADS) void k_gram_big(const double* __restrict__ W, int64_t ldw, int64_t m, int n,
-                                                         double* __restrict__ Gpart, int64_t ntiles32,
-                                                         const int32_t* info, const TallJob* __restrict__ jobs,
-                                                         const BatchItem* __restrict__ items) {
+constexpr int gram_waves() {
+  return NP > 128 ? 8 : 4;
+}
+template <int NP>
+constexpr size_t gram_lds() {
+  return (size_t)2 * NP * TP_LDW * sizeof(double);
+}
+
+template <int NP>
+__global__ __launch_bounds__(64 * gram_waves<NP>()) void k_gram_bal(const double* __restrict__ W, int64_t ldw,
+                                                                     int64_t m, int n, double* __restrict__ Gpart,
+                                                                     int64_t ntiles32, const int32_t* info,
+                                                                     const TallJob* __restrict__ jobs,
+                                                                     const BatchItem* __restrict__ items) {
   int64_t wg = blockIdx.x, nwg = gridDim.x;
   if (items) {  // batched: the Gram of the job's W (its X when it has no solve)
     const BatchItem it = items[blockIdx.x];
@@ -400,55 +412,80 @@ __global__ __launch_bounds__(TP_THREADS) void k_gram_big(const double* __restric
     info = j.info, wg = it.wg, nwg = it.nwg;
   }
   if (info_failed(info)) return;
-  constexpr int NBK = NP / 16;
-  constexpr int JPW = 2;
-  constexpr int MAXB = JPW * NBK;
-  __shared__ double lds[NP * TP_LDW];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int jbase = 8 * (int)blockIdx.y + wave;
-  f64x4 acc[MAXB];
+  constexpr int NW = gram_waves<NP>(), NT = 64 * NW, NB = NP / 16, NBLK = NB * (NB + 1) / 2;
+  constexpr int PB = (NBLK + NW - 1) / NW;  // blocks per wave (at most)
+  constexpr int PER = 32 * NP / NT;         // tile entries loaded per thread
+  extern __shared__ __align__(16) unsigned char gb_smem[];
+  double* lds = (double*)gb_smem;  // [2][NP][TP_LDW]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: block indices stay scalar
+  const int lr = lane & 15, lq = lane >> 4;
+  // this wave's blocks: (ib, jb) of upper-block index g = wave + NW q, ib <= jb,
+  // enumerated column by column
+  int bi[PB], bj[PB];
 #pragma unroll
-  for (int b = 0; b < MAXB; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
-
-  for (int64_t t = wg; t < ntiles32; t += nwg) {
-    // load 32 rows x NP columns: thread -> row (tid % 32), columns tid/32 + 8 k
-    const int lr = tid & 31, lc = tid >> 5;
-    const int64_t row = t * 32 + lr;
-#pragma unroll
-    for (int k = 0; k < NP / 8; ++k) {
-      const int c = lc + 8 * k;
-      lds[c * TP_LDW + lr] = (row < m && c < n) ? W[row + (int64_t)c * ldw] : 0.0;
+  for (int q = 0; q < PB; ++q) {
+    int g = wave + NW * q, jb = 0;
+    while (g > jb) {
+      g -= jb + 1;
+      ++jb;
     }
-    __syncthreads();
+    bi[q] = g;
+    bj[q] = jb;
+  }
+  f64x4 acc[PB];
 #pragma unroll
+  for (int q = 0; q < PB; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  // loader: thread -> row tid % 32, columns tid / 32 + (NT / 32) c
+  const int ldr = tid & 31, ldc = tid >> 5;
+  double pre[PER];
+  auto load = [&](int64_t t) {
+    const int64_t row = t * 32 + ldr;
+#pragma unroll
+    for (int c = 0; c < PER; ++c) {
+      const int col = ldc + (NT / 32) * c;
+      pre[c] = (row < m && col < n) ? __builtin_nontemporal_load(W + row + (int64_t)col * ldw) : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int c = 0; c < PER; ++c) lds[(buf * NP + ldc + (NT / 32) * c) * TP_LDW + ldr] = pre[c];
+  };
+  int64_t t = wg;
+  int buf = 0;
+  if (t < ntiles32) {
+    load(t);
+    store(0);
+  }
+  __syncthreads();
+  for (; t < ntiles32; t += nwg) {
+    const int64_t tn = t + nwg;
+    if (tn < ntiles32) load(tn);
+    const double* ws = lds + buf * NP * TP_LDW;
+#pragma unroll 1
     for (int kk = 0; kk < 8; ++kk) {
-      double f[NBK];
+      // fragment of column block c at K-step kk: lane l holds W[4 kk + l/16][16 c + l%16]
 #pragma unroll
-      for (int ib = 0; ib < NBK; ++ib) f[ib] = lds[(16 * ib + (lane & 15)) * TP_LDW + 4 * kk + (lane >> 4)];
-#pragma unroll
-      for (int jj = 0; jj < JPW; ++jj) {
-        const int jb = jbase + 4 * jj;
-        double fj = f[0];
-#pragma unroll
-        for (int q = 1; q < NBK; ++q)
-          if (q == jb) fj = f[q];
-#pragma unroll
-        for (int ib = 0; ib < NBK; ++ib)
-          if (ib <= jb) acc[jj * NBK + ib] = mfma_f64(f[ib], fj, acc[jj * NBK + ib]);
+      for (int q = 0; q < PB; ++q) {
+        if (wave + NW * q < NBLK) {
+          const double fa = ws[(16 * bi[q] + lr) * TP_LDW + 4 * kk + lq];
+          const double fb = ws[(16 * bj[q] + lr) * TP_LDW + 4 * kk + lq];
+          acc[q] = mfma_f64(fa, fb, acc[q]);
+        }
       }
     }
+    if (tn < ntiles32) store(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
-  for (int jj = 0; jj < JPW; ++jj) {
-    const int jb = jbase + 4 * jj;
-#pragma unroll
-    for (int ib = 0; ib < NBK; ++ib) {
-      if (ib > jb) continue;
+  for (int q = 0; q < PB; ++q) {
+    if (wave + NW * q < NBLK) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gi = 16 * ib + (lane >> 4) + 4 * r, gj = 16 * jb + (lane & 15);
-        Gpart[wg * NP * NP + gi + gj * NP] = acc[jj * NBK + ib][r];
+        const int gi = 16 * bi[q] + lq + 4 * r, gj = 16 * bj[q] + lr;
+        Gpart[wg * NP * NP + gi + gj * NP] = acc[q][r];
       }
     }
   }
@@ -529,7 +566,9 @@ TallPlan plan_tall(int64_t m, int64_t n, int gx_hint) {
   // 256 CUs: register bound), which also keeps the partials few; passes
   // without the Gram (lighter kernel, four per CU) use two rounds
   auto clampg = [&](int g) { return (int)(g > p.ntiles ? p.ntiles : (g < 1 ? 1 : g)); };
-  p.gx = clampg(gx_hint > 0 ? gx_hint : (p.np == 64 ? 512 : 1024));
+  // (n > 64: the Gram kernel keeps one workgroup of 8 waves per CU for n > 128,
+  // two of 4 waves for n <= 128)
+  p.gx = clampg(gx_hint > 0 ? gx_hint : (p.np == 64 ? 512 : p.np == 256 ? 256 : p.np == 128 ? 512 : 1024));
   p.gx_solve = clampg(gx_hint > 0 ? gx_hint : (p.fused_gram ? 2048 : 1024));
   const int gx = p.gx;
   // per-workgroup partials followed by the level-1 sums of the reduction
@@ -595,9 +634,13 @@ static hipError_t launch_tp(const TallPlan& p, const double* X, int64_t ldx, int
     const double* src = trsm ? W : X;
     const int64_t lds_ = trsm ? ldw : ldx;
     const int64_t nt32 = (m + 31) / 32;
-    dim3 ggrid(p.gx, NP / 128);
-    hipLaunchKernelGGL((k_gram_big<(NP > 64 ? NP : 128)>), ggrid, block, 0, st, src, lds_, m, (int)n, Gpart, nt32,
-                       info, nullptr, nullptr);
+    constexpr int NPG = NP > 64 ? NP : 128;
+    constexpr size_t glds = gram_lds<NPG>();
+    hipError_t e = hipFuncSetAttribute((const void*)k_gram_bal<NPG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)glds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_gram_bal<NPG>), dim3(p.gx), dim3(64 * gram_waves<NPG>()), glds, st, src, lds_, m, (int)n,
+                       Gpart, nt32, info, nullptr, nullptr);
     return hipGetLastError();
   }
   return hipSuccess;
@@ -663,8 +706,12 @@ static hipError_t launch_tall_batch_np(int n, bool trsm, bool gram, bool write, 
     if (e != hipSuccess) return e;
   }
   if (gram) {
-    dim3 ggrid((unsigned)nitems, NPB / 128);
-    hipLaunchKernelGGL((k_gram_big<NPB>), ggrid, block, 0, st, nullptr, 0, 0, n, nullptr, 0, nullptr, jobs, items);
+    constexpr size_t glds = gram_lds<NPB>();
+    hipError_t e = hipFuncSetAttribute((const void*)k_gram_bal<NPB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)glds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_gram_bal<NPB>), dim3((unsigned)nitems), dim3(64 * gram_waves<NPB>()), glds, st, nullptr, 0,
+                       0, n, nullptr, 0, nullptr, jobs, items);
     return hipGetLastError();
   }
   return hipSuccess;
