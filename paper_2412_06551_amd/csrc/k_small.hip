@@ -9,8 +9,11 @@
 //               right factor (LC2's R_1 = D S_c N) and product with an earlier
 //               factor (R_3 = R_2 R_1, R = R_4 R_3; eqs. C4, C8).
 // The working copy lives in LDS when it fits, else in a global scratch buffer
-// (same code through generic pointers). Threads form a 64 x 4 grid: tx walks
-// rows (contiguous in the column-major layout), ty walks columns.
+// (same code through generic pointers). Threads form a 64 x 16 grid: tx walks
+// rows (contiguous in the column-major layout), ty walks columns; the column
+// loops keep SD_U loads in flight per thread (the working copy is in L2 when
+// it does not fit LDS, and one outstanding load per thread left them latency
+// bound).
 #include <float.h>
 #include <limits.h>
 
@@ -19,13 +22,15 @@
 
 namespace rclupp {
 
-constexpr int SD_THREADS = 256;
+constexpr int SD_THREADS = 1024;
+constexpr int SD_WAVES = SD_THREADS / 64;
+constexpr int SD_U = 4;  // independent loads in flight per thread in the column loops
 constexpr size_t SD_LDS_LIMIT = 150 * 1024;
 
 struct ArgMaxSh {
-  double v[4];
-  int i[4];
-  int bad[4];
+  double v[SD_WAVES];
+  int i[SD_WAVES];
+  int bad[SD_WAVES];
   int p;
   int pbad;
   double pv;
@@ -72,7 +77,7 @@ __device__ void block_argmax(double& v, int& idx, int& bad, ArgMaxSh* sh) {
 }
 
 template <typename T>
-__device__ T block_sum(T v, T* sh /* [4] */) {
+__device__ T block_sum(T v, T* sh /* [SD_WAVES] */) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -113,7 +118,7 @@ __global__ __launch_bounds__(SD_THREADS) void k_precond(const double* __restrict
                                                         int32_t stage_qr) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ ArgMaxSh amx;
-  __shared__ T red[4];
+  __shared__ T red[SD_WAVES];
   __shared__ T sc_tau, sc_scal;
   __shared__ int fail;
   if (info_failed(info)) return;
@@ -187,9 +192,22 @@ __global__ __launch_bounds__(SD_THREADS) void k_precond(const double* __restrict
       const T piv = A[k + k * s];
       for (int i = k + 1 + tid; i < s; i += SD_THREADS) A[i + k * s] = A[i + k * s] / piv;
       __syncthreads();
-      for (int j = k + 1 + ty; j < n; j += 4) {
+      for (int j = k + 1 + ty; j < n; j += SD_WAVES) {
         const T akj = A[k + j * s];
-        for (int i = k + 1 + tx; i < s; i += 64) A[i + j * s] = A[i + j * s] - A[i + k * s] * akj;
+        T* cj = A + (size_t)j * s;
+        const T* ck = A + (size_t)k * s;
+        int i = k + 1 + tx;
+        for (; i + 64 * (SD_U - 1) < s; i += 64 * SD_U) {
+          T a[SD_U], l[SD_U];
+#pragma unroll
+          for (int u = 0; u < SD_U; ++u) {
+            a[u] = cj[i + 64 * u];
+            l[u] = ck[i + 64 * u];
+          }
+#pragma unroll
+          for (int u = 0; u < SD_U; ++u) cj[i + 64 * u] = a[u] - l[u] * akj;
+        }
+        for (; i < s; i += 64) cj[i] = cj[i] - ck[i] * akj;
       }
       __syncthreads();
     }
@@ -240,19 +258,43 @@ __global__ __launch_bounds__(SD_THREADS) void k_precond(const double* __restrict
     for (int i = k + 1 + tid; i < s; i += SD_THREADS) A[i + k * s] *= scal;
     __syncthreads();
     // wv[j] = A[k][j] + sum_{i>k} v_i A[i][j]; one wave per column (strided)
-    for (int j = k + 1 + ty; j < n; j += 4) {
-      T acc = T(0);
-      for (int i = k + 1 + tx; i < s; i += 64) acc += A[i + k * s] * A[i + j * s];
+    for (int j = k + 1 + ty; j < n; j += SD_WAVES) {
+      const T* cj = A + (size_t)j * s;
+      const T* ck = A + (size_t)k * s;
+      T part[SD_U];
+#pragma unroll
+      for (int u = 0; u < SD_U; ++u) part[u] = T(0);
+      int i = k + 1 + tx;
+      for (; i + 64 * (SD_U - 1) < s; i += 64 * SD_U)
+#pragma unroll
+        for (int u = 0; u < SD_U; ++u) part[u] += ck[i + 64 * u] * cj[i + 64 * u];
+      for (; i < s; i += 64) part[0] += ck[i] * cj[i];
+      T acc = part[0];
+#pragma unroll
+      for (int u = 1; u < SD_U; ++u) acc += part[u];
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
       if (tx == 0) wv[j] = A[k + j * s] + acc;
     }
     __syncthreads();
-    for (int j = k + 1 + ty; j < n; j += 4) {
+    for (int j = k + 1 + ty; j < n; j += SD_WAVES) {
       const T tw = tau * wv[j];
-      for (int i = k + tx; i < s; i += 64) {
-        const T v = (i == k) ? T(1) : A[i + k * s];
-        A[i + j * s] -= tw * v;
+      T* cj = A + (size_t)j * s;
+      const T* ck = A + (size_t)k * s;
+      int i = k + tx;
+      for (; i + 64 * (SD_U - 1) < s; i += 64 * SD_U) {
+        T a[SD_U], v[SD_U];
+#pragma unroll
+        for (int u = 0; u < SD_U; ++u) {
+          a[u] = cj[i + 64 * u];
+          v[u] = (i + 64 * u == k) ? T(1) : ck[i + 64 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < SD_U; ++u) cj[i + 64 * u] = a[u] - tw * v[u];
+      }
+      for (; i < s; i += 64) {
+        const T v = (i == k) ? T(1) : ck[i];
+        cj[i] -= tw * v;
       }
     }
     __syncthreads();
@@ -261,9 +303,19 @@ __global__ __launch_bounds__(SD_THREADS) void k_precond(const double* __restrict
   // R_1 = R_0 N (upper x upper), then the sign fix D
   for (int e = tid; e < n * n; e += SD_THREADS) {
     const int i = e % n, j = e / n;
-    T acc = T(0);
-    if (i <= j)
-      for (int k = i; k <= j; ++k) acc += A[i + k * s] * N[k + j * n];
+    T part[SD_U];
+#pragma unroll
+    for (int u = 0; u < SD_U; ++u) part[u] = T(0);
+    if (i <= j) {
+      int k = i;
+      for (; k + SD_U - 1 <= j; k += SD_U)
+#pragma unroll
+        for (int u = 0; u < SD_U; ++u) part[u] += A[i + (size_t)(k + u) * s] * N[k + u + j * n];
+      for (; k <= j; ++k) part[0] += A[i + (size_t)k * s] * N[k + j * n];
+    }
+    T acc = part[0];
+#pragma unroll
+    for (int u = 1; u < SD_U; ++u) acc += part[u];
     R[e] = acc;
   }
   __syncthreads();
@@ -372,9 +424,21 @@ __global__ __launch_bounds__(SD_THREADS) void k_chol(const double* __restrict__ 
     for (int j = k + 1 + tid; j < n; j += SD_THREADS) A[k + j * n] = A[k + j * n] / rkk;
     if (tid == 0) A[k + k * n] = rkk;
     __syncthreads();
-    for (int j = k + 1 + ty; j < n; j += 4) {
+    for (int j = k + 1 + ty; j < n; j += SD_WAVES) {
       const double akj = A[k + j * n];
-      for (int i = k + 1 + tx; i <= j; i += 64) A[i + j * n] = A[i + j * n] - A[k + i * n] * akj;
+      double* cj = A + (size_t)j * n;
+      int i = k + 1 + tx;
+      for (; i + 64 * (SD_U - 1) <= j; i += 64 * SD_U) {
+        double a[SD_U], l[SD_U];
+#pragma unroll
+        for (int u = 0; u < SD_U; ++u) {
+          a[u] = cj[i + 64 * u];
+          l[u] = A[k + (size_t)(i + 64 * u) * n];
+        }
+#pragma unroll
+        for (int u = 0; u < SD_U; ++u) cj[i + 64 * u] = a[u] - l[u] * akj;
+      }
+      for (; i <= j; i += 64) cj[i] = cj[i] - A[k + (size_t)i * n] * akj;
     }
     __syncthreads();
   }
@@ -382,9 +446,17 @@ __global__ __launch_bounds__(SD_THREADS) void k_chol(const double* __restrict__ 
   if (Npost) {
     for (int e = tid; e < n * n; e += SD_THREADS) {
       const int i = e % n, j = e / n;
-      double acc = 0.0;
-      if (i <= j)
-        for (int k = i; k <= j; ++k) acc += A[i + k * n] * Npost[k + (int64_t)j * ldnp];
+      double part[SD_U] = {};
+      if (i <= j) {
+        int k = i;
+        for (; k + SD_U - 1 <= j; k += SD_U)
+#pragma unroll
+          for (int u = 0; u < SD_U; ++u) part[u] += A[i + (k + u) * n] * Npost[k + u + (int64_t)j * ldnp];
+        for (; k <= j; ++k) part[0] += A[i + k * n] * Npost[k + (int64_t)j * ldnp];
+      }
+      double acc = part[0];
+#pragma unroll
+      for (int u = 1; u < SD_U; ++u) acc += part[u];
       Tm[e] = acc;
     }
     __syncthreads();
@@ -417,9 +489,17 @@ __global__ __launch_bounds__(SD_THREADS) void k_chol(const double* __restrict__ 
     // Rout = R * Rprev, Rprev a padded triangle (ld np)
     for (int e = tid; e < n * n; e += SD_THREADS) {
       const int i = e % n, j = e / n;
-      double acc = 0.0;
-      if (i <= j)
-        for (int k = i; k <= j; ++k) acc += A[i + k * n] * Rprev[(int64_t)k * np + j];
+      double part[SD_U] = {};
+      if (i <= j) {
+        int k = i;
+        for (; k + SD_U - 1 <= j; k += SD_U)
+#pragma unroll
+          for (int u = 0; u < SD_U; ++u) part[u] += A[i + (k + u) * n] * Rprev[(int64_t)(k + u) * np + j];
+        for (; k <= j; ++k) part[0] += A[i + k * n] * Rprev[(int64_t)k * np + j];
+      }
+      double acc = part[0];
+#pragma unroll
+      for (int u = 1; u < SD_U; ++u) acc += part[u];
       if (rout_user)
         Rout[e] = acc;
       else

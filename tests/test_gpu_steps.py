@@ -89,7 +89,8 @@ def test_sketch_leading_dimension():
 
 
 # ---------------------------------------------------------------- preconditioner
-@pytest.mark.parametrize("s,n,seed", [(64, 32, 0), (128, 64, 1), (100, 50, 2), (16, 16, 3), (256, 128, 4)])
+@pytest.mark.parametrize("s,n,seed", [(64, 32, 0), (128, 64, 1), (100, 50, 2), (16, 16, 3), (256, 128, 4),
+                                      (300, 64, 5), (512, 200, 6)])
 @pytest.mark.parametrize("kappa", [1e2, 1e8])
 def test_precond_lu_householder(s, n, seed, kappa):
     x = make_svd(4 * s, n, kappa, seed=seed)
@@ -219,7 +220,7 @@ def test_trsm_in_place_and_ld():
 
 
 # ---------------------------------------------------------------- Cholesky
-@pytest.mark.parametrize("n", [1, 16, 50, 64, 128, 256])
+@pytest.mark.parametrize("n", [1, 16, 50, 64, 128, 200, 256])
 def test_chol_matches_oracle(n):
     b = np.random.default_rng(n).standard_normal((3 * n + 5, n))
     g = np.asfortranarray(b.T @ b)
