@@ -225,7 +225,18 @@ def bench_batched(lib, reps=3):
     for i in range(0, len(man), 64):  # a sample of the results
         o, r = gpu_accuracy(Xs[i], Qs[i], Rs[i])
         worst_orth, worst_res = max(worst_orth, o), max(worst_res, r)
+    # the same problems as one plain FP64 RCLUPP call each, on the same stream
+    for X, p in zip(Xs[:4], man[:4]):
+        lib.qr(X, alg="rclupp", s=2 * p["n"], seed=p["seed"])
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for X, p in zip(Xs, man):
+        lib.qr(X, alg="rclupp", s=2 * p["n"], seed=p["seed"])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    seq_ms = e0.elapsed_time(e1)
     return {"problems": len(man), "ms": round(ms, 3), "qrs_per_s": round(len(man) / (ms / 1e3), 1),
+            "sequential_ms": round(seq_ms, 3), "speedup_vs_sequential": round(seq_ms / ms, 2),
             "GB_s": round(by / (ms / 1e3) / 1e9, 1), "failed": int((info[:, 0] != 0).sum()),
             "sample_worst_orth": worst_orth, "sample_worst_rel_res": worst_res,
             "workload": "512 x RCLUPP, batch_manifest(seed 0), U = normalised Gaussian columns",

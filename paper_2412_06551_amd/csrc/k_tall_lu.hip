@@ -96,17 +96,50 @@ __global__ __launch_bounds__(LU_THREADS) void k_lu_pivot(double* __restrict__ M,
                                                          int32_t* __restrict__ perm, const LuPartial* __restrict__ part,
                                                          int nparts, double* __restrict__ prow, int32_t* info) {
   __shared__ int s_p, s_fail;
+  __shared__ double rv[LU_THREADS / 64];
+  __shared__ int ri[LU_THREADS / 64], rb[LU_THREADS / 64];
   if (info_failed(info)) return;
-  if (threadIdx.x == 0) {
-    double bv = part[0].v;
-    int bi = part[0].idx, bb = part[0].bad;
-    for (int w = 1; w < nparts; ++w) {
+  // reduce the partials in parallel (max |v|, lowest index on ties, OR of bad:
+  // the result does not depend on the order)
+  {
+    double bv = -1.0;
+    int bi = INT_MAX, bb = 0;
+    for (int w = threadIdx.x; w < nparts; w += LU_THREADS) {
       const LuPartial q = part[w];
       if (q.v > bv || (q.v == bv && q.idx < bi)) {
         bv = q.v;
         bi = q.idx;
       }
       bb |= q.bad;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(bv, off);
+      const int oi = __shfl_xor(bi, off);
+      const int ob = __shfl_xor(bb, off);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+      bb |= ob;
+    }
+    if (lane == 0) {
+      rv[wave] = bv;
+      ri[wave] = bi;
+      rb[wave] = bb;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double bv = rv[0];
+    int bi = ri[0], bb = rb[0];
+    for (int w = 1; w < LU_THREADS / 64; ++w) {
+      if (rv[w] > bv || (rv[w] == bv && ri[w] < bi)) {
+        bv = rv[w];
+        bi = ri[w];
+      }
+      bb |= rb[w];
     }
     s_fail = 0;
     if (bb) {
