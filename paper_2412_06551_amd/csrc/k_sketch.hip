@@ -30,16 +30,20 @@ namespace rclupp {
 constexpr int SK_TK = 64;  // tall rows per tile
 constexpr int SK_THREADS = 256;
 
-template <int SM, int NN>
+template <int SM, int NN, int TK = SK_TK, bool WM = false>
 struct SketchLds {
   static constexpr int LDX = NN + 1;
-  static constexpr int TILE = SK_TK * LDX;
-  static constexpr int RED = SM * NN;
+  static constexpr int TILE = TK * LDX;
+  static constexpr int RED = WM ? 0 : SM * NN;
   static constexpr int SIZE = (2 * TILE > RED) ? 2 * TILE : RED;
 };
 
-template <int SM, int NN, bool WM>
-__global__ __launch_bounds__(SK_THREADS) void k_sketch_f64(const double* __restrict__ X, int64_t m, int n, int64_t ld,
+// NW waves per workgroup: 4, or 2 with wave-owned rows and 32-row tiles (a
+// workgroup then covers 2 SM sketch rows with half the registers and a
+// quarter of the LDS, so four workgroups and two waves per SIMD share a CU)
+constexpr int sketch_f64_tk(int nw) { return nw == 2 ? 32 : SK_TK; }
+template <int SM, int NN, bool WM, int NW>
+__global__ __launch_bounds__(64 * NW) void k_sketch_f64(const double* __restrict__ X, int64_t m, int n, int64_t ld,
                                                            int64_t ntiles, uint64_t seed, double* __restrict__ Ypart,
                                                            int64_t s_pad, int64_t n_pad, const int32_t* info,
                                                            const SketchJob* __restrict__ jobs,
@@ -52,13 +56,17 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch_f64(const double* __restr
     wg = it.wg, nwg = it.nwg;
   }
   if (info_failed(info)) return;
-  constexpr int MB = SM / 16, NB = NN / 16, LDX = SketchLds<SM, NN>::LDX, TILE = SketchLds<SM, NN>::TILE;
-  constexpr int CPT = NN / 4;  // tile columns loaded per thread
-  __shared__ double lds[SketchLds<SM, NN>::SIZE];
+  constexpr int TK = sketch_f64_tk(NW);
+  using L = SketchLds<SM, NN, TK, WM>;
+  constexpr int MB = SM / 16, NB = NN / 16, LDX = L::LDX, TILE = L::TILE;
+  static_assert(WM || NW == 4, "the row-split form uses four waves");
+  constexpr int CG = 64 * NW / TK;  // loader column groups
+  constexpr int CPT = NN / CG;      // tile columns loaded per thread
+  __shared__ double lds[L::SIZE];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int sg = blockIdx.y, col0 = blockIdx.z * NN;
-  const int lr = tid & 63, lc0 = (tid >> 6) * CPT;  // loader: row, first column
+  const int lr = tid % TK, lc0 = (tid / TK) * CPT;  // loader: row, first column
 
   f64x4 acc[MB][NB];
 #pragma unroll
@@ -68,7 +76,7 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch_f64(const double* __restr
 
   double pre[CPT];
   auto load_tile = [&](int64_t t) {
-    const int64_t row = t * SK_TK + lr;
+    const int64_t row = t * TK + lr;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       const int col = col0 + lc0 + c;
@@ -82,7 +90,7 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch_f64(const double* __restr
 
   // A-operand slot of this lane: i = lane % 16 = 4c + t, K row = lane / 16
   const int ai = lane & 15, ak = lane >> 4;
-  const int grp = WM ? 4 * sg + wave : sg;  // this wave's group of SM sketch rows
+  const int grp = WM ? NW * sg + wave : sg;  // this wave's group of SM sketch rows
   const uint32_t qbase = (uint32_t)((grp * SM) / 4 + 4 * (ai >> 2) + (ai & 3));
 
   int64_t t = wg;
@@ -97,9 +105,9 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch_f64(const double* __restr
     if (tn < ntiles) load_tile(tn);
     const double* xs = lds + buf * TILE;
 #pragma unroll 1
-    for (int ks = 0; ks < (WM ? 16 : 4); ++ks) {
+    for (int ks = 0; ks < (WM ? TK / 4 : 4); ++ks) {
       const int rloc = (WM ? 0 : 16 * wave) + 4 * ks + ak;
-      const int64_t j = t * SK_TK + rloc;
+      const int64_t j = t * TK + rloc;
       double b[NB];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) b[nb] = xs[rloc * LDX + 16 * nb + ai];
@@ -430,12 +438,20 @@ SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int gx_hint) {
   while (p.sm * 2 <= max_sm && p.s_pad % (p.sm * 2) == 0) p.sm *= 2;
   // four or more row groups: give each wave its own group (X read 4x less)
   p.wm = p.s_pad % (4 * p.sm) == 0;
-  p.gy = (int)(p.s_pad / (p.wm ? 4 * p.sm : p.sm));
+  p.nw = 4;
+  if (prec == 0 && !p.wm && p.sm >= 128 && p.s_pad % 128 == 0) {
+    // FP64 with two 64-row groups' worth of rows: 64-row groups owned by the
+    // waves instead (a 128-row group needs all 512 registers of a wave)
+    p.sm = 64;
+    p.wm = true;
+    p.nw = (p.s_pad % 256 == 0) ? 4 : 2;
+  }
+  p.gy = (int)(p.s_pad / (p.wm ? p.nw * p.sm : p.sm));
   p.gz = (int)((n + p.nn - 1) / p.nn);
   p.n_pad = (int64_t)p.gz * p.nn;
-  const int tk = (prec == 2) ? 128 : SK_TK;  // BF16 tiles are 128 rows
+  const int tk = (prec == 2) ? 128 : (prec == 0 ? sketch_f64_tk(p.nw) : SK_TK);  // BF16 tiles are 128 rows
   p.ntiles = (m + tk - 1) / tk;
-  int gx = gx_hint > 0 ? gx_hint : 512;
+  int gx = gx_hint > 0 ? gx_hint : 512 * 4 / p.nw;  // 2048 waves in all
   const int per_chunk = p.gy * p.gz;
   if (per_chunk > 1) gx = (gx + per_chunk - 1) / per_chunk;
   if (gx < 1) gx = 1;
@@ -451,8 +467,11 @@ static hipError_t launch_sk_wm(const SketchPlan& p, const double* X, int64_t m, 
                                int prec, double* Ypart, const int32_t* info, const SketchJob* jobs,
                                const BatchItem* items, int nitems, hipStream_t st) {
   dim3 grid(items ? (unsigned)nitems : (unsigned)p.gx, p.gy, p.gz);
-  if (prec == 0)
-    hipLaunchKernelGGL((k_sketch_f64<SM, NN, WM>), grid, dim3(SK_THREADS), 0, st, X, m, (int)n, ld, p.ntiles, seed,
+  if (prec == 0 && WM && p.nw == 2)
+    hipLaunchKernelGGL((k_sketch_f64<SM, NN, WM, (WM ? 2 : 4)>), grid, dim3(128), 0, st, X, m, (int)n, ld, p.ntiles,
+                       seed, Ypart, p.s_pad, p.n_pad, info, jobs, items);
+  else if (prec == 0)
+    hipLaunchKernelGGL((k_sketch_f64<SM, NN, WM, 4>), grid, dim3(SK_THREADS), 0, st, X, m, (int)n, ld, p.ntiles, seed,
                        Ypart, p.s_pad, p.n_pad, info, jobs, items);
   else if (prec == 1)
     hipLaunchKernelGGL((k_sketch_lp<SM, NN, false, WM>), grid, dim3(SK_THREADS), 0, st, X, m, (int)n, ld, p.ntiles,

@@ -72,8 +72,9 @@ struct SketchPlan {
   int nn;          // columns per workgroup (16, 32, 64 or 128)
   int gx;          // row-chunk workgroups
   int gy, gz;      // sketch-row groups, column groups
-  bool wm;         // each wave owns its own sm sketch rows (a workgroup covers 4 sm)
-  int64_t s_pad;   // padded sketch rows (gy * sm, times 4 when wm)
+  bool wm;         // each wave owns its own sm sketch rows (a workgroup covers nw sm)
+  int nw;          // waves per workgroup (4; 2 for the FP64 form with wave-owned rows)
+  int64_t s_pad;   // padded sketch rows (gy * sm, times nw when wm)
   int64_t n_pad;   // padded columns (gz * nn)
   int64_t ntiles;  // 64-row tiles of the tall operand
   size_t part_bytes;  // bytes of the per-workgroup partial sums
