@@ -90,13 +90,16 @@ __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(co
   constexpr int NOFF = NB * (NB - 1) / 2;      // off-diagonal block pairs c < b
   constexpr int NBLK = NB * (NB + 1) / 2;      // upper Gram blocks
   constexpr int HB = tm_hb(NP), RW = 16 * HB;           // 16-row blocks and rows per wave
-  constexpr int TTAB = TRSM ? 4 * RW * TM_LDT : 1;       // per-wave transpose regions
+  // per-wave transpose regions; with the Gram they share the per-wave Gram
+  // staging regions (used after the solve of the tile), which are larger
+  constexpr bool SHARE = GRAM && NP * TM_LDG >= RW * TM_LDT;
+  constexpr int TTAB = (TRSM && !SHARE) ? 4 * RW * TM_LDT : 1;
   constexpr int GST = GRAM ? ((4 * NP * TM_LDG > NBLK * 256) ? 4 * NP * TM_LDG : NBLK * 256) : 1;
   // off-diagonal A fragments: an LDS table for NP <= 64, read from R (L2) above
   constexpr bool OG = NP > 128;
   constexpr int OTAB = (TRSM && NOFF > 0 && !OG) ? NOFF * 4 * 64 : 1;  // [pair][kk][lane]
   __shared__ double otab[OTAB];
-  __shared__ double gst[GST];
+  __shared__ __align__(16) double gst[GST];
   __shared__ __align__(16) double ttab[TTAB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lq = lane >> 4;
@@ -157,7 +160,7 @@ __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(co
         // (all terms of the blocks c < b are in: solve the diagonal block b)
         // transpose so that lane l < RW holds row l's 16 entries, substitute in
         // registers, transpose back
-        double* tt = ttab + wave * RW * TM_LDT;
+        double* tt = SHARE ? gst + wave * NP * TM_LDG : ttab + wave * RW * TM_LDT;
 #pragma unroll
         for (int h = 0; h < HB; ++h)
 #pragma unroll
