@@ -115,7 +115,8 @@ constexpr int dn_ld() {
 }
 template <typename T, int A, int CS>
 constexpr size_t precond_reg_lds() {
-  return (CS == 1 ? 2 * 64 * dn_ld<1>() * sizeof(double) : 0) + 2 * 16 * A * sizeof(T) + 2 * 16 * A * sizeof(int);
+  return (CS == 1 ? 2 * 64 * dn_ld<1>() * sizeof(double) : 0) + 2 * 16 * A * sizeof(T) +
+         (A > 8 ? 2 * 16 * A * sizeof(int) : 0);
 }
 size_t precond_reg_scratch_bytes() { return 2 * (size_t)128 * dn_ld<2>() * sizeof(double); }
 
@@ -134,8 +135,15 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
   double* R0l = (CS == 1) ? (double*)dn_smem : gtab;  // R_0(i, j) at i*LD + j
   double* Nl = R0l + NT * LD;                           // N(i, j) at i*LD + j
   T* vb = (T*)(dn_smem + (CS == 1 ? 2 * NT * LD * sizeof(double) : 0));  // [2][SR] step vectors
-  int* posl = (int*)(vb + 2 * SR);  // position of row r at (r%16)*A + r/16
-  int* rowl = posl + SR;            // row at position p
+  // Row positions (lazy pivoting: rows never move, positions trade). Up to 128
+  // rows every thread keeps the positions of its rows tr + 16 a in registers
+  // (two 16-bit positions per register) and applies each trade itself; the
+  // 256-row tiles are at the register limit and keep them in LDS instead
+  // (position of row r at (r%16)*A + r/16, and the row at each position),
+  // updated by the pivot's owner.
+  constexpr bool PREG = A <= 8;
+  int* posl = (int*)(vb + 2 * SR);
+  int* rowl = posl + SR;
   __shared__ int bc_row[2];
   __shared__ T bc_tau[2];
   __shared__ int bc_fail, bc_min;
@@ -153,10 +161,21 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
       x[c][a] = (row < s && col < n) ? (T)Y[row + (int64_t)col * s] : T(0);
     }
   for (int e = tid; e < 2 * NT * LD; e += DN_THREADS) R0l[e] = 0.0;  // R0l and Nl
-  for (int r = tid; r < SR; r += DN_THREADS) {
-    posl[(r & 15) * A + (r >> 4)] = r;
-    rowl[r] = r;
-  }
+  uint32_t posw[PREG ? (A + 1) / 2 : 1];
+#pragma unroll
+  for (int h = 0; h < (PREG ? (A + 1) / 2 : 1); ++h)
+    posw[h] = (uint32_t)(tr + 32 * h) | ((uint32_t)(tr + 32 * h + 16) << 16);
+  if (!PREG)
+    for (int r = tid; r < SR; r += DN_THREADS) {
+      posl[(r & 15) * A + (r >> 4)] = r;
+      rowl[r] = r;
+    }
+  auto pos = [&](int a) -> int {
+    if constexpr (PREG)
+      return (int)((posw[a >> 1] >> (16 * (a & 1))) & 0xFFFFu);
+    else
+      return posl[tr * A + a];
+  };
   if (tid == 0) {
     bc_fail = 0;
     bc_min = INT_MAX;
@@ -172,17 +191,17 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
         const int buf = k & 1;
         if (wave == (kk >> 2)) {
           // pivot search over the rows at positions >= k of column k
-          int pos[A];
+          int pp[A];
 #pragma unroll
-          for (int a = 0; a < A; ++a) pos[a] = posl[tr * A + a];
+          for (int a = 0; a < A; ++a) pp[a] = pos(a);
           T best = T(0);
           int key = INT_MAX, bad = 0;
 #pragma unroll
           for (int a = 0; a < A; ++a) {
             const int row = tr + 16 * a;
-            if (row < s && pos[a] >= k) {
+            if (row < s && pp[a] >= k) {
               bad |= !is_finite((double)x[kc][a]);
-              piv_take(best, key, x[kc][a], (pos[a] << 12) | row);
+              piv_take(best, key, x[kc][a], (pp[a] << 12) | row);
             }
           }
           row16_argmax(best, key);
@@ -201,26 +220,37 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
 #pragma unroll
               for (int a = 0; a < A; ++a) {
                 const int row = tr + 16 * a;
-                const bool live = row < s && pos[a] >= k && row != prow;
+                const bool live = row < s && pp[a] >= k && row != prow;
                 const T l = live ? x[kc][a] / best : T(0);
                 if (live) x[kc][a] = l;
                 vb[buf * SR + tr * A + a] = l;
               }
               if (tr == 0) {
-                // positions k and ppos trade rows
-                const int q = rowl[k];
-                rowl[k] = prow;
-                rowl[ppos] = q;
-                posl[(prow & 15) * A + (prow >> 4)] = k;
-                posl[(q & 15) * A + (q >> 4)] = ppos;
-                bc_row[buf] = prow;
+                if (!PREG) {  // positions k and ppos trade rows
+                  const int q = rowl[k];
+                  rowl[k] = prow;
+                  rowl[ppos] = q;
+                  posl[(prow & 15) * A + (prow >> 4)] = k;
+                  posl[(q & 15) * A + (q >> 4)] = ppos;
+                }
+                bc_row[buf] = key;  // pivot row and its position
               }
             }
           }
         }
         __syncthreads();
         if (bc_fail) return;
-        const int prow = __builtin_amdgcn_readfirstlane(bc_row[buf]);
+        const int pkey = __builtin_amdgcn_readfirstlane(bc_row[buf]);
+        const int prow = pkey & 4095, ppos = pkey >> 12;
+        if constexpr (PREG) {  // positions k and ppos trade rows
+#pragma unroll
+          for (int a = 0; a < A; ++a) {
+            const int pa = pos(a);
+            const int np_ = (tr + 16 * a == prow) ? k : (pa == k ? ppos : pa);
+            const int sh = 16 * (a & 1);
+            posw[a >> 1] = (posw[a >> 1] & ~(0xFFFFu << sh)) | ((uint32_t)np_ << sh);
+          }
+        }
         const int ap = prow >> 4, src = (lane & 48) | (prow & 15);
 #pragma unroll
         for (int c = kc; c < CS; ++c) {
@@ -243,9 +273,9 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
   }
 
   {
-  int pos[A];
+  int pp[A];
 #pragma unroll
-  for (int a = 0; a < A; ++a) pos[a] = posl[tr * A + a];
+  for (int a = 0; a < A; ++a) pp[a] = pos(a);
   if (lu) {
     // N = the rows at positions < n (upper part); M = unit lower trapezoid
 #pragma unroll
@@ -253,14 +283,22 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
       const int col = col0 + 64 * c;
 #pragma unroll
       for (int a = 0; a < A; ++a) {
-        if (pos[a] < n) {
-          if (col < n && col >= pos[a]) Nl[pos[a] * LD + col] = (double)x[c][a];
-          x[c][a] = (col < pos[a]) ? x[c][a] : (col == pos[a] ? T(1) : T(0));
+        if (pp[a] < n) {
+          if (col < n && col >= pp[a]) Nl[pp[a] * LD + col] = (double)x[c][a];
+          x[c][a] = (col < pp[a]) ? x[c][a] : (col == pp[a] ? T(1) : T(0));
         }
       }
     }
-    if (perm_out)
-      for (int p = tid; p < s; p += DN_THREADS) perm_out[p] = rowl[p];
+    if (perm_out) {
+      if (PREG) {
+        if (tid < 16)
+#pragma unroll
+          for (int a = 0; a < A; ++a)
+            if (tr + 16 * a < s) perm_out[pp[a]] = tr + 16 * a;
+      } else {
+        for (int p = tid; p < s; p += DN_THREADS) perm_out[p] = rowl[p];
+      }
+    }
   } else {
     // M = Y; N external (upper part) or the identity. Non-finite entries of M
     // are reported before the reflections (lowest column).
@@ -284,7 +322,7 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
     for (int c = 0; c < CS; ++c)
 #pragma unroll
       for (int a = 0; a < A; ++a)
-        if (tr + 16 * a < s && col0 + 64 * c < n) Mout[pos[a] + (int64_t)(col0 + 64 * c) * s] = (double)x[c][a];
+        if (tr + 16 * a < s && col0 + 64 * c < n) Mout[pp[a] + (int64_t)(col0 + 64 * c) * s] = (double)x[c][a];
   }
   }
 
@@ -296,32 +334,33 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
       if (k >= n) break;
       const int buf = k & 1;
       if (wave == (kk >> 2)) {
-        int pos[A];
+        int pp[A];
 #pragma unroll
-        for (int a = 0; a < A; ++a) pos[a] = posl[tr * A + a];
+        for (int a = 0; a < A; ++a) pp[a] = pos(a);
         T sq = T(0), al = T(0);
 #pragma unroll
         for (int a = 0; a < A; ++a) {
-          if (pos[a] > k && tr + 16 * a < s) sq = dn_fma(x[kc][a], x[kc][a], sq);
-          if (pos[a] == k) al = x[kc][a];
+          if (pp[a] > k && tr + 16 * a < s) sq = dn_fma(x[kc][a], x[kc][a], sq);
+          if (pp[a] == k) al = x[kc][a];
         }
         sq = row16_sum(sq);
         al = row16_sum(al);  // one non-zero term: exact
         if (col0 == kk) {
-          const T xnorm = sqrt(sq);
+          // dlarfg: beta = -sign(alpha) ||(alpha, x)||, the norm from the sum of
+          // squares already formed (one square root on the critical path)
           T tau = T(0), scal = T(0), beta = al;
-          if (xnorm != T(0)) {
-            beta = -copysign(hypot(al, xnorm), al);
+          if (sq != T(0)) {
+            beta = -copysign(sqrt(dn_fma(al, al, sq)), al);
             tau = (beta - al) / beta;
             scal = T(1) / (al - beta);
           }
 #pragma unroll
           for (int a = 0; a < A; ++a) {
-            const T v = (pos[a] > k && tr + 16 * a < s) ? x[kc][a] * scal : (pos[a] == k ? T(1) : T(0));
+            const T v = (pp[a] > k && tr + 16 * a < s) ? x[kc][a] * scal : (pp[a] == k ? T(1) : T(0));
             if (tau != T(0)) {
-              if (pos[a] > k)
+              if (pp[a] > k)
                 x[kc][a] = v;
-              else if (pos[a] == k)
+              else if (pp[a] == k)
                 x[kc][a] = beta;
             }
             vb[buf * SR + tr * A + a] = v;
@@ -351,12 +390,15 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
   }
 
   // R_0: the rows at positions < n, columns >= position
+  int pp2[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) pp2[a] = pos(a);
 #pragma unroll
   for (int c = 0; c < CS; ++c) {
     const int col = col0 + 64 * c;
 #pragma unroll
     for (int a = 0; a < A; ++a) {
-      const int pa = posl[tr * A + a];
+      const int pa = pp2[a];
       if (pa < n && col < n && col >= pa) R0l[pa * LD + col] = (double)x[c][a];
     }
   }
