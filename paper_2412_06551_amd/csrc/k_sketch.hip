@@ -229,20 +229,24 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch_lp(const double* __restri
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  // prefetch registers: FP32 values, or BF16 pairs (two columns per word)
-  constexpr int PRE = BF ? CPT / 2 : CPT;
-  uint32_t pre[PRE];
+  // prefetch registers: FP32 keeps the FP64 values as loaded (converting at
+  // load time would wait for every load before the tile's products, so the
+  // loads would not overlap them); BF16 (a 128-row tile, twice the entries)
+  // packs pairs of columns per word to stay within the registers
+  constexpr int PRE = BF ? CPT / 2 : 1;
+  uint32_t prb[PRE];
+  double pre[BF ? 1 : CPT];
   auto load_tile = [&](int64_t t) {
     const int64_t row = t * TK + lrow;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       const int col = col0 + lcol0 + CSTEP * c;
-      const float v = (row < m && col < n) ? (float)X[row + (int64_t)col * ld] : 0.f;
       if constexpr (BF) {
+        const float v = (row < m && col < n) ? (float)X[row + (int64_t)col * ld] : 0.f;
         const uint32_t h = f32_to_bf16_rne(v);
-        pre[c >> 1] = (c & 1) ? (pre[c >> 1] | (h << 16)) : h;
+        prb[c >> 1] = (c & 1) ? (prb[c >> 1] | (h << 16)) : h;
       } else {
-        pre[c] = __float_as_uint(v);
+        pre[c] = (row < m && col < n) ? X[row + (int64_t)col * ld] : 0.0;
       }
     }
   };
@@ -251,11 +255,11 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch_lp(const double* __restri
       unsigned short* xs = (unsigned short*)(lds_raw + buf * L::TILE_BYTES);
 #pragma unroll
       for (int c = 0; c < CPT; ++c)
-        xs[(lcol0 + CSTEP * c) * LD + lrow] = (unsigned short)((c & 1) ? (pre[c >> 1] >> 16) : (pre[c >> 1] & 0xFFFFu));
+        xs[(lcol0 + CSTEP * c) * LD + lrow] = (unsigned short)((c & 1) ? (prb[c >> 1] >> 16) : (prb[c >> 1] & 0xFFFFu));
     } else {
       float* xs = (float*)(lds_raw + buf * L::TILE_BYTES);
 #pragma unroll
-      for (int c = 0; c < CPT; ++c) xs[lrow * LD + lcol0 + CSTEP * c] = __uint_as_float(pre[c]);
+      for (int c = 0; c < CPT; ++c) xs[lrow * LD + lcol0 + CSTEP * c] = (float)pre[c];
     }
   };
 
