@@ -123,14 +123,15 @@ __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(co
   for (int g = 0; g < (GRAM ? NBLK : 1); ++g) gacc[g] = f64x4{0.0, 0.0, 0.0, 0.0};
   double* ws = gst + wave * NP * TM_LDG;
 
-  for (int64_t t = wg; t < ntiles; t += nwg) {
-    const int64_t row0 = t * tm_tile(NP) + wave * RW;
-    f64x4 acc[HB][NB];
-    // addresses: a wave-uniform column base (scalar) plus a 32-bit per-lane offset
-    // (row + (l/16) ld); requires 3 ld + m < 2^29, checked by the launcher
+  // X tile of this wave in the MFMA B layout. Addresses: a wave-uniform column
+  // base (scalar) plus a 32-bit per-lane offset (row + (l/16) ld); requires
+  // 3 ld + m < 2^29, checked by the launcher. Streamed once: nontemporal, so X
+  // and W do not evict R, the tables and the partials from the caches.
+  auto load_x = [&](int64_t tt, f64x4 (&dst)[HB][NB]) {
+    const int64_t r0 = tt * tm_tile(NP) + wave * RW;
 #pragma unroll
     for (int h = 0; h < HB; ++h) {
-      const int64_t row = row0 + 16 * h + lr;
+      const int64_t row = r0 + 16 * h + lr;
       const bool live = row < m;
       const uint32_t voff = (uint32_t)(row + (int64_t)lq * ldx);
 #pragma unroll
@@ -139,10 +140,29 @@ __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(co
         for (int r = 0; r < 4; ++r) {
           const int col = 16 * b + lq + 4 * r;
           const double* cb = X + (int64_t)(16 * b + 4 * r) * ldx;
-          // streamed once: nontemporal, so X and W do not evict R, the tables
-          // and the partials from the caches
-          acc[h][b][r] = (live && col < n) ? __builtin_nontemporal_load(cb + voff) : 0.0;
+          dst[h][b][r] = (live && col < n) ? __builtin_nontemporal_load(cb + voff) : 0.0;
         }
+    }
+  };
+  // n = 64 with the Gram: the next tile's loads are issued before this tile's
+  // work (64 more registers, still two workgroups per CU), so they are in
+  // flight during it. A tile t + nwg belongs to this workgroup alone, so the
+  // early read never sees another workgroup's writes, also in place.
+  constexpr bool PF = NP == 64 && GRAM && TRSM;
+  f64x4 pre[HB][NB];
+  if (PF && wg < ntiles) load_x(wg, pre);
+
+  for (int64_t t = wg; t < ntiles; t += nwg) {
+    const int64_t row0 = t * tm_tile(NP) + wave * RW;
+    f64x4 acc[HB][NB];
+    if (PF) {
+#pragma unroll
+      for (int h = 0; h < HB; ++h)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[h][b] = pre[h][b];
+      if (t + nwg < ntiles) load_x(t + nwg, pre);
+    } else {
+      load_x(t, acc);
     }
     if (TRSM) {
       // opaque per tile: keeps the table reads inside the tile loop (hoisting
