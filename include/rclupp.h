@@ -69,7 +69,10 @@ typedef enum {
   RCLUPP_INFO_LU_ZERO_PIVOT = 1,  /* LU with partial pivoting met an exactly zero column */
   RCLUPP_INFO_CHOL_BREAKDOWN = 2, /* a Cholesky pivot was not > 0                          */
   RCLUPP_INFO_NONFINITE = 3,      /* the input of a small factorization held NaN or Inf    */
-  RCLUPP_INFO_SINGULAR = 4        /* the preconditioner R_1 has an exactly zero diagonal   */
+  RCLUPP_INFO_SINGULAR = 4,       /* the preconditioner R_1 has an exactly zero diagonal   */
+  RCLUPP_INFO_SYNC_TIMEOUT = 5    /* a grid-wide step barrier of the multi-workgroup small
+                                     factorization did not complete within its bounded wait
+                                     (should not happen; the kernel exits rather than hang) */
 } rclupp_info_code;
 
 /* Stage = the role of the failing small factorization in the pipeline. */

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "librclupp.so")
 # status codes (rclupp_status)
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_ALLOC, ERR_HIP, ERR_WORKSPACE = 0, 1, 2, 3, 4, 5
 # info codes and stages (rclupp_info_code, rclupp_stage)
-INFO_OK, INFO_LU_ZERO_PIVOT, INFO_CHOL_BREAKDOWN, INFO_NONFINITE, INFO_SINGULAR = 0, 1, 2, 3, 4
+INFO_OK, INFO_LU_ZERO_PIVOT, INFO_CHOL_BREAKDOWN, INFO_NONFINITE, INFO_SINGULAR, INFO_SYNC_TIMEOUT = 0, 1, 2, 3, 4, 5
 STAGE_NONE, STAGE_LU, STAGE_QR, STAGE_PRECOND, STAGE_CHOL_A, STAGE_CHOL_B = 0, 1, 2, 3, 4, 5
 # precisions and algorithms (rclupp_prec, rclupp_alg)
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}

@@ -12,7 +12,8 @@
 namespace rclupp {
 
 // Asynchronous outcome codes and stages (the values the C ABI documents).
-enum : int32_t { INFO_OK = 0, INFO_LU_ZERO_PIVOT = 1, INFO_CHOL_BREAKDOWN = 2, INFO_NONFINITE = 3, INFO_SINGULAR = 4 };
+enum : int32_t { INFO_OK = 0, INFO_LU_ZERO_PIVOT = 1, INFO_CHOL_BREAKDOWN = 2, INFO_NONFINITE = 3, INFO_SINGULAR = 4,
+                INFO_SYNC_TIMEOUT = 5 };
 enum : int32_t { STAGE_LU = 1, STAGE_QR = 2, STAGE_PRECOND = 3, STAGE_CHOL_A = 4, STAGE_CHOL_B = 5 };
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));

@@ -1,19 +1,21 @@
-// Small dense stages on the s x n sketch and the n x n Grams, one workgroup
-// each (they are O(s n^2) and O(n^3) and latency bound):
-//   k_precond : [M, N, P] = LU(Y) with partial pivoting (eq. elu), R_0 = R
-//               factor of M by Householder reflections (eq. eh, Q_s never
+// Small dense stages for the shapes the register-resident kernels of
+// k_dense.hip cannot hold (s > 256 or n > 128):
+//   k_precond_coop : [M, N, P] = LU(Y) with partial pivoting (eq. elu), R_0 =
+//               R factor of M by Householder reflections (eq. eh, Q_s never
 //               formed), R_1 = D R_0 N with D = sign(diag(R_0 N)) (eq. ey)
 //               (Algorithm 2 steps 2-4; Algorithm 7 steps 3-4 with an external
-//               N; Algorithm 6 step 2 without the LU);
+//               N; Algorithm 6 step 2 without the LU); several workgroups, one
+//               grid-wide barrier per column step;
 //   k_chol    : upper Cholesky of G (+ the shift of Algorithm 4), optional
 //               right factor (LC2's R_1 = D S_c N) and product with an earlier
-//               factor (R_3 = R_2 R_1, R = R_4 R_3; eqs. C4, C8).
-// The working copy lives in LDS when it fits, else in a global scratch buffer
-// (same code through generic pointers). Threads form a 64 x 16 grid: tx walks
-// rows (contiguous in the column-major layout), ty walks columns; the column
-// loops keep SD_U loads in flight per thread (the working copy is in L2 when
-// it does not fit LDS, and one outstanding load per thread left them latency
-// bound).
+//               factor (R_3 = R_2 R_1, R = R_4 R_3; eqs. C4, C8); one
+//               workgroup (O(n^3), latency bound).
+// k_chol keeps its working copy in LDS when it fits, else in a global scratch
+// buffer (same code through generic pointers). Threads form a 64 x 16 grid: tx
+// walks rows (contiguous in the column-major layout), ty walks columns; the
+// column loops keep SD_U loads in flight per thread (the working copy is in L2
+// when it does not fit LDS, and one outstanding load per thread left them
+// latency bound).
 #include <float.h>
 #include <limits.h>
 
@@ -76,18 +78,6 @@ __device__ void block_argmax(double& v, int& idx, int& bad, ArgMaxSh* sh) {
   bad = sh->pbad;
 }
 
-template <typename T>
-__device__ T block_sum(T v, T* sh /* [SD_WAVES] */) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  if (lane == 0) sh[wave] = v;
-  __syncthreads();
-  T r = sh[0];
-  for (int w = 1; w < SD_THREADS / 64; ++w) r += sh[w];
-  __syncthreads();
-  return r;
-}
 
 template <typename T>
 __device__ __forceinline__ T tabs(T v) {
@@ -107,258 +97,6 @@ __device__ void write_padded(const double* R /* n x n generic */, int ldr, int n
     Rpad[e] = v;
   }
   for (int j = threadIdx.x; j < np; j += SD_THREADS) Rpad[np * np + j] = (j < n) ? 1.0 / R[j + j * ldr] : 1.0;
-}
-
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(SD_THREADS) void k_precond(const double* __restrict__ Y, int s, int n, int lu,
-                                                        const double* __restrict__ Nin, int ldn, double* R1pad, int np,
-                                                        double* R1out, int32_t* perm_out, double* Mout, T* gA, T* gN,
-                                                        T* gR, int32_t* gperm, int use_lds, int32_t* info,
-                                                        int32_t stage_qr) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ ArgMaxSh amx;
-  __shared__ T red[SD_WAVES];
-  __shared__ T sc_tau, sc_scal;
-  __shared__ int fail;
-  if (info_failed(info)) return;
-  T* A = use_lds ? (T*)smem_raw : gA;
-  T* wv = use_lds ? A + (size_t)s * n : gA + (size_t)s * n;  // n entries
-  int32_t* perm = gperm;
-  T* N = gN;
-  T* R = gR;
-  const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
-
-  for (int e = tid; e < s * n; e += SD_THREADS) A[e] = (T)Y[e];
-  if (tid == 0) fail = 0;
-  for (int i = tid; i < s; i += SD_THREADS) perm[i] = i;
-  __syncthreads();
-
-  // Without the LU, non-finite entries are reported before the Householder
-  // steps (lowest column); with the LU each pivot column is checked as it is
-  // reached (rows k..s-1 after the earlier updates), as partial pivoting does.
-  if (!lu) {
-    double v = -1.0;
-    int idx = INT_MAX, bad = 0;
-    for (int e = tid; e < s * n; e += SD_THREADS)
-      if (!is_finite((double)A[e]) && e / s < idx) {
-        idx = e / s;
-        bad = 1;
-      }
-    // lowest failing column: reuse the argmax reduction with v = -column
-    v = bad ? -(double)idx : -1e300;
-    block_argmax(v, idx, bad, &amx);
-    if (bad) {
-      if (tid == 0) info_set(info, INFO_NONFINITE, stage_qr, (int32_t)(-v) + 1);
-      return;
-    }
-  }
-
-  if (lu) {
-    for (int k = 0; k < n; ++k) {
-      double best = -1.0;
-      int idx = INT_MAX, bad = 0;
-      for (int i = k + tid; i < s; i += SD_THREADS) {
-        const double a = (double)tabs(A[i + k * s]);
-        if (!is_finite(a)) bad = 1;
-        if (a > best) {
-          best = a;
-          idx = i;
-        }
-      }
-      block_argmax(best, idx, bad, &amx);
-      if (bad) {
-        if (tid == 0) info_set(info, INFO_NONFINITE, STAGE_LU, k + 1);
-        return;
-      }
-      if (best == 0.0) {
-        if (tid == 0) info_set(info, INFO_LU_ZERO_PIVOT, STAGE_LU, k + 1);
-        return;
-      }
-      const int p = idx;
-      if (p != k) {
-        for (int j = tid; j < n; j += SD_THREADS) {
-          const T t = A[k + j * s];
-          A[k + j * s] = A[p + j * s];
-          A[p + j * s] = t;
-        }
-        if (tid == 0) {
-          const int32_t t = perm[k];
-          perm[k] = perm[p];
-          perm[p] = t;
-        }
-      }
-      __syncthreads();
-      const T piv = A[k + k * s];
-      for (int i = k + 1 + tid; i < s; i += SD_THREADS) A[i + k * s] = A[i + k * s] / piv;
-      __syncthreads();
-      for (int j = k + 1 + ty; j < n; j += SD_WAVES) {
-        const T akj = A[k + j * s];
-        T* cj = A + (size_t)j * s;
-        const T* ck = A + (size_t)k * s;
-        int i = k + 1 + tx;
-        for (; i + 64 * (SD_U - 1) < s; i += 64 * SD_U) {
-          T a[SD_U], l[SD_U];
-#pragma unroll
-          for (int u = 0; u < SD_U; ++u) {
-            a[u] = cj[i + 64 * u];
-            l[u] = ck[i + 64 * u];
-          }
-#pragma unroll
-          for (int u = 0; u < SD_U; ++u) cj[i + 64 * u] = a[u] - l[u] * akj;
-        }
-        for (; i < s; i += 64) cj[i] = cj[i] - ck[i] * akj;
-      }
-      __syncthreads();
-    }
-    // N = upper n x n; then A := unit lower trapezoidal M
-    for (int e = tid; e < n * n; e += SD_THREADS) {
-      const int i = e % n, j = e / n;
-      N[e] = (i <= j) ? A[i + j * s] : T(0);
-    }
-    __syncthreads();
-    for (int e = tid; e < n * n; e += SD_THREADS) {
-      const int i = e % n, j = e / n;
-      if (i <= j) A[i + j * s] = (i == j) ? T(1) : T(0);
-    }
-    __syncthreads();
-    if (Mout)
-      for (int e = tid; e < s * n; e += SD_THREADS) Mout[e] = (double)A[e];
-    if (perm_out)
-      for (int i = tid; i < s; i += SD_THREADS) perm_out[i] = perm[i];
-  } else {
-    for (int e = tid; e < n * n; e += SD_THREADS) {
-      const int i = e % n, j = e / n;
-      N[e] = Nin ? ((i <= j) ? (T)Nin[i + j * ldn] : T(0)) : (i == j ? T(1) : T(0));
-    }
-  }
-  __syncthreads();
-
-  // Householder R factor of A (s x n), LAPACK dlarfg convention
-  for (int k = 0; k < n; ++k) {
-    T part = T(0);
-    for (int i = k + 1 + tid; i < s; i += SD_THREADS) part += A[i + k * s] * A[i + k * s];
-    const T ss = block_sum(part, red);
-    if (tid == 0) {
-      const T alpha = A[k + k * s];
-      const T xnorm = sqrt(ss);
-      T tau = T(0), scal = T(0);
-      if (xnorm != T(0)) {
-        const T beta = -copysign(hypot(alpha, xnorm), alpha);
-        tau = (beta - alpha) / beta;
-        scal = T(1) / (alpha - beta);
-        A[k + k * s] = beta;
-      }
-      sc_tau = tau;
-      sc_scal = scal;
-    }
-    __syncthreads();
-    const T tau = sc_tau, scal = sc_scal;
-    if (tau == T(0)) continue;
-    for (int i = k + 1 + tid; i < s; i += SD_THREADS) A[i + k * s] *= scal;
-    __syncthreads();
-    // wv[j] = A[k][j] + sum_{i>k} v_i A[i][j]; one wave per column (strided)
-    for (int j = k + 1 + ty; j < n; j += SD_WAVES) {
-      const T* cj = A + (size_t)j * s;
-      const T* ck = A + (size_t)k * s;
-      T part[SD_U];
-#pragma unroll
-      for (int u = 0; u < SD_U; ++u) part[u] = T(0);
-      int i = k + 1 + tx;
-      for (; i + 64 * (SD_U - 1) < s; i += 64 * SD_U)
-#pragma unroll
-        for (int u = 0; u < SD_U; ++u) part[u] += ck[i + 64 * u] * cj[i + 64 * u];
-      for (; i < s; i += 64) part[0] += ck[i] * cj[i];
-      T acc = part[0];
-#pragma unroll
-      for (int u = 1; u < SD_U; ++u) acc += part[u];
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-      if (tx == 0) wv[j] = A[k + j * s] + acc;
-    }
-    __syncthreads();
-    for (int j = k + 1 + ty; j < n; j += SD_WAVES) {
-      const T tw = tau * wv[j];
-      T* cj = A + (size_t)j * s;
-      const T* ck = A + (size_t)k * s;
-      int i = k + tx;
-      for (; i + 64 * (SD_U - 1) < s; i += 64 * SD_U) {
-        T a[SD_U], v[SD_U];
-#pragma unroll
-        for (int u = 0; u < SD_U; ++u) {
-          a[u] = cj[i + 64 * u];
-          v[u] = (i + 64 * u == k) ? T(1) : ck[i + 64 * u];
-        }
-#pragma unroll
-        for (int u = 0; u < SD_U; ++u) cj[i + 64 * u] = a[u] - tw * v[u];
-      }
-      for (; i < s; i += 64) {
-        const T v = (i == k) ? T(1) : ck[i];
-        cj[i] -= tw * v;
-      }
-    }
-    __syncthreads();
-  }
-
-  // R_1 = R_0 N (upper x upper), then the sign fix D
-  for (int e = tid; e < n * n; e += SD_THREADS) {
-    const int i = e % n, j = e / n;
-    T part[SD_U];
-#pragma unroll
-    for (int u = 0; u < SD_U; ++u) part[u] = T(0);
-    if (i <= j) {
-      int k = i;
-      for (; k + SD_U - 1 <= j; k += SD_U)
-#pragma unroll
-        for (int u = 0; u < SD_U; ++u) part[u] += A[i + (size_t)(k + u) * s] * N[k + u + j * n];
-      for (; k <= j; ++k) part[0] += A[i + (size_t)k * s] * N[k + j * n];
-    }
-    T acc = part[0];
-#pragma unroll
-    for (int u = 1; u < SD_U; ++u) acc += part[u];
-    R[e] = acc;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    for (int i = 0; i < n; ++i) {
-      const T d = R[i + i * n];
-      if (!is_finite((double)d)) {
-        info_set(info, INFO_NONFINITE, STAGE_PRECOND, i + 1);
-        fail = 1;
-        break;
-      }
-      if (d == T(0)) {
-        info_set(info, INFO_SINGULAR, STAGE_PRECOND, i + 1);
-        fail = 1;
-        break;
-      }
-    }
-  }
-  __syncthreads();
-  if (fail) return;
-  // widen to double with the signs folded in
-  for (int e = tid; e < np * np; e += SD_THREADS) {
-    const int i = e / np, j = e % np;
-    double v;
-    if (i < n && j < n) {
-      const double d = (double)R[i + i * n];
-      v = (i <= j) ? (double)R[i + j * n] : 0.0;
-      if (d < 0.0) v = -v;
-    } else {
-      v = (i == j) ? 1.0 : 0.0;
-    }
-    R1pad[e] = v;
-    if (R1out && i < n && j < n) R1out[i + j * n] = v;
-  }
-  __syncthreads();
-  for (int j = tid; j < np; j += SD_THREADS) {
-    double v = 1.0;
-    if (j < n) {
-      const double d = (double)R[j + j * n];
-      v = 1.0 / (d < 0.0 ? -d : d);
-    }
-    R1pad[np * np + j] = v;
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -529,43 +267,439 @@ __global__ void k_pad(const double* __restrict__ R, int n, int np, double* __res
 }
 
 // ---------------------------------------------------------------------------
+// Preconditioner for the shapes the register-resident kernel cannot hold
+// (s > 256 or n > 128), one cooperative launch of G workgroups: column j lives
+// in the LDS of workgroup j % G (cpw columns each). Every column step is one
+// grid-wide barrier: the owner of column k finds the pivot (LU) or forms the
+// reflector (Householder), publishes the multipliers or the reflector in a
+// double-buffered global vector, and after the barrier every workgroup applies
+// the step to its own columns. Rows are swapped physically in every column,
+// so no position bookkeeping is needed. Same arithmetic as k_precond: true
+// division for the multipliers, dlarfg's beta = -sign(alpha) hypot(alpha, |x|).
+// The barrier waits are bounded: a wait that does not end records
+// INFO_SYNC_TIMEOUT and the kernel exits.
+// ---------------------------------------------------------------------------
+constexpr int CP_THREADS = 256;
+constexpr int CP_WAVES = CP_THREADS / 64;
+
+struct CoopCtl {
+  unsigned count, gen;  // grid barrier: arrivals, generation
+  int fail;             // a step failed (set by its owner before the barrier)
+  int mincol;           // lowest column with a non-finite entry (no LU)
+  int piv[2];           // pivot row of the step, double-buffered
+  double tau[2];        // reflector scale of the step, double-buffered
+};
+
+size_t coop_ctl_bytes() { return (sizeof(CoopCtl) + 255) / 256 * 256; }
+
+__global__ void k_coop_ctl_init(CoopCtl* c) {
+  if (threadIdx.x == 0) {
+    c->count = 0;
+    c->gen = 0;
+    c->fail = 0;
+    c->mincol = INT_MAX;
+    c->piv[0] = c->piv[1] = 0;
+    c->tau[0] = c->tau[1] = 0.0;
+  }
+}
+
+// All G workgroups arrive; false if this workgroup's bounded wait ran out.
+// The workgroup barrier makes every wave's stores complete in this CU's L2
+// before thread 0's agent-scope release (which writes that L2 back, for the
+// other XCDs); thread 0's acquire invalidates this CU's caches before the
+// workgroup barrier lets the other waves read. One fence pair per workgroup:
+// each is a cache-wide operation.
+__device__ bool coop_barrier(CoopCtl* c, unsigned nblocks) {
+  __shared__ int timed_out;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    timed_out = 0;
+    __threadfence();  // release: this workgroup's writes before the arrival
+    const unsigned g = __hip_atomic_load(&c->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (atomicAdd(&c->count, 1u) == nblocks - 1) {
+      __hip_atomic_store(&c->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+      atomicAdd(&c->gen, 1u);
+    } else {
+      unsigned spins = 0;
+      while (__hip_atomic_load(&c->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > (1u << 24)) {
+          timed_out = 1;
+          break;
+        }
+      }
+    }
+    __threadfence();  // acquire: the other workgroups' writes after the wait
+  }
+  __syncthreads();
+  return timed_out == 0;
+}
+
+__device__ __forceinline__ int cp_load_i(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double cp_load_d(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum over the workgroup of NV values per thread (each thread gets the sums).
+template <int NV, typename T>
+__device__ void cp_sum(T (&v)[NV], T* sh /* [CP_WAVES][NV] */) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off);
+    if (lane == 0) sh[wave * NV + q] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    T r = sh[q];
+    for (int w = 1; w < CP_WAVES; ++w) r += sh[w * NV + q];
+    v[q] = r;
+  }
+  __syncthreads();
+}
+
+constexpr int CP_MAXC = 8;  // columns per workgroup at most
+
+template <typename T>
+__global__ __launch_bounds__(CP_THREADS) void k_precond_coop(const double* __restrict__ Y, int s, int n, int lu,
+                                                             const double* __restrict__ Nin, int ldn, double* R1pad,
+                                                             int np, double* R1out, int32_t* perm_out, double* Mout,
+                                                             double* vbuf, double* Ng, double* R0g, int32_t* permg,
+                                                             CoopCtl* ctl, int cpw, int32_t* info, int32_t stage_qr) {
+  extern __shared__ __align__(16) unsigned char cp_smem[];
+  T* cols = (T*)cp_smem;  // local column q (global g + q G) at q*s
+  __shared__ T shr[CP_WAVES * CP_MAXC];
+  __shared__ double amv[CP_WAVES];
+  __shared__ int ami[CP_WAVES], amb[CP_WAVES];
+  const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+  const unsigned nb = (unsigned)G;
+  // (no workgroup writes info before the first barrier, so all read the same)
+  if (info_failed(info)) return;
+  auto col = [&](int q) { return cols + (size_t)q * s; };
+  const int nloc = (n - g + G - 1) / G;  // columns of this workgroup
+#pragma unroll
+  for (int q = 0; q < CP_MAXC; ++q) {
+    if (q >= nloc) break;
+    const int j = g + q * G;
+    for (int i = tid; i < s; i += CP_THREADS) col(q)[i] = (T)Y[i + (int64_t)j * s];
+  }
+  if (g == 0)
+    for (int i = tid; i < s; i += CP_THREADS) permg[i] = i;
+  if (!coop_barrier(ctl, nb)) goto timeout;
+
+  if (lu) {
+    for (int k = 0; k < n; ++k) {
+      const int buf = k & 1, owner = k % G;
+      if (g == owner) {
+        T* c = col(k / G);
+        double best = -1.0;
+        int idx = INT_MAX, bad = 0;
+        for (int i = k + tid; i < s; i += CP_THREADS) {
+          const double a = (double)c[i];
+          if (!is_finite(a)) bad = 1;
+          const double v = fabs(a);
+          if (v > best) {
+            best = v;
+            idx = i;
+          }
+        }
+        // workgroup argmax, first row on ties
+        const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          const double ov = __shfl_xor(best, off);
+          const int oi = __shfl_xor(idx, off);
+          const int ob = __shfl_xor(bad, off);
+          if (ov > best || (ov == best && oi < idx)) {
+            best = ov;
+            idx = oi;
+          }
+          bad |= ob;
+        }
+        if (lane == 0) {
+          amv[wave] = best;
+          ami[wave] = idx;
+          amb[wave] = bad;
+        }
+        __syncthreads();
+        best = amv[0];
+        idx = ami[0];
+        bad = amb[0];
+        for (int w = 1; w < CP_WAVES; ++w) {
+          if (amv[w] > best || (amv[w] == best && ami[w] < idx)) {
+            best = amv[w];
+            idx = ami[w];
+          }
+          bad |= amb[w];
+        }
+        if (bad || !(best > 0.0)) {
+          if (tid == 0) {
+            info_set(info, bad ? INFO_NONFINITE : INFO_LU_ZERO_PIVOT, STAGE_LU, k + 1);
+            ctl->fail = 1;
+          }
+        } else {
+          const int p = idx;
+          const T piv = c[p];
+          const T ck = c[k];
+          __syncthreads();
+          if (tid == 0) {
+            c[k] = piv;
+            c[p] = ck;
+            const int32_t t = permg[k];
+            permg[k] = permg[p];
+            permg[p] = t;
+            ctl->piv[buf] = p;
+          }
+          __syncthreads();
+          for (int i = k + 1 + tid; i < s; i += CP_THREADS) {
+            const T l = c[i] / piv;
+            c[i] = l;
+            vbuf[buf * s + i] = (double)l;
+          }
+        }
+      }
+      if (!coop_barrier(ctl, nb)) goto timeout;
+      if (cp_load_i(&ctl->fail)) return;
+      const int p = cp_load_i(&ctl->piv[buf]);
+      // read phase: the pivot row's entries (row k after the swap) and row k's
+      // old entries (row p after the swap), in every column but k (the
+      // multipliers of the earlier columns trade rows too, as in getrf)
+      T akj[CP_MAXC], okk[CP_MAXC];
+#pragma unroll
+      for (int q = 0; q < CP_MAXC; ++q) {
+        if (q >= nloc) break;
+        const int j = g + q * G;
+        if (j != k) {
+          akj[q] = col(q)[p];
+          okk[q] = col(q)[k];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < CP_MAXC; ++q) {
+        if (q >= nloc) break;
+        const int j = g + q * G;
+        if (j == k) continue;
+        T* c = col(q);
+        if (j < k) {  // finished column: the swap only
+          if (tid == 0 && p != k) {
+            c[k] = akj[q];
+            c[p] = okk[q];
+          }
+          continue;
+        }
+        for (int i = k + tid; i < s; i += CP_THREADS) {
+          if (i == k) {
+            c[k] = akj[q];
+          } else {
+            const T l = (T)vbuf[buf * s + i];
+            const T a = (i == p) ? okk[q] : c[i];
+            c[i] = a - l * akj[q];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // N = the upper n x n part; M = unit lower trapezoid
+#pragma unroll
+    for (int q = 0; q < CP_MAXC; ++q) {
+      if (q >= nloc) break;
+      const int j = g + q * G;
+      T* c = col(q);
+      for (int i = tid; i < n; i += CP_THREADS) {
+        Ng[i + (int64_t)j * n] = (i <= j) ? (double)c[i] : 0.0;
+        if (i <= j) c[i] = (i == j) ? T(1) : T(0);
+      }
+      if (Mout)
+        for (int i = tid; i < s; i += CP_THREADS) Mout[i + (int64_t)j * s] = (double)c[i];
+    }
+  } else {
+    // M = Y; N external (upper part) or the identity; non-finite entries of M
+    // are reported before the reflections (lowest column)
+    int lowest = INT_MAX;
+#pragma unroll
+    for (int q = 0; q < CP_MAXC; ++q) {
+      if (q >= nloc) break;
+      const int j = g + q * G;
+      for (int i = tid; i < s; i += CP_THREADS)
+        if (!is_finite((double)col(q)[i]) && j < lowest) lowest = j;
+      for (int i = tid; i < n; i += CP_THREADS)
+        Ng[i + (int64_t)j * n] = Nin ? ((i <= j) ? Nin[i + (int64_t)j * ldn] : 0.0) : (i == j ? 1.0 : 0.0);
+    }
+    if (lowest != INT_MAX) atomicMin(&ctl->mincol, lowest);
+    if (!coop_barrier(ctl, nb)) goto timeout;
+    const int mc = cp_load_i(&ctl->mincol);
+    if (mc != INT_MAX) {
+      if (g == 0 && tid == 0) info_set(info, INFO_NONFINITE, stage_qr, mc + 1);
+      return;
+    }
+  }
+
+  // Householder reflections (LAPACK dlarfg convention)
+  for (int k = 0; k < n; ++k) {
+    const int buf = k & 1, owner = k % G;
+    if (g == owner) {
+      T* c = col(k / G);
+      T part[1] = {T(0)};
+      for (int i = k + 1 + tid; i < s; i += CP_THREADS) part[0] += c[i] * c[i];
+      cp_sum<1>(part, shr);
+      const T al = c[k];
+      const T xnorm = sqrt(part[0]);
+      T tau = T(0), scal = T(0), beta = al;
+      if (xnorm != T(0)) {
+        beta = -copysign(hypot(al, xnorm), al);
+        tau = (beta - al) / beta;
+        scal = T(1) / (al - beta);
+      }
+      if (tau != T(0)) {
+        for (int i = k + 1 + tid; i < s; i += CP_THREADS) {
+          const T v = c[i] * scal;
+          c[i] = v;
+          vbuf[buf * s + i] = (double)v;
+        }
+      }
+      __syncthreads();
+      if (tid == 0) {
+        if (tau != T(0)) c[k] = beta;
+        vbuf[buf * s + k] = 1.0;
+        ctl->tau[buf] = (double)tau;
+      }
+    }
+    if (!coop_barrier(ctl, nb)) goto timeout;
+    const T tau = (T)cp_load_d(&ctl->tau[buf]);
+    if (tau == T(0)) continue;
+    // w_j = v^T M(:, j) for the local columns j > k (one reduction for all), then M(:, j) -= tau w_j v
+    T w[CP_MAXC];
+    for (int q = 0; q < CP_MAXC; ++q) w[q] = T(0);
+    for (int i = k + tid; i < s; i += CP_THREADS) {
+      const T v = (T)vbuf[buf * s + i];
+#pragma unroll
+      for (int q = 0; q < CP_MAXC; ++q)
+        if (q < nloc && g + q * G > k) w[q] += v * col(q)[i];
+    }
+    cp_sum<CP_MAXC>(w, shr);
+#pragma unroll
+    for (int q = 0; q < CP_MAXC; ++q) {
+      if (q >= nloc) break;
+      if (g + q * G <= k) continue;
+      T* c = col(q);
+      const T tw = tau * w[q];
+      for (int i = k + tid; i < s; i += CP_THREADS) c[i] -= tw * (T)vbuf[buf * s + i];
+    }
+    __syncthreads();
+  }
+
+  // R_0 (rows < n, upper), then R_1 = D R_0 N for this workgroup's columns
+#pragma unroll
+  for (int q = 0; q < CP_MAXC; ++q) {
+    if (q >= nloc) break;
+    const int j = g + q * G;
+    for (int i = tid; i < n; i += CP_THREADS) R0g[i + (int64_t)j * n] = (i <= j) ? (double)col(q)[i] : 0.0;
+  }
+  if (!coop_barrier(ctl, nb)) goto timeout;
+  {
+    // diag(R_0 N) = diag(R_0) diag(N); every workgroup finds the same first failure
+    __shared__ int bad_at;
+    if (tid == 0) bad_at = INT_MAX;
+    __syncthreads();
+    for (int i = tid; i < n; i += CP_THREADS) {
+      const double d = (double)(T)(cp_load_d(&R0g[i + (int64_t)i * n]) * cp_load_d(&Ng[i + (int64_t)i * n]));
+      if (!is_finite(d) || d == 0.0) atomicMin(&bad_at, i);
+    }
+    __syncthreads();
+    if (bad_at != INT_MAX) {
+      if (g == 0 && tid == 0) {
+        const int i = bad_at;
+        const double d = cp_load_d(&R0g[i + (int64_t)i * n]) * cp_load_d(&Ng[i + (int64_t)i * n]);
+        info_set(info, is_finite(d) ? INFO_SINGULAR : INFO_NONFINITE, STAGE_PRECOND, i + 1);
+      }
+      return;
+    }
+    // columns j = g, g + G, ... < np of the padded triangle
+    for (int j = g; j < np; j += G) {
+      for (int i = tid; i < np; i += CP_THREADS) {
+        double v;
+        if (i < n && j < n) {
+          T acc = T(0);
+          if (i <= j)
+            for (int k2 = i; k2 <= j; ++k2) acc += (T)cp_load_d(&R0g[i + (int64_t)k2 * n]) * (T)cp_load_d(&Ng[k2 + (int64_t)j * n]);
+          const double dii = (double)(T)(cp_load_d(&R0g[i + (int64_t)i * n]) * cp_load_d(&Ng[i + (int64_t)i * n]));
+          v = (i <= j) ? (double)acc : 0.0;
+          if (dii < 0.0) v = -v;
+          if (R1out) R1out[i + (int64_t)j * n] = v;
+        } else {
+          v = (i == j) ? 1.0 : 0.0;
+        }
+        R1pad[(int64_t)i * np + j] = v;
+      }
+      if (tid == 0) {
+        double r = 1.0;
+        if (j < n) {
+          const double d = (double)(T)(cp_load_d(&R0g[j + (int64_t)j * n]) * cp_load_d(&Ng[j + (int64_t)j * n]));
+          r = 1.0 / fabs(d);
+        }
+        R1pad[(int64_t)np * np + j] = r;
+      }
+    }
+    if (lu && perm_out && g == 0)
+      for (int i = tid; i < s; i += CP_THREADS) perm_out[i] = permg[i];
+  }
+  return;
+timeout:
+  if (threadIdx.x == 0) info_set(info, INFO_SYNC_TIMEOUT, STAGE_LU, 0);
+}
+
+// ---------------------------------------------------------------------------
 // Launchers. n <= 64 (and s <= 256 for the preconditioner) go to the
 // register-resident kernels of k_dense.hip.
 // ---------------------------------------------------------------------------
 size_t precond_scratch_bytes(int64_t s, int64_t n) {
   // generic kernel: A (s*n) + wv (n) + N (n*n) + R (n*n) in doubles, + perm
-  // (s ints), aligned; the register-resident kernel for n > 64: its two tables
+  // (s ints), aligned; the multi-workgroup kernel uses 2 s + 2 n^2 doubles, s
+  // ints and its control block of it; the register-resident kernel for
+  // n > 64: its two tables
   size_t b = ((size_t)s * n + n + 2 * (size_t)n * n) * sizeof(double);
   b = (b + 255) / 256 * 256;
   b += ((size_t)s * sizeof(int32_t) + 255) / 256 * 256;
+  b += coop_ctl_bytes();
   if (n > 64 && precond_reg_fits(s, n) && b < precond_reg_scratch_bytes()) b = precond_reg_scratch_bytes();
   return b;
 }
 
 template <typename T>
-static hipError_t launch_pc(const double* Y, int64_t s, int64_t n, int lu, const double* Nin, int64_t ldn,
-                            double* R1pad, double* R1out, int32_t* perm, double* Mout, double* scratch, int32_t* info,
-                            int32_t stage_qr, hipStream_t st) {
+static hipError_t launch_pc_coop(const double* Y, int64_t s, int64_t n, int lu, const double* Nin, int64_t ldn,
+                                 double* R1pad, double* R1out, int32_t* perm, double* Mout, double* scratch,
+                                 int32_t* info, int32_t stage_qr, hipStream_t st) {
   const int np = pad_cols(n);
-  T* gA = (T*)scratch;
-  T* gN = gA + (size_t)s * n + n;
-  T* gR = gN + (size_t)n * n;
-  size_t off = ((size_t)s * n + n + 2 * (size_t)n * n) * sizeof(double);
+  // scratch: vbuf (2 s) | N (n n) | R_0 (n n) doubles | perm (s ints) | control block
+  double* vbuf = scratch;
+  double* Ng = vbuf + 2 * s;
+  double* R0g = Ng + (size_t)n * n;
+  size_t off = ((size_t)2 * s + 2 * (size_t)n * n) * sizeof(double);
   off = (off + 255) / 256 * 256;
-  int32_t* gperm = (int32_t*)((char*)scratch + off);
-  const size_t lds = ((size_t)s * n + n) * sizeof(T);
-  const int use_lds = lds <= SD_LDS_LIMIT;
-  if (use_lds && lds > 64 * 1024) {
-    hipError_t e =
-        hipFuncSetAttribute((const void*)k_precond<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      return e;
-    }
-  }
-  hipLaunchKernelGGL((k_precond<T>), dim3(1), dim3(SD_THREADS), use_lds ? lds : 0, st, Y, (int)s, (int)n, lu, Nin,
-                     (int)ldn, R1pad, np, R1out, perm, Mout, gA, gN, gR, gperm, use_lds, info, stage_qr);
-  return hipGetLastError();
+  int32_t* permg = (int32_t*)((char*)scratch + off);
+  off += ((size_t)s * sizeof(int32_t) + 255) / 256 * 256;
+  CoopCtl* ctl = (CoopCtl*)((char*)scratch + off);
+  // columns per workgroup: as many as 60 KB of LDS holds, at most CP_MAXC
+  int cpw = (int)(61440 / ((size_t)s * sizeof(T)));
+  if (cpw > CP_MAXC) cpw = CP_MAXC;
+  if (cpw < 1) return hipErrorInvalidValue;
+  const int G = (int)((n + cpw - 1) / cpw);
+  const size_t lds = (size_t)cpw * s * sizeof(T);
+  hipLaunchKernelGGL(k_coop_ctl_init, dim3(1), dim3(64), 0, st, ctl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int si = (int)s, ni = (int)n, ldni = (int)ldn;
+  void* args[] = {(void*)&Y, &si, &ni, &lu, (void*)&Nin, &ldni, &R1pad, (void*)&np, &R1out, &perm, &Mout,
+                  &vbuf, &Ng, &R0g, &permg, &ctl, &cpw, &info, &stage_qr};
+  // a cooperative launch: all G workgroups are resident together (the step
+  // barriers wait for every one of them)
+  return hipLaunchCooperativeKernel((const void*)k_precond_coop<T>, dim3(G), dim3(CP_THREADS), args, (unsigned)lds, st);
 }
 
 hipError_t launch_precond(const double* Y, int64_t s, int64_t n, int lu, int prec, const double* Nin, int64_t ldn,
@@ -574,8 +708,9 @@ hipError_t launch_precond(const double* Y, int64_t s, int64_t n, int lu, int pre
   if (s < n || n < 1 || n > 256) return hipErrorInvalidValue;
   if (precond_reg_fits(s, n))
     return launch_precond_reg(Y, s, n, lu, prec, Nin, ldn, R1pad, R1out, perm, Mout, scratch, info, stage_qr, st);
-  if (prec == 1) return launch_pc<float>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, scratch, info, stage_qr, st);
-  return launch_pc<double>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, scratch, info, stage_qr, st);
+  if (prec == 1)
+    return launch_pc_coop<float>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, scratch, info, stage_qr, st);
+  return launch_pc_coop<double>(Y, s, n, lu, Nin, ldn, R1pad, R1out, perm, Mout, scratch, info, stage_qr, st);
 }
 
 size_t chol_scratch_bytes(int64_t n) { return ((size_t)2 * n * n * sizeof(double) + 255) / 256 * 256; }

@@ -113,7 +113,7 @@ def test_precond_lu_householder(s, n, seed, kappa):
     assert np.linalg.norm(r1.T @ r1 - g) <= 1e-13 * np.linalg.norm(g)
 
 
-@pytest.mark.parametrize("s,n,seed", [(64, 32, 0), (128, 64, 1), (256, 128, 4)])
+@pytest.mark.parametrize("s,n,seed", [(64, 32, 0), (128, 64, 1), (256, 128, 4), (512, 200, 6)])
 @pytest.mark.parametrize("kappa", [1e2, 1e4])
 def test_precond_fp32(s, n, seed, kappa):
     # FP32 LU + Householder on the FP64 sketch, R_1 widened to FP64: an FP32-accurate R factor of Y
@@ -129,7 +129,7 @@ def test_precond_fp32(s, n, seed, kappa):
     assert np.linalg.norm(r1 - r1o) <= 64 * 2.0**-24 * kappa * n * np.linalg.norm(r1o)
 
 
-@pytest.mark.parametrize("s,n", [(64, 32), (40, 40)])
+@pytest.mark.parametrize("s,n", [(64, 32), (40, 40), (300, 64), (520, 150)])
 def test_precond_householder_only(s, n):
     x = make_svd(8 * s, n, 1e4, seed=11)
     y = oracle.sketch(x, s, 3)
@@ -139,9 +139,11 @@ def test_precond_householder_only(s, n):
     assert np.linalg.norm(to_host(R1) - r0) <= 1e-13 * np.linalg.norm(r0)
 
 
+@pytest.mark.parametrize("shape", [(32, 8), (300, 40)])
 @pytest.mark.parametrize("case", ["zero", "zero_then_nan", "nan_first", "inf"])
-def test_precond_info_codes(case):
-    y = np.random.default_rng(0).standard_normal((32, 8))
+def test_precond_info_codes(case, shape):
+    # (300, 40): s > 256, the multi-workgroup kernel
+    y = np.random.default_rng(0).standard_normal(shape)
     if case in ("zero", "zero_then_nan"):
         y[:, 3] = 0.0
     if case == "zero_then_nan":
