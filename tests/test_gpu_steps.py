@@ -188,7 +188,7 @@ def _check_trsm(w, wo, x, R):
 
 
 @pytest.mark.parametrize("m,n", [(1000, 1), (4096 + 77, 16), (3000, 32), (20000 + 5, 50), (9999, 64),
-                                 (5000, 100), (3000, 128), (1500, 256)])
+                                 (5000, 100), (3000, 128), (1200, 129), (2500, 200), (1500, 256)])
 def test_trsm_gram_matches_oracle(m, n):
     rng = np.random.default_rng(m + n)
     x = np.asfortranarray(rng.standard_normal((m, n)))
