@@ -251,9 +251,16 @@ def bench_krylov(lib):
     X = make_krylov_device(m, n, 0)
     ms, info, Q, R = time_qr(lib, X, "rcluppr", s, 0, 1)
     orth, res = gpu_accuracy(X, Q, R)
-    return {"workload": "rcluppr m=%d n=%d s=%d Krylov-monomial (device-generated)" % (m, n, s), "ms": round(ms, 3),
-            "GB_s": round(tall_bytes(m, n)["total"] / (ms / 1e3) / 1e9, 1), "info": info, "orth": orth,
-            "rel_res": res}
+    out = {"workload": "rcluppr m=%d n=%d s=%d Krylov-monomial (device-generated)" % (m, n, s), "ms": round(ms, 3),
+           "GB_s": round(tall_bytes(m, n)["total"] / (ms / 1e3) / 1e9, 1), "info": info, "orth": orth,
+           "rel_res": res}
+    # the mixed-precision form: BF16 sketch of M, FP32 LU/Householder of the sketch
+    del Q, R
+    torch.cuda.empty_cache()
+    ms2, info2, Q, R = time_qr(lib, X, "rcluppr", s, 0, 1, sketch_prec="bf16", lu_prec="fp32")
+    orth2, res2 = gpu_accuracy(X, Q, R)
+    out["mixed_bf16_sketch_fp32_lu"] = {"ms": round(ms2, 3), "info": info2, "orth": orth2, "rel_res": res2}
+    return out
 
 
 def main():
