@@ -223,13 +223,35 @@ __global__ __launch_bounds__(LU_THREADS) void k_lu_trailing(double* __restrict__
     double l[LU_NB];
 #pragma unroll
     for (int t = 0; t < LU_NB; ++t) l[t] = (t < nb) ? M[i + (int64_t)(c0 + t) * ldm] : 0.0;
-    for (int j = 0; j < nt; ++j) {
+    // column 0 first (its argmax partial), then four columns at a time so that
+    // four loads are in flight per thread
+    {
+      double a = M[i + (int64_t)c1 * ldm];
+#pragma unroll
+      for (int t = 0; t < LU_NB; ++t)
+        if (t < nb) a -= l[t] * u[t];
+      M[i + (int64_t)c1 * ldm] = a;
+      track(a, i, best, idx, bad);
+    }
+    int j = 1;
+    for (; j + 3 < nt; j += 4) {
+      double a[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = __builtin_nontemporal_load(M + i + (int64_t)(c1 + j + q) * ldm);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int t = 0; t < LU_NB; ++t)
+          if (t < nb) a[q] -= l[t] * u[t + (j + q) * nb];
+        __builtin_nontemporal_store(a[q], M + i + (int64_t)(c1 + j + q) * ldm);
+      }
+    }
+    for (; j < nt; ++j) {
       double a = M[i + (int64_t)(c1 + j) * ldm];
 #pragma unroll
       for (int t = 0; t < LU_NB; ++t)
         if (t < nb) a -= l[t] * u[t + j * nb];
       M[i + (int64_t)(c1 + j) * ldm] = a;
-      if (j == 0) track(a, i, best, idx, bad);
     }
   }
   wg_argmax_write(best, idx, bad, part + blockIdx.x);
