@@ -104,6 +104,27 @@ __device__ __forceinline__ void info_set(int32_t* info, int32_t code, int32_t st
 
 __device__ __forceinline__ bool is_finite(double v) { return __builtin_isfinite(v); }
 
+// Streaming hints for the tall operands. A 16-row run of one column (a
+// quarter of a wave's load or store) fills one 128-byte line only when the
+// column starts on a line: base 128-byte aligned and ld a multiple of 16
+// elements. With any other leading dimension every run straddles two lines
+// whose other parts belong to the neighbouring runs, and a nontemporal access
+// lets the line leave the caches before the neighbour reaches it (measured:
+// more than twice the time of a pass). The kernels then use ordinary accesses.
+__device__ __forceinline__ bool runs_line_aligned(const void* p, int64_t ld) {
+  return ((ld & 15) == 0) && (((uintptr_t)p & 127) == 0);
+}
+template <bool NT>
+__device__ __forceinline__ double stream_load(const double* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT>
+__device__ __forceinline__ void stream_store(double v, double* p) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 // Makes a wave-uniform pointer opaque to the optimizer and returns it as a
 // constant-address-space pointer, so loads through it are scalar loads issued
 // where they are consumed (inside a row-tile loop) rather than hoisted out of

@@ -11,6 +11,8 @@
 // MFMA Gram kernel over W.
 // Per-workgroup Gram partials are added in a fixed two-level order by
 // k_partial_sum and k_gram_final, so results do not depend on timing.
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "launch.hpp"
 
@@ -127,7 +129,10 @@ __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(co
   // base (scalar) plus a 32-bit per-lane offset (row + (l/16) ld); requires
   // 3 ld + m < 2^29, checked by the launcher. Streamed once: nontemporal, so X
   // and W do not evict R, the tables and the partials from the caches.
-  auto load_x = [&](int64_t tt, f64x4 (&dst)[HB][NB]) {
+  // (nontemporal only when the column runs fill whole lines)
+  const bool ntx = runs_line_aligned(X, ldx), ntw = WRITE && runs_line_aligned(W, ldw);
+  auto load_rows = [&](auto nt, int64_t tt, f64x4 (&dst)[HB][NB]) {
+    constexpr bool NT = decltype(nt)::value;
     const int64_t r0 = tt * tm_tile(NP) + wave * RW;
 #pragma unroll
     for (int h = 0; h < HB; ++h) {
@@ -140,9 +145,13 @@ __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(co
         for (int r = 0; r < 4; ++r) {
           const int col = 16 * b + lq + 4 * r;
           const double* cb = X + (int64_t)(16 * b + 4 * r) * ldx;
-          dst[h][b][r] = (live && col < n) ? __builtin_nontemporal_load(cb + voff) : 0.0;
+          dst[h][b][r] = (live && col < n) ? stream_load<NT>(cb + voff) : 0.0;
         }
     }
+  };
+  auto load_x = [&](int64_t tt, f64x4 (&dst)[HB][NB]) {
+    if (ntx) load_rows(std::true_type{}, tt, dst);
+    else load_rows(std::false_type{}, tt, dst);
   };
   // n = 64 with the Gram: the next tile's loads are issued before this tile's
   // work (64 more registers, still two workgroups per CU), so they are in
@@ -235,21 +244,26 @@ __global__ __launch_bounds__(TP_THREADS, (NP > 128 ? 1 : 2)) void k_tall_mfma(co
       }
     }
     if (WRITE) {
+      auto store_rows = [&](auto nt) {
+        constexpr bool NT = decltype(nt)::value;
 #pragma unroll
-      for (int h = 0; h < HB; ++h) {
-        const int64_t row = row0 + 16 * h + lr;
-        const uint32_t voff = (uint32_t)(row + (int64_t)lq * ldw);
-        if (row < m) {
+        for (int h = 0; h < HB; ++h) {
+          const int64_t row = row0 + 16 * h + lr;
+          const uint32_t voff = (uint32_t)(row + (int64_t)lq * ldw);
+          if (row < m) {
 #pragma unroll
-          for (int b = 0; b < NB; ++b)
+            for (int b = 0; b < NB; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int col = 16 * b + lq + 4 * r;
-              double* cb = W + (int64_t)(16 * b + 4 * r) * ldw;
-              if (col < n) __builtin_nontemporal_store(acc[h][b][r], cb + voff);
-            }
+              for (int r = 0; r < 4; ++r) {
+                const int col = 16 * b + lq + 4 * r;
+                double* cb = W + (int64_t)(16 * b + 4 * r) * ldw;
+                if (col < n) stream_store<NT>(acc[h][b][r], cb + voff);
+              }
+          }
         }
-      }
+      };
+      if (ntw) store_rows(std::true_type{});
+      else store_rows(std::false_type{});
     }
     if (GRAM) {
       // stage 16 rows at a time column-major (stride TM_LDG), then Gram fragments
@@ -351,6 +365,10 @@ __global__ __launch_bounds__(GS_THREADS) void k_tall_gemm_sub(const double* X2, 
     atab[e] = (col < n2) ? -R12[(int64_t)(4 * kk + (l >> 4)) * ldr + col] : 0.0;
   }
   __syncthreads();
+  // nontemporal only when every operand's column runs fill whole lines
+  const bool nt = runs_line_aligned(X2, ldx) && runs_line_aligned(W1, ldw1) && runs_line_aligned(W2, ldw2);
+  auto tiles = [&](auto ntc) {
+  constexpr bool NT = decltype(ntc)::value;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t row0 = t * GS_TILE + wave * 32;
     f64x4 acc[HB][ND];
@@ -366,7 +384,7 @@ __global__ __launch_bounds__(GS_THREADS) void k_tall_gemm_sub(const double* X2, 
         for (int r = 0; r < 4; ++r) {
           const int col = 16 * d + lq + 4 * r;
           const double* cb = X2 + (int64_t)(16 * d + 4 * r) * ldx;
-          acc[h][d][r] = (live && col < n2) ? __builtin_nontemporal_load(cb + voff) : 0.0;
+          acc[h][d][r] = (live && col < n2) ? stream_load<NT>(cb + voff) : 0.0;
         }
     }
 #pragma unroll 2
@@ -377,7 +395,8 @@ __global__ __launch_bounds__(GS_THREADS) void k_tall_gemm_sub(const double* X2, 
 #pragma unroll
       for (int h = 0; h < HB; ++h) {
         const int64_t row = row0 + 16 * h + lr;
-        b[h] = (row < m) ? __builtin_nontemporal_load(wb + (uint32_t)(row + (int64_t)lq * ldw1)) : 0.0;
+        const double* p = wb + (uint32_t)(row + (int64_t)lq * ldw1);
+        b[h] = (row < m) ? stream_load<NT>(p) : 0.0;
       }
 #pragma unroll
       for (int d = 0; d < ND; ++d) {
@@ -397,11 +416,14 @@ __global__ __launch_bounds__(GS_THREADS) void k_tall_gemm_sub(const double* X2, 
           for (int r = 0; r < 4; ++r) {
             const int col = 16 * d + lq + 4 * r;
             double* cb = W2 + (int64_t)(16 * d + 4 * r) * ldw2;
-            if (col < n2) __builtin_nontemporal_store(acc[h][d][r], cb + voff);
+            if (col < n2) stream_store<NT>(acc[h][d][r], cb + voff);
           }
       }
     }
   }
+  };
+  if (nt) tiles(std::true_type{});
+  else tiles(std::false_type{});
 }
 
 // ---------------------------------------------------------------------------
@@ -463,13 +485,20 @@ __global__ __launch_bounds__(64 * gram_waves<NP>()) void k_gram_bal(const double
   // loader: thread -> row tid % 32, columns tid / 32 + (NT / 32) c
   const int ldr = tid & 31, ldc = tid >> 5;
   double pre[PER];
-  auto load = [&](int64_t t) {
+  // (nontemporal only when the column runs fill whole lines)
+  const bool ntw = runs_line_aligned(W, ldw);
+  auto load_rows = [&](auto ntc, int64_t t) {
+    constexpr bool NTL = decltype(ntc)::value;
     const int64_t row = t * 32 + ldr;
 #pragma unroll
     for (int c = 0; c < PER; ++c) {
       const int col = ldc + (NT / 32) * c;
-      pre[c] = (row < m && col < n) ? __builtin_nontemporal_load(W + row + (int64_t)col * ldw) : 0.0;
+      pre[c] = (row < m && col < n) ? stream_load<NTL>(W + row + (int64_t)col * ldw) : 0.0;
     }
+  };
+  auto load = [&](int64_t t) {
+    if (ntw) load_rows(std::true_type{}, t);
+    else load_rows(std::false_type{}, t);
   };
   auto store = [&](int buf) {
 #pragma unroll

@@ -221,6 +221,38 @@ def test_trsm_in_place_and_ld():
     _check_trsm(to_host(X), wo, x, R)
 
 
+@pytest.mark.parametrize("n", [32, 64, 128, 200])
+@pytest.mark.parametrize("layout", ["ld16", "ld_odd", "base_off"])
+def test_trsm_gram_layouts(n, layout):
+    """Both access forms of the tall kernels against the oracle: nontemporal
+    when every column run fills whole 128-byte lines (ld a multiple of 16,
+    aligned base), ordinary loads and stores otherwise (an odd ld; an aligned
+    ld with the matrix starting one row into its buffer, written to an aligned
+    W). Also the Gram of X alone."""
+    m = 4000 + 3 * n
+    rng = np.random.default_rng(7 * n)
+    x = np.asfortranarray(rng.standard_normal((m, n)))
+    R = _upper(n, 5)
+    if layout == "ld16":
+        X = to_dev(x, ld=m + 16 - m % 16)
+    elif layout == "ld_odd":
+        X = to_dev(x, ld=m + 3)
+    else:
+        X = to_dev(np.vstack([np.zeros((1, n)), x]), ld=m + 1 + 16 - (m + 1) % 16)[1:]
+    W, G = _lib().trsm_gram(X, to_dev(R), gram=True)
+    wo = oracle.trsm(x, R)
+    w = to_host(W)
+    _check_trsm(w, wo, x, R)
+    go = oracle.gram(wo)
+    assert np.max(np.abs(to_host(G) - go)) <= 1e-12 * np.max(np.abs(go))
+    _, G0 = _lib().trsm_gram(X, None, gram=True)
+    g0 = oracle.gram(x)
+    assert np.max(np.abs(to_host(G0) - g0)) <= 1e-12 * np.max(np.abs(g0))
+    # in place (W aliases X, same layout)
+    _lib().trsm_gram(X, to_dev(R), gram=False, out=X)
+    _check_trsm(to_host(X), wo, x, R)
+
+
 # ---------------------------------------------------------------- Cholesky
 @pytest.mark.parametrize("n", [1, 16, 50, 64, 128, 200, 256])
 def test_chol_matches_oracle(n):
