@@ -77,13 +77,15 @@ __device__ __forceinline__ T dn_abs(T v) {
 }
 
 // Pivot candidate order: larger |v| first, then the smaller key (position).
+// A strict total order on live candidates (keys are unique), so any reduction
+// tree gives the same winner; selects rather than branches (a branch per
+// candidate costs an exec-mask save and restore on the search's critical path).
 template <typename T>
 __device__ __forceinline__ void piv_take(T& v, int& key, T ov, int okey) {
   const T a = dn_abs(v), b = dn_abs(ov);
-  if (b > a || (b == a && okey < key)) {
-    v = ov;
-    key = okey;
-  }
+  const bool take = (b > a) | ((b == a) & (okey < key));
+  v = take ? ov : v;
+  key = take ? okey : key;
 }
 
 template <int CTRL, typename T>
@@ -146,7 +148,7 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
   int* rowl = posl + SR;
   __shared__ int bc_row[2];
   __shared__ T bc_tau[2];
-  __shared__ int bc_fail, bc_min;
+  __shared__ int bc_min;
   __shared__ double dsg[NT];
   if (info_failed(info)) return;
 
@@ -177,7 +179,6 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
       return posl[tr * A + a];
   };
   if (tid == 0) {
-    bc_fail = 0;
     bc_min = INT_MAX;
   }
   __syncthreads();
@@ -194,16 +195,23 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
           int pp[A];
 #pragma unroll
           for (int a = 0; a < A; ++a) pp[a] = pos(a);
-          T best = T(0);
-          int key = INT_MAX, bad = 0;
+          // candidates (rows not yet pivoted), reduced as a tree
+          T cv[A];
+          int ck[A], bad = 0;
 #pragma unroll
           for (int a = 0; a < A; ++a) {
             const int row = tr + 16 * a;
-            if (row < s && pp[a] >= k) {
-              bad |= !is_finite((double)x[kc][a]);
-              piv_take(best, key, x[kc][a], (pp[a] << 12) | row);
-            }
+            const bool live = (row < s) & (pp[a] >= k);
+            bad |= live & !is_finite((double)x[kc][a]);
+            cv[a] = live ? x[kc][a] : T(0);
+            ck[a] = live ? ((pp[a] << 12) | row) : INT_MAX;
           }
+#pragma unroll
+          for (int w = 1; w < A; w *= 2)
+#pragma unroll
+            for (int a = 0; a + w < A; a += 2 * w) piv_take(cv[a], ck[a], cv[a + w], ck[a + w]);
+          T best = cv[0];
+          int key = ck[0];
           row16_argmax(best, key);
           const bool own = (col0 == kk);
           const bool anybad = __ballot(own && bad) != 0;
@@ -213,16 +221,19 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
             if (code) {
               if (tr == 0) {
                 info_set(info, code, STAGE_LU, k + 1);
-                bc_fail = 1;
+                bc_row[buf] = -1;  // (keys are non-negative)
               }
             } else {
-              // multipliers l_i = x_ik / pivot (true division) for the rows still to eliminate
+              // multipliers l_i = x_ik / pivot (true division) for the rows still to
+              // eliminate; every quotient is formed and then selected, so the A
+              // divisions are independent chains rather than A branches
 #pragma unroll
               for (int a = 0; a < A; ++a) {
                 const int row = tr + 16 * a;
-                const bool live = row < s && pp[a] >= k && row != prow;
-                const T l = live ? x[kc][a] / best : T(0);
-                if (live) x[kc][a] = l;
+                const bool live = (row < s) & (pp[a] >= k) & (row != prow);
+                const T qv = x[kc][a] / best;
+                const T l = live ? qv : T(0);
+                x[kc][a] = live ? l : x[kc][a];
                 vb[buf * SR + tr * A + a] = l;
               }
               if (tr == 0) {
@@ -239,8 +250,8 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
           }
         }
         __syncthreads();
-        if (bc_fail) return;
         const int pkey = __builtin_amdgcn_readfirstlane(bc_row[buf]);
+        if (pkey < 0) return;
         const int prow = pkey & 4095, ppos = pkey >> 12;
         if constexpr (PREG) {  // positions k and ppos trade rows
 #pragma unroll
@@ -354,15 +365,13 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
             tau = (beta - al) / beta;
             scal = T(1) / (al - beta);
           }
+          // (selects, not branches: the A entries are independent)
+          const bool upd = tau != T(0);
 #pragma unroll
           for (int a = 0; a < A; ++a) {
-            const T v = (pp[a] > k && tr + 16 * a < s) ? x[kc][a] * scal : (pp[a] == k ? T(1) : T(0));
-            if (tau != T(0)) {
-              if (pp[a] > k)
-                x[kc][a] = v;
-              else if (pp[a] == k)
-                x[kc][a] = beta;
-            }
+            const bool below = pp[a] > k, diag = pp[a] == k;
+            const T v = (below & (tr + 16 * a < s)) ? x[kc][a] * scal : (diag ? T(1) : T(0));
+            x[kc][a] = (upd & below) ? v : ((upd & diag) ? beta : x[kc][a]);
             vb[buf * SR + tr * A + a] = v;
           }
           if (tr == 0) bc_tau[buf] = tau;
