@@ -224,14 +224,21 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
                 bc_row[buf] = -1;  // (keys are non-negative)
               }
             } else {
-              // multipliers l_i = x_ik / pivot (true division) for the rows still to
-              // eliminate; every quotient is formed and then selected, so the A
-              // divisions are independent chains rather than A branches
+              // multipliers l_i = x_ik / pivot, correctly rounded, for the rows still
+              // to eliminate: one division y = RN(1 / pivot), then per entry
+              // q0 = RN(x y) and RN(q0 + (x - q0 pivot) y), which is RN(x / pivot)
+              // by Markstein's theorem (|x / pivot| <= 1: no overflow; only a
+              // subnormal quotient may differ). The per-entry form is three
+              // independent FP64 operations; a division sequence is a dozen
+              // dependent ones through VCC, so A divisions could not overlap.
+              // Every quotient is formed and then selected (no branches).
+              const T y = T(1) / best;
 #pragma unroll
               for (int a = 0; a < A; ++a) {
                 const int row = tr + 16 * a;
                 const bool live = (row < s) & (pp[a] >= k) & (row != prow);
-                const T qv = x[kc][a] / best;
+                const T q0 = x[kc][a] * y;
+                const T qv = dn_fma(dn_fma(-q0, best, x[kc][a]), y, q0);
                 const T l = live ? qv : T(0);
                 x[kc][a] = live ? l : x[kc][a];
                 vb[buf * SR + tr * A + a] = l;
@@ -539,24 +546,36 @@ __global__ __launch_bounds__(DN_THREADS) void k_chol_reg(const double* __restric
               bc_fail = 1;
             }
           } else {
-            const double rkk = sqrt(d);
+            // row k of R: r_kj = g_kj / r_kk, each correctly rounded through one
+            // reciprocal and Markstein's correction (as the LU multipliers), so
+            // the A quotients are independent three-operation chains
+            const double rkk = sqrt(d), y = 1.0 / rkk;
 #pragma unroll
             for (int a = 0; a < A; ++a) {
               const int row = tr + 16 * a;
-              Rl[k * LD + row] = (row > k) ? x[kc][a] / rkk : (row == k ? rkk : 0.0);
+              const double q0 = x[kc][a] * y;
+              const double q = __builtin_fma(__builtin_fma(-q0, rkk, x[kc][a]), y, q0);
+              Rl[k * LD + row] = (row > k) ? q : (row == k ? rkk : 0.0);
             }
           }
         }
       }
       __syncthreads();
-      if (bc_fail) return;
+      // row k of R read together with the failure flag (one LDS round trip)
+      double rk[A];
+#pragma unroll
+      for (int a = 0; a < A; ++a) rk[a] = Rl[k * LD + tr + 16 * a];
+      double rkc[CS];
+#pragma unroll
+      for (int c = 0; c < CS; ++c) rkc[c] = Rl[k * LD + col0 + 64 * c];
+      if (__builtin_amdgcn_readfirstlane(bc_fail)) return;
 #pragma unroll
       for (int c = kc; c < CS; ++c) {
         if (4 * wave + 3 + 64 * c > k) {
           const int col = col0 + 64 * c;
-          const double rkj = (col > k) ? Rl[k * LD + col] : 0.0;
+          const double rkj = (col > k) ? rkc[c] : 0.0;
 #pragma unroll
-          for (int a = 0; a < A; ++a) x[c][a] = __builtin_fma(-Rl[k * LD + tr + 16 * a], rkj, x[c][a]);
+          for (int a = 0; a < A; ++a) x[c][a] = __builtin_fma(-rk[a], rkj, x[c][a]);
         }
       }
     }
