@@ -21,6 +21,10 @@
  *     are ignored by the unsketched methods; the tall kernels address a
  *     row tile with 32-bit offsets, so m + 3 ld < 2^29 (else
  *     RCLUPP_ERR_UNSUPPORTED); s <= 4096;
+ *   - performance only: X and Q are streamed fastest when every column
+ *     starts on a 128-byte line (pointer 128-byte aligned and ld a multiple
+ *     of 16); any other ld is supported at a lower rate (the tall passes
+ *     then keep lines cached between neighbouring row segments);
  *   - X is read only; X and Q must not overlap; Q and R are written only;
  *   - the sketch is S = G / sqrt(s) with G_ij a standard normal drawn from
  *     Philox4x32-10 (counter = (j lo, j hi, floor(i/4), 0), key = (seed lo,
