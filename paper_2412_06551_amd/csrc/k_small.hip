@@ -250,6 +250,39 @@ __global__ __launch_bounds__(SD_THREADS) void k_chol(const double* __restrict__ 
   }
 }
 
+// Rout = R Rprev for two padded triangles (row-major np x np, identity
+// padding beyond n; eqs. C4, C8: R_3 = R_2 R_1, R = R_4 R_3) on FP64 MFMA: one
+// wave per 16 x 16 output block, R's block row times Rprev's block column over
+// K = I..J (both factors are upper triangular). The output is the user layout
+// (column-major n x n, zeros below the diagonal) or a padded triangle with the
+// reciprocals of its diagonal. Many small workgroups: the single-workgroup
+// product read both factors from L2 one dependent load at a time.
+__global__ __launch_bounds__(64) void k_trmm_pad(const double* __restrict__ Rpad, const double* __restrict__ Rprev,
+                                                 int np, int n, double* __restrict__ Rout, int rout_user,
+                                                 const int32_t* info) {
+  if (info_failed(info)) return;
+  const int nb = np / 16, I = blockIdx.x / nb, J = blockIdx.x % nb;
+  const int lane = threadIdx.x, lr = lane & 15, lq = lane >> 4;
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int K = I; K <= J; ++K)
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const double av = Rpad[(int64_t)(16 * I + lr) * np + 16 * K + 4 * kk + lq];
+      const double bv = Rprev[(int64_t)(16 * K + 4 * kk + lq) * np + 16 * J + lr];
+      acc = mfma_f64(av, bv, acc);
+    }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = 16 * I + lq + 4 * r, j = 16 * J + lr;
+    if (rout_user) {
+      if (i < n && j < n) Rout[i + (int64_t)j * n] = (i > j) ? 0.0 : acc[r];
+    } else {
+      Rout[(int64_t)i * np + j] = (i < n && j < n) ? ((i > j) ? 0.0 : acc[r]) : (i == j ? 1.0 : 0.0);
+      if (i == j) Rout[(int64_t)np * np + i] = (i < n) ? 1.0 / acc[r] : 1.0;
+    }
+  }
+}
+
 __global__ void k_unpad(const double* __restrict__ Rpad, int np, int n, double* __restrict__ R) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * n) return;
@@ -733,8 +766,14 @@ hipError_t launch_chol(const double* G, int ldg, int64_t n, int64_t m, int shift
       return e;
     }
   }
+  // the factor (and its optional right factor) on one workgroup; the product
+  // with the earlier factor from the padded result on many
   hipLaunchKernelGGL(k_chol, dim3(1), dim3(SD_THREADS), use_lds ? lds : 0, st, G, ldg, (int)n, m, shift_mode, Rpad, np,
-                     Rout, rout_user, Rprev, Npost, (int)ldnp, gA, gT, use_lds, info, stage);
+                     nullptr, rout_user, nullptr, Npost, (int)ldnp, gA, gT, use_lds, info, stage);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !Rout) return e;
+  const int nb = np / 16;
+  hipLaunchKernelGGL(k_trmm_pad, dim3(nb * nb), dim3(64), 0, st, Rpad, Rprev, np, (int)n, Rout, rout_user, info);
   return hipGetLastError();
 }
 
