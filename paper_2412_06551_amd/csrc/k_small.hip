@@ -250,6 +250,207 @@ __global__ __launch_bounds__(SD_THREADS) void k_chol(const double* __restrict__ 
   }
 }
 
+// Lane src's value (src a compile-time constant in the unrolled loops below),
+// as a wave-uniform scalar.
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, src), hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+// ---------------------------------------------------------------------------
+// Blocked Cholesky for n in (128, 256] without a right factor: the upper
+// factor of G (+ the shift of Algorithm 4) by 16-column blocks, right-looking.
+// Per block column K:
+//   1. the 16 x 16 diagonal block by unblocked steps on 16 lanes of wave 0
+//      (lane j holds column j; row k of the block is broadcast lane by lane);
+//   2. the block row R_KJ = R_KK^{-T} A_KJ by substitution, one thread per
+//      column;
+//   3. the trailing update A_IJ -= R_KI^T R_KJ for K < I <= J on FP64 MFMA,
+//      16 x 16 blocks dealt round-robin to the waves.
+// The matrix is padded to np x np with the identity (its factor is R padded
+// with the identity) and kept row-major (element (i, j) at j + i np, the
+// padded triangle's own layout) in a global scratch buffer that stays in L2;
+// only its upper block triangle is used. Row-major makes every access below
+// a run of consecutive addresses across lanes (the MFMA layouts put the
+// column index on lane % 16; the block row walks columns across threads). Inside a block every
+// entry takes its terms in ascending order (fma; quotients correctly rounded
+// from one reciprocal, as in the register-resident kernels); across blocks
+// the matrix cores sum four terms at a time, so R agrees with the
+// column-at-a-time form to rounding. The one-workgroup column-at-a-time form
+// took 10 us per column at n = 256 (its updates are dependent L2 loads).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(SD_THREADS) void k_chol_blk(const double* __restrict__ G, int ldg, int n, int64_t m,
+                                                         int shift_mode, double* __restrict__ Rpad, int np,
+                                                         double* __restrict__ A, int32_t* info, int32_t stage) {
+  __shared__ ArgMaxSh amx;
+  __shared__ int fail;
+  __shared__ double rkk_l[16 * 17];  // R_KK (row i, column j at i * 17 + j)
+  __shared__ double yk_l[16];        // RN(1 / r_ii)
+  if (info_failed(info)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int nb = np / 16, total = np * np;
+  // copy in (eight loads in flight per thread: the copy loops are latency
+  // bound on one workgroup) and find the lowest column with a non-finite
+  // entry in the upper triangle
+  int idx = INT_MAX, bad = 0;
+  for (int e0 = tid; e0 < total; e0 += 8 * SD_THREADS) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * SD_THREADS, i = e % np, j = e / np;
+      v[u] = (e < total && i < n && j < n) ? (i <= j ? G[i + (int64_t)j * ldg] : 0.0) : (i == j ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * SD_THREADS, i = e % np, j = e / np;
+      if (e < total) {
+        A[j + (int64_t)i * np] = v[u];
+        if (!is_finite(v[u]) && j < idx) {
+          idx = j;
+          bad = 1;
+        }
+      }
+    }
+  }
+  if (tid == 0) fail = 0;
+  __syncthreads();
+  {
+    double v = bad ? -(double)idx : -1e300;
+    block_argmax(v, idx, bad, &amx);
+    if (bad) {
+      if (tid == 0) info_set(info, INFO_NONFINITE, stage, (int32_t)(-v) + 1);
+      return;
+    }
+  }
+  if (shift_mode == 1) {
+    double gm = 0.0;
+    int idx = 0, bad = 0;
+    for (int j = tid; j < n; j += SD_THREADS) gm = fmax(gm, A[j + (int64_t)j * np]);  // (the diagonal)
+    block_argmax(gm, idx, bad, &amx);
+    const double u = 0x1p-53;
+    const double sigma = 11.0 * ((double)m * (double)n * u + (double)n * (double)(n + 1) * u) * gm;
+    for (int j = tid; j < n; j += SD_THREADS) A[j + (int64_t)j * np] += sigma;
+    __syncthreads();
+  }
+  for (int K = 0; K < nb; ++K) {
+    const int k0 = 16 * K;
+    // 1. diagonal block
+    if (wave == 0) {
+      double c[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) c[i] = (lane < 16 && i <= lane) ? A[k0 + lane + (int64_t)(k0 + i) * np] : 0.0;
+      // (no early exit: the loops stay unrolled, so every index below is a
+      // constant; after a breakdown the remaining steps run on a dummy pivot
+      // and nothing is stored)
+      bool ok = true;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const double d = lane_bcast(c[k], k);
+        if (ok && !(d > 0.0)) {
+          if (lane == 0) {
+            info_set(info, INFO_CHOL_BREAKDOWN, stage, k0 + k + 1);
+            fail = 1;
+          }
+          ok = false;
+        }
+        const double r = sqrt(ok ? d : 1.0), y = 1.0 / r;
+        // row k: r_kj = a_kj / r_kk (Markstein's corrected quotient)
+        const double q0 = c[k] * y;
+        const double q = __builtin_fma(__builtin_fma(-q0, r, c[k]), y, q0);
+        c[k] = (lane == k) ? r : ((lane > k) ? q : c[k]);
+        if (lane == 0) yk_l[k] = y;
+#pragma unroll
+        for (int i = k + 1; i < 16; ++i) {
+          const double rki = lane_bcast(c[k], i);
+          if (lane >= i) c[i] = __builtin_fma(-rki, c[k], c[i]);
+        }
+      }
+      if (ok && lane < 16) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          if (i <= lane) A[k0 + lane + (int64_t)(k0 + i) * np] = c[i];
+          rkk_l[i * 17 + lane] = (i <= lane) ? c[i] : 0.0;
+        }
+      }
+    }
+    __syncthreads();
+    if (fail) return;
+    // 2. block row: column c of the trailing part, x = R_KK^{-T} a
+    const int ncol = np - k0 - 16;
+    if (tid < ncol) {
+      const int64_t col = k0 + 16 + tid;
+      double x[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) x[i] = A[col + (int64_t)(k0 + i) * np];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+#pragma unroll
+        for (int p = 0; p < i; ++p) x[i] = __builtin_fma(-rkk_l[p * 17 + i], x[p], x[i]);
+        const double r = rkk_l[i * 17 + i], y = yk_l[i];
+        const double q0 = x[i] * y;
+        x[i] = __builtin_fma(__builtin_fma(-q0, r, x[i]), y, q0);
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) A[col + (int64_t)(k0 + i) * np] = x[i];
+    }
+    __syncthreads();
+    // 3. trailing blocks K < I <= J
+    const int nt = nb - K - 1, nblk = nt * (nt + 1) / 2;
+    // (two blocks per round: their L2 loads are in flight together)
+    for (int t0 = wave; t0 < nblk; t0 += 2 * SD_WAVES) {
+      f64x4 acc[2];
+      double fa[2][4], fb[2][4];
+      int Ib[2], Jb[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        int J = 0, g = t0 + u * SD_WAVES;
+        if (g >= nblk) g = t0;  // (a repeat of the first block, not stored)
+        while (g > J) {
+          g -= J + 1;
+          ++J;
+        }
+        Ib[u] = K + 1 + g;
+        Jb[u] = K + 1 + J;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[u][r] = A[16 * Jb[u] + lr + (int64_t)(16 * Ib[u] + lq + 4 * r) * np];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          fa[u][kk] = -A[16 * Ib[u] + lr + (int64_t)(k0 + 4 * kk + lq) * np];
+          fb[u][kk] = A[16 * Jb[u] + lr + (int64_t)(k0 + 4 * kk + lq) * np];
+        }
+      }
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) acc[u] = mfma_f64(fa[u][kk], fb[u][kk], acc[u]);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (t0 + u * SD_WAVES < nblk) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) A[16 * Jb[u] + lr + (int64_t)(16 * Ib[u] + lq + 4 * r) * np] = acc[u][r];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int e0 = tid; e0 < total; e0 += 8 * SD_THREADS) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * SD_THREADS, i = e / np, j = e % np;
+      v[u] = (e < total && i <= j) ? A[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * SD_THREADS;
+      if (e < total) Rpad[e] = v[u];
+    }
+  }
+  for (int j = tid; j < np; j += SD_THREADS) Rpad[np * np + j] = 1.0 / A[j + (int64_t)j * np];
+}
+
 // Rout = R Rprev for two padded triangles (row-major np x np, identity
 // padding beyond n; eqs. C4, C8: R_3 = R_2 R_1, R = R_4 R_3) on FP64 MFMA: one
 // wave per 16 x 16 output block, R's block row times Rprev's block column over
@@ -755,6 +956,16 @@ hipError_t launch_chol(const double* G, int ldg, int64_t n, int64_t m, int shift
   const int np = pad_cols(n);
   if (n <= 128 && !(Npost && Rout))
     return launch_chol_reg(G, ldg, n, m, shift_mode, Rpad, Rout, rout_user, Rprev, Npost, ldnp, info, stage, st);
+  if (!Npost) {
+    // blocked factor on one workgroup, then the product with the earlier factor
+    hipLaunchKernelGGL(k_chol_blk, dim3(1), dim3(SD_THREADS), 0, st, G, ldg, (int)n, m, shift_mode, Rpad, np, scratch,
+                       info, stage);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !Rout) return e;
+    hipLaunchKernelGGL(k_trmm_pad, dim3((np / 16) * (np / 16)), dim3(64), 0, st, Rpad, Rprev, np, (int)n, Rout,
+                       rout_user, info);
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)n * n * sizeof(double);
   const int use_lds = lds <= SD_LDS_LIMIT;
   double* gA = scratch;
