@@ -283,6 +283,35 @@ def test_chol_shift_and_breakdown():
     assert info.cpu().tolist()[:3] == [2, 5, 3]
 
 
+@pytest.mark.parametrize("n", [136, 200, 256])
+def test_chol_blocked_shift_breakdown_nonfinite(n):
+    # n > 128: the blocked kernel; Algorithm 4's shift, the first failing
+    # column of a breakdown (a negative pivot) and of a non-finite entry
+    m = 1000000
+    b = np.random.default_rng(n + 1).standard_normal((2 * n, n))
+    g = np.asfortranarray(b.T @ b)
+    R, _, info = _lib().chol(to_dev(g), m=m, shift=True)
+    assert info.cpu().tolist()[0] == 0
+    sigma = oracle.scholqr3_shift(m, n, float(np.max(np.diag(g))))
+    ro, _ = oracle.chol(g, shift=sigma)
+    np.testing.assert_allclose(to_host(R), ro, rtol=0, atol=1e-12 * np.abs(ro).max())
+    # a column made dependent on the earlier ones after the first blocks: the
+    # pivot of column k is exactly zero in exact arithmetic, so it breaks down
+    # there (not earlier) in both; the reported index is the oracle's
+    k = n - 7
+    c = np.random.default_rng(5).standard_normal((2 * n, n))
+    c[:, k] = c[:, 3] - 2.0 * c[:, 20]
+    gd = np.asfortranarray(c.T @ c)
+    gd[k, k] -= 1.0  # now indefinite at column k
+    _, _, info = _lib().chol(to_dev(gd), stage=5)
+    _, io = oracle.chol(gd, stage=5)
+    assert info.cpu().tolist()[:3] == [2, 5, k + 1] == io[:3].tolist()
+    gn = g.copy(order="F")
+    gn[10, 150 if n > 150 else n - 1] = np.nan
+    _, _, info = _lib().chol(to_dev(gn), stage=4)
+    assert info.cpu().tolist()[:3] == [3, 4, (150 if n > 150 else n - 1) + 1]
+
+
 # ---------------------------------------------------------------- tall LU
 @pytest.mark.parametrize("m,n", [(1000, 8), (5000 + 13, 32), (20000, 50), (3000, 64), (2000, 100)])
 def test_tall_lu_matches_oracle(m, n):
