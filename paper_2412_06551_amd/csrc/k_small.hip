@@ -612,6 +612,7 @@ __global__ __launch_bounds__(CP_THREADS) void k_precond_coop(const double* __res
   __shared__ int ami[CP_WAVES], amb[CP_WAVES];
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const unsigned nb = (unsigned)G;
+  (void)cpw;  // the LDS holds cpw columns; G = ceil(n / cpw) keeps every workgroup's count within it
   // (no workgroup writes info before the first barrier, so all read the same)
   if (info_failed(info)) return;
   auto col = [&](int q) { return cols + (size_t)q * s; };
