@@ -6,10 +6,13 @@
 //               (Algorithm 2 steps 2-4; Algorithm 7 steps 3-4 with an external
 //               N; Algorithm 6 step 2 without the LU); several workgroups, one
 //               grid-wide barrier per column step;
-//   k_chol    : upper Cholesky of G (+ the shift of Algorithm 4), optional
-//               right factor (LC2's R_1 = D S_c N) and product with an earlier
-//               factor (R_3 = R_2 R_1, R = R_4 R_3; eqs. C4, C8); one
-//               workgroup (O(n^3), latency bound).
+//   k_chol_blk : upper Cholesky of G (+ the shift of Algorithm 4) for n in
+//               (128, 256], blocked on one workgroup with MFMA trailing updates;
+//   k_trmm_pad : the product with an earlier factor (R_3 = R_2 R_1,
+//               R = R_4 R_3; eqs. C4, C8) on many workgroups;
+//   k_chol    : the column-at-a-time Cholesky with the optional right factor
+//               (LC2's R_1 = D S_c N), one workgroup (O(n^3), latency bound);
+//               used for that right factor when n > 128.
 // k_chol keeps its working copy in LDS when it fits, else in a global scratch
 // buffer (same code through generic pointers). Threads form a 64 x 16 grid: tx
 // walks rows (contiguous in the column-major layout), ty walks columns; the
@@ -508,8 +511,9 @@ __global__ void k_pad(const double* __restrict__ R, int n, int np, double* __res
 // reflector (Householder), publishes the multipliers or the reflector in a
 // double-buffered global vector, and after the barrier every workgroup applies
 // the step to its own columns. Rows are swapped physically in every column,
-// so no position bookkeeping is needed. Same arithmetic as k_precond: true
-// division for the multipliers, dlarfg's beta = -sign(alpha) hypot(alpha, |x|).
+// so no position bookkeeping is needed. The multipliers are true quotients
+// (so the LU factor equals the oracle's bit for bit, as k_precond_reg's
+// does); dlarfg's beta = -sign(alpha) hypot(alpha, |x|).
 // The barrier waits are bounded: a wait that does not end records
 // INFO_SYNC_TIMEOUT and the kernel exits.
 // ---------------------------------------------------------------------------
