@@ -25,6 +25,8 @@ Further legs (skipped with --no-extras), each with its own time and accuracy:
   krylov       = RCLUPPr on m = 16,777,216, n = 128 Krylov-monomial columns.
 Large inputs are generated on the GPU (gen.make_*_device).
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
+       python bench.py --only {mixed,batched,krylov}   (one extra leg alone, for a
+                                                        kernel trace of that workload)
 """
 from __future__ import annotations
 
@@ -271,6 +273,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extras", action="store_true", help="skip the other methods")
     ap.add_argument("--kappa", type=float, default=KAPPA)
+    ap.add_argument("--only", choices=("mixed", "batched", "krylov"),
+                    help="run just that extra leg and print its JSON object (for kernel traces of that workload; "
+                         "not the benchmark line)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain elementwise copy of X (8mn bytes read, 8mn written) before timing, "
                          "as the reference kernel for the HBM traffic counters")
@@ -288,6 +293,10 @@ def main():
     from gen import make_svd
 
     torch.cuda.set_device(0)
+    if args.only:
+        leg = {"mixed": bench_mixed, "batched": bench_batched, "krylov": bench_krylov}[args.only]
+        print(json.dumps({args.only: leg(lib)}), flush=True)
+        return
     dev = torch.device("cuda:0")
     m, n, s = M, N, S
     print("bench: generating %dx%d kappa=%.0e input" % (m, n, args.kappa), file=sys.stderr, flush=True)
