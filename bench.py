@@ -14,6 +14,9 @@ Reported (one JSON line):
   roofline    = the dominant kernel's algorithmic rate (per launch, from HIP
                 events recorded between the launches on the library's stream)
                 against MI355X's published peak for its binding resource;
+  stage_rates = each tall kernel (sketch, substitution+Gram, final substitution)
+                against both ceilings: algorithmic GB/s over the HBM peak and
+                algorithmic FP64 TFLOP/s over the FP64 MFMA peak;
   cpu_baseline= the CPU oracle (oracle/) timed on the host cores on the same
                 input; the same leg also checks the GPU result against it.
 Further legs (skipped with --no-extras), each with its own time and accuracy:
@@ -79,6 +82,24 @@ def measured_traffic(name):
     if not e or e.get("source_sha256_16") != kernel_source_hash(name):
         return None
     return e.get("bytes_per_launch")
+
+
+def stage_rates(stages, m, n, s):
+    """Every tall kernel's rate against both of its ceilings (HBM and FP64 MFMA),
+    from the same per-launch event timings as the roofline entry."""
+    by = tall_bytes(m, n)
+    fl = tall_flops(m, n, s)
+    out = {}
+    for name in ("sketch", "trsm_gram", "trsm_final"):
+        if name not in stages:
+            continue
+        ms, cnt = stages[name]
+        t = ms / cnt / 1e3
+        gbs = by[name] / t / 1e9
+        tfs = fl[name] / t / 1e12
+        out[name] = {"avg_launch_ms": round(ms / cnt, 5), "GB_s": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                     "fp64_TFLOP_s": round(tfs, 2), "frac_fp64": round(tfs / FP64_PEAK_TFLOPS, 4)}
+    return out
 
 
 def roofline_entry(stages, m, n, s):
@@ -360,6 +381,7 @@ def main():
         "gpu_info": gpu_info,
         "stages_ms_per_step": {k: round(v[0] / args.steps, 5) for k, v in stages.items()},
         "roofline": roofline_entry(stages, m, n, s),
+        "stage_rates": stage_rates(stages, m, n, s),
     }
 
     if not args.no_extras:
