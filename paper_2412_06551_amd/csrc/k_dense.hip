@@ -104,6 +104,8 @@ __device__ __forceinline__ void row16_argmax(T& v, int& key) {
 }
 
 __device__ __forceinline__ double dn_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ double dn_min_normal(double) { return 0x1p-1022; }
+__device__ __forceinline__ float dn_min_normal(float) { return 0x1p-126f; }
 __device__ __forceinline__ float dn_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
 // ---------------------------------------------------------------------------
@@ -232,13 +234,21 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
               // independent FP64 operations; a division sequence is a dozen
               // dependent ones through VCC, so A divisions could not overlap.
               // Every quotient is formed and then selected (no branches).
+              // A subnormal pivot (|p| below the smallest normal) would overflow
+              // 1 / p: that step divides directly.
+              const bool tiny = dn_abs(best) < dn_min_normal(best);
               const T y = T(1) / best;
 #pragma unroll
               for (int a = 0; a < A; ++a) {
                 const int row = tr + 16 * a;
                 const bool live = (row < s) & (pp[a] >= k) & (row != prow);
-                const T q0 = x[kc][a] * y;
-                const T qv = dn_fma(dn_fma(-q0, best, x[kc][a]), y, q0);
+                T qv;
+                if (tiny) {
+                  qv = x[kc][a] / best;
+                } else {
+                  const T q0 = x[kc][a] * y;
+                  qv = dn_fma(dn_fma(-q0, best, x[kc][a]), y, q0);
+                }
                 const T l = live ? qv : T(0);
                 x[kc][a] = live ? l : x[kc][a];
                 vb[buf * SR + tr * A + a] = l;

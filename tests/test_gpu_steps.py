@@ -116,6 +116,19 @@ def test_precond_lu_householder(s, n, seed, kappa):
     assert np.linalg.norm(r1.T @ r1 - g) <= 1e-13 * np.linalg.norm(g)
 
 
+@pytest.mark.parametrize("s,n", [(64, 32), (128, 64)])
+def test_precond_lu_subnormal_pivots(s, n):
+    # every entry subnormal: 1 / pivot would overflow, so those steps divide
+    # directly; M still equals the oracle's bit for bit (IEEE subnormals)
+    y = np.asfortranarray(np.random.default_rng(s).standard_normal((s, n)) * 1e-310)
+    assert np.all(np.abs(y) < np.finfo(np.float64).tiny)
+    _, perm, M, info = _lib().precond(to_dev(y), lu=True, want_m=True)
+    Mo, _, po, io = oracle.gepp(y)
+    assert info.cpu().tolist()[0] == 0 and io[0] == 0
+    np.testing.assert_array_equal(perm.cpu().numpy(), po)
+    np.testing.assert_array_equal(to_host(M), Mo)
+
+
 @pytest.mark.parametrize("s,n,seed", [(64, 32, 0), (128, 64, 1), (256, 128, 4), (512, 200, 6)])
 @pytest.mark.parametrize("kappa", [1e2, 1e4])
 def test_precond_fp32(s, n, seed, kappa):
