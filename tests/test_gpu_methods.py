@@ -133,6 +133,16 @@ def test_info_nonfinite_and_zero_column(method):
         assert res.info_host()[:3] == orc.info.tolist()[:3]
 
 
+def test_underflow_scaled_input_is_reported():
+    # X scaled to the underflow threshold: R_1's diagonal is subnormal, its
+    # reciprocals overflow, and the non-finite solve is reported by the first
+    # Cholesky (info, not a silently wrong factor)
+    x = make_svd(3000, 16, 1e2, seed=3) * 1e-312
+    res = _lib().qr(to_dev(np.asfortranarray(x)), alg="rclupp", s=32, seed=0)
+    info = res.info_host()
+    assert info[0] == oracle.NONFINITE and info[1] == oracle.ST_CHOL_A, info
+
+
 def test_invalid_arguments_are_synchronous_errors():
     from paper_2412_06551_amd import _native as nat
     x = to_dev(make_svd(100, 8, 10.0, seed=0))
