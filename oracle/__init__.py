@@ -24,8 +24,18 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SOURCES = ("oracle.c", "checker.c")
+# the oracle's reading (fused multiply-add in the LU elimination and the
+# substitution) and the other one (product and sum rounded separately), which
+# only serves to document outcomes outside the paper's conditions
+VARIANTS = {"": [], "separate_muladd": ["-DORC_SEPARATE_MULADD"]}
+
+
+def _lib_path(variant: str = "") -> str:
+    return os.path.join(_HERE, "liboracle%s.so" % ("_" + variant if variant else ""))
+
+
+_LIB_PATH = _lib_path()
 
 # info codes / stages (the oracle's own definition of the documented convention)
 OK, LU_ZERO_PIVOT, CHOL_BREAKDOWN, NONFINITE, SINGULAR = 0, 1, 2, 3, 4
@@ -35,31 +45,36 @@ U = 2.0 ** -53  # unit roundoff of float64 (Section 1)
 
 
 def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (plain C11, OpenMP, no FP contraction)."""
-    if not force and os.path.exists(_LIB_PATH):
-        return _LIB_PATH
-    srcs = [os.path.join(_HERE, s) for s in _SOURCES]
-    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-    # no implicit contraction; the explicit fma() calls use the FMA instruction
-    cmd = ["gcc", "-std=c11", "-O2", "-mfma", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
-           "-o", tmp] + srcs + ["-lm"]
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB_PATH)
+    """Compile liboracle.so (and its separate-multiply-add variant) with gcc
+    (plain C11, OpenMP, no FP contraction)."""
+    for variant, defs in VARIANTS.items():
+        path = _lib_path(variant)
+        if not force and os.path.exists(path):
+            continue
+        srcs = [os.path.join(_HERE, s) for s in _SOURCES]
+        tmp = path + ".tmp%d" % os.getpid()
+        # no implicit contraction; the explicit fma() calls use the FMA instruction
+        cmd = ["gcc", "-std=c11", "-O2", "-mfma", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off"] + defs + \
+            ["-o", tmp] + srcs + ["-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, path)
     return _LIB_PATH
 
 
-_lib = None
+_libs = {}
 
 
-def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    stale = not os.path.exists(_LIB_PATH) or any(
-        os.path.getmtime(os.path.join(_HERE, s)) > os.path.getmtime(_LIB_PATH) for s in _SOURCES)
+def _load(variant: str = ""):
+    if variant in _libs:
+        return _libs[variant]
+    if variant not in VARIANTS:
+        raise ValueError("unknown oracle variant %r" % variant)
+    path = _lib_path(variant)
+    stale = not os.path.exists(path) or any(
+        os.path.getmtime(os.path.join(_HERE, s)) > os.path.getmtime(path) for s in _SOURCES)
     if stale:
         build(force=True)
-    lib = ctypes.CDLL(_LIB_PATH)
+    lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     I64 = ctypes.c_int64
     U64 = ctypes.c_uint64
@@ -92,7 +107,7 @@ def _load():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = res
-    _lib = lib
+    _libs[variant] = lib
     return lib
 
 
@@ -245,7 +260,7 @@ class Result:
         return int(self.info[0]) == OK
 
 
-def _run(name: str, x, s=None, seed=None) -> Result:
+def _run(name: str, x, s=None, seed=None, variant: str = "") -> Result:
     x = _f64(x)
     m, n = x.shape
     Q = np.zeros((m, n), order="F")
@@ -254,7 +269,7 @@ def _run(name: str, x, s=None, seed=None) -> Result:
     R2 = np.zeros((n, n), order="F")
     R4 = np.zeros((n, n), order="F")
     info = np.zeros(4, dtype=np.int32)
-    lib = _load()
+    lib = _load(variant)
     f = getattr(lib, "orc_" + name)
     if name in ("rclupp", "rcluppr"):
         if not (n <= s <= m):
@@ -306,7 +321,13 @@ METHODS = {"rclupp": rclupp, "rcluppr": rcluppr, "cholqr2": cholqr2, "scholqr3":
            "rcholqr": rcholqr}
 
 
-def run(method: str, x, s=None, seed: int = 0) -> Result:
+def run(method: str, x, s=None, seed: int = 0, variant: str = "") -> Result:
+    """Run one method; variant "separate_muladd" takes the other rounding
+    reading of the LU elimination and the substitution (see VARIANTS)."""
+    if variant:
+        if method in ("rclupp", "rcluppr", "rcholqr"):
+            return _run(method, x, s, seed, variant)
+        return _run(method, x, variant=variant)
     f = METHODS[method]
     if method in ("rclupp", "rcluppr", "rcholqr"):
         return f(x, s, seed)

@@ -47,8 +47,3 @@ def rclupp_bounds(m: int, n: int, xf: float, x2: float, eps: float = 0.5):
     se = math.sqrt(1.0 - eps)
     delta = 4.36 / se * h * n * math.sqrt(n) * U * xf + 3.02 / se * h * n * n * U * x2
     return 6.0 * _c(m, n), delta
-
-
-def rcholqr_orth_bound(m: int, n: int, eps: float = 0.5) -> float:
-    """Lemma 3.4 orthogonality: 5445 / (25 sqrt((1-eps)/(1+eps)) - 3)^2 (mnu+n(n+1)u)."""
-    return 5445.0 / (25.0 * math.sqrt((1.0 - eps) / (1.0 + eps)) - 3.0) ** 2 * _c(m, n)

@@ -44,6 +44,16 @@
 
 #define ORC_BLOCK 4096
 
+/* Multiply-add of the LU elimination and of the substitution. The oracle's
+ * reading is one rounding per term (fused). Built with -DORC_SEPARATE_MULADD
+ * the product and the sum are rounded separately: the other reading, kept to
+ * record how outcomes outside the conditions of eq. (s4) depend on it. */
+#ifdef ORC_SEPARATE_MULADD
+#define ORC_MULADD(a, b, c) ((a) * (b) + (c))
+#else
+#define ORC_MULADD(a, b, c) fma((a), (b), (c))
+#endif
+
 /* info codes */
 #define ORC_OK 0
 #define ORC_LU_ZERO_PIVOT 1
@@ -263,7 +273,7 @@ int orc_gepp(double* A, int64_t r, int64_t n, int64_t lda, int64_t* perm, int32_
       for (int64_t j = k + 1; j < n; ++j) {
         double akj = A[k + j * lda];
         double* aj = A + j * lda;
-        for (int64_t i = i0; i < i1; ++i) aj[i] = fma(-ak[i], akj, aj[i]);
+        for (int64_t i = i0; i < i1; ++i) aj[i] = ORC_MULADD(-ak[i], akj, aj[i]);
       }
     }
   }
@@ -345,7 +355,7 @@ void orc_trsm(const double* X, int64_t m, int64_t n, int64_t ldx, const double* 
     for (int64_t r = 0; r < m; ++r) {
       for (int64_t j = 0; j < n; ++j) {
         double acc = X[r + j * ldx];
-        for (int64_t i = 0; i < j; ++i) acc = fma(-w[i], R[i + j * n], acc);
+        for (int64_t i = 0; i < j; ++i) acc = ORC_MULADD(-w[i], R[i + j * n], acc);
         w[j] = acc / R[j + j * n];
       }
       for (int64_t j = 0; j < n; ++j) W[r + j * ldw] = w[j];

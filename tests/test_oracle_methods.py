@@ -228,12 +228,35 @@ def test_arrowhead_family_rcluppr(beta):
 
 @pytest.mark.parametrize("beta", [1e-25, 1e-30])
 def test_arrowhead_beyond_sufficient_condition(beta):
-    # kappa(N) ~ 1/beta far beyond eq. (s4): with fused multiply-add in the
-    # substitution (no exact cancellation), X R_1^{-1} loses its conditioning and
-    # the Cholesky of the first Gram breaks down at the last column
+    # kappa(N) ~ 1/beta far beyond eq. (s4). The outcome depends on how the
+    # multiply-adds of the LU elimination and the substitution round:
+    #  - fused (the oracle's reading): X R_1^{-1} loses its conditioning and
+    #    the Cholesky of the first Gram breaks down at the last column, so
+    #    Section 5.1.3's stated outcome (RCLUPPr accurate down to 1e-30) is not
+    #    reproduced; RCLUPP, by contrast, succeeds;
+    #  - product and sum rounded separately: RCLUPPr is exact to rounding (the
+    #    stated outcome) and RCLUPP is the one that breaks down.
     x = make_arrowhead(beta)
     r = oracle.rcluppr(x, 100, seed=0)
     assert r.info.tolist()[:3] == [oracle.CHOL_BREAKDOWN, oracle.ST_CHOL_A, 50]
+    r = oracle.rclupp(x, 100, seed=0)
+    assert r.ok and oracle.orthogonality(r.Q) < 1e-14
+    r = oracle.run("rcluppr", x, s=100, seed=0, variant="separate_muladd")
+    m = check_qr(x, r)
+    assert m["orth"] < 1e-28
+    r = oracle.run("rclupp", x, s=100, seed=0, variant="separate_muladd")
+    assert r.info.tolist()[:3] == [oracle.CHOL_BREAKDOWN, oracle.ST_CHOL_A, 50]
+
+
+def test_separate_muladd_variant_agrees_inside_the_conditions():
+    # inside the paper's conditions the two readings agree to rounding
+    x = make_svd(3000, 20, 1e10, seed=31)
+    for method in ("rclupp", "rcluppr", "lc2"):
+        a = oracle.run(method, x, s=40, seed=2)
+        b = oracle.run(method, x, s=40, seed=2, variant="separate_muladd")
+        assert a.ok and b.ok
+        assert np.linalg.norm(a.R - b.R) / np.linalg.norm(a.R) <= 1e-14 * 1e10
+        assert not np.array_equal(a.Q, b.Q)  # the variant is really built differently
 
 
 def test_krylov_rcluppr_vs_householder():
