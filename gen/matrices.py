@@ -138,22 +138,39 @@ def _torch_colmajor(x):
     return out
 
 
+def _orthonormalize_device(u):
+    """Orthonormal columns spanning those of a well-conditioned device matrix u
+    (a Gaussian, kappa ~ 1 + O(sqrt(n/m))): two Cholesky QR passes whose small
+    n x n factors are formed on the host, so the device runs plain matrix
+    products only (no device LAPACK)."""
+    import torch
+    for _ in range(2):
+        g = (u.t() @ u).cpu().numpy()
+        r = np.linalg.cholesky(g).T                       # upper, g = r^T r
+        rinv = np.linalg.inv(r)
+        u = u @ torch.from_numpy(np.ascontiguousarray(rinv)).to(u.device)
+    return u
+
+
 def make_svd_device(m: int, n: int, kappa: float, seed: int = 0, device="cuda", orthonormal: bool = True):
     """X = U diag(sigma) V^T on the device, column-major, sigma as in make_svd.
 
-    orthonormal=True: U is the Q factor of a Gaussian (kappa_2(X) = kappa).
+    orthonormal=True: U has orthonormal columns spanning a Gaussian's
+    (kappa_2(X) = kappa to rounding).
     orthonormal=False: U is a Gaussian with unit columns, whose condition number
     is 1 + O(sqrt(n/m)), so kappa_2(X) is kappa to within a few percent (cheap
-    enough for hundreds of matrices)."""
+    enough for hundreds of matrices).
+    V is the sign-fixed Q factor of a seeded n x n Gaussian, formed on the host."""
     import torch
     g = torch.Generator(device=device)
     g.manual_seed(int(seed))
     u = torch.randn((m, n), generator=g, dtype=torch.float64, device=device)
     if orthonormal:
-        u, _ = torch.linalg.qr(u, mode="reduced")
+        u = _orthonormalize_device(u)
     else:
         u /= torch.linalg.vector_norm(u, dim=0, keepdim=True)
-    v, _ = torch.linalg.qr(torch.randn((n, n), generator=g, dtype=torch.float64, device=device))
+    v = _orthonormal_columns(np.random.default_rng(int(seed) + 7919), n, n)
+    v = torch.from_numpy(np.ascontiguousarray(v)).to(u.device)
     if n == 1:
         sig = torch.ones(1, dtype=torch.float64, device=device)
     else:

@@ -32,7 +32,8 @@
  *     (seed, i, j); see rclupp_omega;
  *   - all work is enqueued on `stream` (a hipStream_t; NULL = default
  *     stream); calls return before the work finishes and never synchronize
- *     the device, except rclupp_last_info;
+ *     the device, except rclupp_last_info, rclupp_release and the first
+ *     autotuned batched call for a batch shape;
  *   - synchronous errors (bad arguments, unsupported sizes, allocation or
  *     launch failures) are returned as an rclupp_status and nothing is
  *     enqueued for them;
@@ -164,6 +165,15 @@ int rclupp_last_info(hipStream_t stream, rclupp_info* h_info);
 /* Static description of a status code. */
 const char* rclupp_status_string(int status);
 
+/* Frees every object the library keeps for the life of the process: the
+ * pinned job tables and cached graphs of the batched form, its capture
+ * streams and autotuning results, the stage-timing events and the per-stream
+ * outcome slots of the 9-argument forms. It waits for the library's work on
+ * the device to finish first. Afterwards the library can be used again
+ * (rclupp_last_info then knows no earlier call). Meant for orderly shutdown
+ * before the HIP runtime is torn down, e.g. from an exit handler. */
+int rclupp_release(void);
+
 /* ---------------------------------------------------------------------------
  * Full-control form: caller-owned workspace and device info.
  *   rclupp_workspace_size: bytes of device workspace needed by rclupp_qr_ex for
@@ -189,8 +199,14 @@ int rclupp_qr_ex(int alg, const double* X, int64_t m, int64_t n, int64_t ld, int
  * row chunks, one workgroup each; small stages take one workgroup per
  * problem), optionally graph-captured and autotuned (opts->batch_flags).
  * Other batches run problem after problem with the single-problem pipeline.
- * Without RCLUPP_BATCH_GRAPH the call waits for the upload of its job tables
- * (a short host synchronization of `stream`).
+ * The job tables are built on the host in pinned memory that the library
+ * keeps (reused once the upload that read it has completed, freed by
+ * rclupp_release) and uploaded on `stream`; the call does not wait for them.
+ * Captured graphs are cached per argument set (16 entries, least recently
+ * used evicted; an evicted graph is destroyed once its last replay is done).
+ * h_probs is a host array because the grouping, the partition into
+ * workgroups and the job tables are planned on the host before anything is
+ * enqueued; alg takes the rclupp_alg values as a plain int (ABI-stable).
  * ------------------------------------------------------------------------- */
 typedef struct {
   const double* X;

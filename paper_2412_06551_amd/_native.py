@@ -6,6 +6,7 @@ CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 
@@ -28,7 +29,7 @@ EXPORTS = [
     "rclupp_last_info", "rclupp_status_string", "rclupp_workspace_size", "rclupp_qr_ex",
     "rclupp_batched_workspace_size", "rclupp_qr_batched", "rclupp_omega", "rclupp_philox",
     "rclupp_sketch", "rclupp_precond", "rclupp_trsm_gram", "rclupp_chol", "rclupp_tall_lu",
-    "rclupp_trace_enable", "rclupp_trace_read",
+    "rclupp_trace_enable", "rclupp_trace_read", "rclupp_release",
 ]
 
 
@@ -88,6 +89,7 @@ def load(path: str = LIB_PATH):
         "rclupp_tall_lu": [P, I64, I64, I64, P, I64, P, P, P],
         "rclupp_trace_enable": [ctypes.c_int],
         "rclupp_trace_read": [ctypes.c_int, ctypes.c_char_p, ctypes.c_int, P, P, P],
+        "rclupp_release": [],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -96,7 +98,17 @@ def load(path: str = LIB_PATH):
     lib.rclupp_status_string.argtypes = [ctypes.c_int]
     lib.rclupp_status_string.restype = ctypes.c_char_p
     _lib = lib
+    # free the library's process-lifetime HIP objects (pinned tables, cached
+    # graphs, events, streams) before the HIP runtime is torn down at exit
+    atexit.register(release)
     return lib
+
+
+def release() -> None:
+    """rclupp_release: free the library's process-lifetime objects (no-op if
+    the library was never loaded)."""
+    if _lib is not None:
+        check(_lib.rclupp_release(), "rclupp_release")
 
 
 def status_string(status: int) -> str:

@@ -689,14 +689,89 @@ uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
   return h;
 }
 
+// ---- pinned staging of the job tables ---------------------------------------------
+// The tables are built on the host and uploaded on the stream, so their pinned
+// source must outlive the upload (for a captured graph: every replay). Buffers
+// come from a pool and are reused only once the event recorded after their
+// last use has completed; that is polled, never waited for. When no buffer is
+// free a new one is allocated (hipHostMalloc does not synchronize; hipHostFree
+// does, so buffers are freed only by rclupp_release).
+struct PinnedBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;  // recorded after the last enqueued use
+  bool held = false;          // in use by a call being enqueued or by a cached graph
+  bool recorded = false;      // `done` has been recorded at least once
+};
+
 struct GraphEntry {
   hipGraphExec_t exec = nullptr;
-  void* host_tables = nullptr;  // pinned image the captured copy reads on every replay
+  PinnedBuf* tables = nullptr;   // pinned image the captured copy reads on every replay
+  hipEvent_t launched = nullptr; // recorded after every replay
+  bool replayed = false;
+  uint64_t tick = 0;             // last use (least recently used entries are evicted first)
 };
-std::mutex g_batch_mu;
+struct RetiredExec {
+  hipGraphExec_t exec;
+  hipEvent_t launched;
+  bool replayed;
+};
+
+std::mutex g_batch_mu;  // guards everything below
+std::vector<PinnedBuf*> g_pinned;
 std::map<uint64_t, GraphEntry> g_graphs;
+std::vector<RetiredExec> g_retired;  // evicted graphs whose last replay may still run
+uint64_t g_tick = 0;
 std::map<uint64_t, int> g_tuned;  // batch shape -> tall tiles per workgroup
 std::map<int, hipStream_t> g_capture_stream;
+constexpr size_t kGraphCacheEntries = 16;
+
+PinnedBuf* pinned_acquire(size_t bytes) {
+  for (PinnedBuf* b : g_pinned) {
+    if (b->held || b->bytes < bytes) continue;
+    if (b->recorded && hipEventQuery(b->done) != hipSuccess) continue;  // in flight (or unknown)
+    b->held = true;
+    return b;
+  }
+  PinnedBuf* b = new PinnedBuf;
+  b->bytes = bytes < 4096 ? 4096 : bytes;
+  if (hipHostMalloc(&b->ptr, b->bytes, hipHostMallocDefault) != hipSuccess) {
+    delete b;
+    return nullptr;
+  }
+  if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+    g_pinned.push_back(b);  // kept (held) so that rclupp_release frees it
+    b->held = true;
+    return nullptr;
+  }
+  b->held = true;
+  g_pinned.push_back(b);
+  return b;
+}
+
+// The buffer becomes reusable once the work enqueued so far on `st` is done.
+// If the event cannot be recorded the buffer stays held (never reused).
+int pinned_release_after(PinnedBuf* b, hipStream_t st) {
+  if (hipEventRecord(b->done, st) != hipSuccess) return RCLUPP_ERR_HIP;
+  b->recorded = true;
+  b->held = false;
+  return RCLUPP_OK;
+}
+
+// Destroys the retired graph executables whose last replay has completed.
+void reap_retired() {
+  for (size_t i = 0; i < g_retired.size();) {
+    RetiredExec& r = g_retired[i];
+    if (r.replayed && hipEventQuery(r.launched) != hipSuccess) {
+      ++i;
+      continue;
+    }
+    (void)hipGraphExecDestroy(r.exec);
+    (void)hipEventDestroy(r.launched);
+    g_retired[i] = g_retired.back();
+    g_retired.pop_back();
+  }
+}
 
 uint64_t shape_key(const rclupp_problem* h, int batch, const rclupp_opts* o) {
   uint64_t k = 1469598103934665603ull;
@@ -708,12 +783,11 @@ uint64_t shape_key(const rclupp_problem* h, int batch, const rclupp_opts* o) {
   return fnv1a(k, pr, sizeof(pr));
 }
 
-// Host side of a grouped run: the job tables and their pinned image (the
-// upload's source, which must outlive the copy; a captured graph re-reads it
-// on every replay).
+// Host side of a grouped run: the job tables written into a pinned buffer
+// (held by the caller until it releases or hands it to a graph entry).
 struct BatchPrep {
   std::vector<GroupTables> gt;
-  void* pinned = nullptr;
+  PinnedBuf* buf = nullptr;
   size_t bytes = 0;
 };
 
@@ -722,18 +796,32 @@ int batch_prepare(const BatchPlan& P, const rclupp_problem* h, char* ws, rclupp_
   out->gt = build_tables(P, h, ws, infos, img);
   if (img.size() > P.table_bytes) return RCLUPP_ERR_WORKSPACE;
   out->bytes = img.size() ? img.size() : 1;
-  if (hipHostMalloc(&out->pinned, out->bytes, hipHostMallocDefault) != hipSuccess) return RCLUPP_ERR_ALLOC;
-  if (!img.empty()) std::memcpy(out->pinned, img.data(), img.size());
+  out->buf = pinned_acquire(out->bytes);
+  if (!out->buf) return RCLUPP_ERR_ALLOC;
+  if (!img.empty()) std::memcpy(out->buf->ptr, img.data(), img.size());
   return RCLUPP_OK;
 }
 
 // Stream part of a grouped run: the table upload, then the launch sequence.
 int batch_enqueue(const BatchPlan& P, const BatchPrep& prep, int batch, const rclupp_opts* o, char* ws,
-                  rclupp_info* infos, hipStream_t st, hipEvent_t copied) {
-  if (hipMemcpyAsync(ws + P.table_off, prep.pinned, prep.bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+                  rclupp_info* infos, hipStream_t st) {
+  if (hipMemcpyAsync(ws + P.table_off, prep.buf->ptr, prep.bytes, hipMemcpyHostToDevice, st) != hipSuccess)
     return RCLUPP_ERR_HIP;
-  if (copied && hipEventRecord(copied, st) != hipSuccess) return RCLUPP_ERR_HIP;
   return batch_launch(P, prep.gt, ws + P.table_off, infos, batch, o, st);
+}
+
+// Enqueues one grouped run (tables, upload, launches) and hands the pinned
+// buffer back to the pool behind an event. Called with g_batch_mu held.
+int batch_run_once(const BatchPlan& P, const rclupp_problem* h, int batch, const rclupp_opts* o, char* ws,
+                   rclupp_info* infos, hipStream_t st) {
+  BatchPrep prep;
+  int rc = batch_prepare(P, h, ws, infos, &prep);
+  if (rc == RCLUPP_OK) rc = batch_enqueue(P, prep, batch, o, ws, infos, st);
+  if (prep.buf) {
+    const int rr = pinned_release_after(prep.buf, st);
+    if (rc == RCLUPP_OK) rc = rr;
+  }
+  return rc;
 }
 
 int batched_grouped(int alg, const rclupp_problem* h, int batch, const rclupp_opts* o, void* ws_v, size_t ws_bytes,
@@ -743,32 +831,33 @@ int batched_grouped(int alg, const rclupp_problem* h, int batch, const rclupp_op
   const int flags = o ? o->batch_flags : 0;
   int tpw = kDefaultTpw;
   const uint64_t skey = shape_key(h, batch, o);
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  reap_retired();
   if (flags & RCLUPP_BATCH_AUTOTUNE) {
-    std::unique_lock<std::mutex> lk(g_batch_mu);
     auto it = g_tuned.find(skey);
     if (it != g_tuned.end()) {
       tpw = it->second;
     } else {
-      lk.unlock();
-      // time every candidate once (each run is a complete batch) and keep the fastest
+      // time every candidate once (each run is a complete batch; this waits
+      // for the stream, as the header states) and keep the fastest
       float best = 0.f;
       int best_tpw = kDefaultTpw;
       hipEvent_t e0, e1;
-      if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return RCLUPP_ERR_HIP;
+      if (hipEventCreate(&e0) != hipSuccess) return RCLUPP_ERR_HIP;
+      if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return RCLUPP_ERR_HIP;
+      }
+      int rc = RCLUPP_OK;
       for (int cand : kTuneTpw) {
         BatchPlan P = make_batch_plan(h, batch, o, cand);
         if (P.total > ws_bytes) continue;
         rclupp_info* infos = d_info ? d_info : (rclupp_info*)(ws + P.info_off);
-        BatchPrep prep;
-        int rc = batch_prepare(P, h, ws, infos, &prep);
-        if (rc == RCLUPP_OK) {
-          (void)hipEventRecord(e0, stream);
-          rc = batch_enqueue(P, prep, batch, o, ws, infos, stream, nullptr);
-          (void)hipEventRecord(e1, stream);
-          (void)hipEventSynchronize(e1);
-        }
-        if (prep.pinned) (void)hipHostFree(prep.pinned);
-        if (rc) return rc;
+        if (hipEventRecord(e0, stream) != hipSuccess) rc = RCLUPP_ERR_HIP;
+        if (rc == RCLUPP_OK) rc = batch_run_once(P, h, batch, o, ws, infos, stream);
+        if (rc == RCLUPP_OK && hipEventRecord(e1, stream) != hipSuccess) rc = RCLUPP_ERR_HIP;
+        if (rc == RCLUPP_OK && hipEventSynchronize(e1) != hipSuccess) rc = RCLUPP_ERR_HIP;
+        if (rc) break;
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, e0, e1);
         if (best == 0.f || ms < best) {
@@ -778,37 +867,20 @@ int batched_grouped(int alg, const rclupp_problem* h, int batch, const rclupp_op
       }
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
+      if (rc) return rc;
       tpw = best_tpw;
-      std::lock_guard<std::mutex> lk2(g_batch_mu);
       g_tuned[skey] = tpw;
     }
   }
   BatchPlan P = make_batch_plan(h, batch, o, tpw);
   if (P.total > ws_bytes) return RCLUPP_ERR_WORKSPACE;
   rclupp_info* infos = d_info ? d_info : (rclupp_info*)(ws + P.info_off);
-  if (!(flags & RCLUPP_BATCH_GRAPH)) {
-    BatchPrep prep;
-    int rc = batch_prepare(P, h, ws, infos, &prep);
-    if (rc == RCLUPP_OK) {
-      hipEvent_t copied;
-      if (hipEventCreateWithFlags(&copied, hipEventDisableTiming) != hipSuccess) {
-        (void)hipHostFree(prep.pinned);
-        return RCLUPP_ERR_HIP;
-      }
-      rc = batch_enqueue(P, prep, batch, o, ws, infos, stream, copied);
-      // the table upload must finish before its pinned source goes away
-      (void)hipEventSynchronize(copied);
-      (void)hipEventDestroy(copied);
-    }
-    if (prep.pinned) (void)hipHostFree(prep.pinned);
-    return rc;
-  }
+  if (!(flags & RCLUPP_BATCH_GRAPH)) return batch_run_once(P, h, batch, o, ws, infos, stream);
   // graph: key = every argument that the captured sequence depends on
   uint64_t key = fnv1a(skey, h, sizeof(rclupp_problem) * (size_t)batch);
   const void* ptrs[3] = {ws_v, (const void*)d_info, nullptr};
   key = fnv1a(key, ptrs, sizeof(ptrs));
   key = fnv1a(key, &tpw, sizeof(tpw));
-  std::lock_guard<std::mutex> lk(g_batch_mu);
   auto it = g_graphs.find(key);
   if (it == g_graphs.end()) {
     int dev = 0;
@@ -818,47 +890,113 @@ int batched_grouped(int alg, const rclupp_problem* h, int batch, const rclupp_op
       if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return RCLUPP_ERR_HIP;
       g_capture_stream[dev] = cs;
     }
+    GraphEntry e;
+    if (hipEventCreateWithFlags(&e.launched, hipEventDisableTiming) != hipSuccess) return RCLUPP_ERR_HIP;
     BatchPrep prep;
     int rc = batch_prepare(P, h, ws, infos, &prep);
+    hipGraph_t graph = nullptr;
+    if (rc == RCLUPP_OK) {
+      if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        rc = RCLUPP_ERR_HIP;
+      } else {
+        rc = batch_enqueue(P, prep, batch, o, ws, infos, cs);
+        const hipError_t ec = hipStreamEndCapture(cs, &graph);
+        if (rc == RCLUPP_OK && ec != hipSuccess) rc = RCLUPP_ERR_HIP;
+      }
+    }
+    if (rc == RCLUPP_OK && hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0) != hipSuccess) rc = RCLUPP_ERR_HIP;
+    if (graph) (void)hipGraphDestroy(graph);
     if (rc) {
-      if (prep.pinned) (void)hipHostFree(prep.pinned);
+      // nothing was enqueued from the buffer: it is free again at once
+      if (prep.buf) prep.buf->held = false;
+      (void)hipEventDestroy(e.launched);
       return rc;
     }
-    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-      (void)hipHostFree(prep.pinned);
-      return RCLUPP_ERR_HIP;
-    }
-    rc = batch_enqueue(P, prep, batch, o, ws, infos, cs, nullptr);
-    hipGraph_t graph = nullptr;
-    const hipError_t ec = hipStreamEndCapture(cs, &graph);
-    if (rc || ec != hipSuccess) {
-      if (graph) (void)hipGraphDestroy(graph);
-      (void)hipHostFree(prep.pinned);
-      return rc ? rc : RCLUPP_ERR_HIP;
-    }
-    GraphEntry e;
-    e.host_tables = prep.pinned;
-    void* keep = prep.pinned;
-    const hipError_t ei = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (ei != hipSuccess) {
-      (void)hipHostFree(keep);
-      return RCLUPP_ERR_HIP;
-    }
-    if (g_graphs.size() >= 16) {  // bounded cache: drop the oldest key
+    e.tables = prep.buf;
+    if (g_graphs.size() >= kGraphCacheEntries) {
+      // evict the least recently used entry: its pinned tables return to the
+      // pool behind the event of its last replay, and the executable is
+      // destroyed once that replay has completed (reap_retired)
       auto old = g_graphs.begin();
-      (void)hipGraphExecDestroy(old->second.exec);
-      (void)hipHostFree(old->second.host_tables);
+      for (auto jt = g_graphs.begin(); jt != g_graphs.end(); ++jt)
+        if (jt->second.tick < old->second.tick) old = jt;
+      GraphEntry& v = old->second;
+      v.tables->held = false;  // its `done` event already follows the last replay
+      g_retired.push_back({v.exec, v.launched, v.replayed});
       g_graphs.erase(old);
+      reap_retired();
     }
     it = g_graphs.emplace(key, e).first;
   }
-  return hipGraphLaunch(it->second.exec, stream) == hipSuccess ? RCLUPP_OK : RCLUPP_ERR_HIP;
+  GraphEntry& ge = it->second;
+  ge.tick = ++g_tick;
+  if (hipGraphLaunch(ge.exec, stream) != hipSuccess) return RCLUPP_ERR_HIP;
+  // both events follow this replay: the entry's (for its executable) and the
+  // pinned buffer's (for reuse of the tables after eviction)
+  if (hipEventRecord(ge.launched, stream) != hipSuccess) return RCLUPP_ERR_HIP;
+  ge.replayed = true;
+  if (hipEventRecord(ge.tables->done, stream) != hipSuccess) return RCLUPP_ERR_HIP;
+  ge.tables->recorded = true;
+  return RCLUPP_OK;
+}
+
+// Frees every process-lifetime object of the library (rclupp_release).
+int release_all() {
+  int rc = RCLUPP_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    for (auto& kv : g_graphs) {
+      GraphEntry& v = kv.second;
+      if (v.replayed && hipEventSynchronize(v.launched) != hipSuccess) rc = RCLUPP_ERR_HIP;
+      if (hipGraphExecDestroy(v.exec) != hipSuccess) rc = RCLUPP_ERR_HIP;
+      (void)hipEventDestroy(v.launched);
+      if (v.tables) v.tables->held = false;
+    }
+    g_graphs.clear();
+    for (RetiredExec& r : g_retired) {
+      if (r.replayed && hipEventSynchronize(r.launched) != hipSuccess) rc = RCLUPP_ERR_HIP;
+      (void)hipGraphExecDestroy(r.exec);
+      (void)hipEventDestroy(r.launched);
+    }
+    g_retired.clear();
+    for (PinnedBuf* b : g_pinned) {
+      if (b->recorded && hipEventSynchronize(b->done) != hipSuccess) rc = RCLUPP_ERR_HIP;
+      if (b->done) (void)hipEventDestroy(b->done);
+      if (b->ptr && hipHostFree(b->ptr) != hipSuccess) rc = RCLUPP_ERR_HIP;
+      delete b;
+    }
+    g_pinned.clear();
+    for (auto& kv : g_capture_stream)
+      if (kv.second && hipStreamDestroy(kv.second) != hipSuccess) rc = RCLUPP_ERR_HIP;
+    g_capture_stream.clear();
+    g_tuned.clear();
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_trace_mu);
+    g_trace_on = false;
+    g_trace_marks.clear();
+    for (hipEvent_t ev : g_trace_pool) {
+      if (hipEventSynchronize(ev) != hipSuccess) rc = RCLUPP_ERR_HIP;
+      (void)hipEventDestroy(ev);
+    }
+    g_trace_pool.clear();
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    // (hipHostFree waits for the device, so the outcome copies enqueued into
+    // the slots have completed before they are freed)
+    for (auto& kv : g_last)
+      if (hipHostFree(kv.second) != hipSuccess) rc = RCLUPP_ERR_HIP;
+    g_last.clear();
+  }
+  return rc;
 }
 
 }  // namespace
 
 extern "C" {
+
+int rclupp_release(void) { return release_all(); }
 
 int rclupp_batched_workspace_size(int alg, const rclupp_problem* h_probs, int batch, const rclupp_opts* opts,
                                   size_t* bytes) {

@@ -234,16 +234,19 @@ __global__ __launch_bounds__(DN_THREADS) void k_precond_reg(const double* __rest
               // independent FP64 operations; a division sequence is a dozen
               // dependent ones through VCC, so A divisions could not overlap.
               // Every quotient is formed and then selected (no branches).
-              // A subnormal pivot (|p| below the smallest normal) would overflow
-              // 1 / p: that step divides directly.
-              const bool tiny = dn_abs(best) < dn_min_normal(best);
+              // Markstein's theorem needs y = RN(1 / p) normal: a subnormal pivot
+              // (|p| below the smallest normal) would overflow 1 / p, and a pivot
+              // above 1 / (smallest normal) has a subnormal reciprocal that has
+              // lost bits. Such steps divide directly.
+              const T ap = dn_abs(best);
+              const bool direct = ap < dn_min_normal(best) || ap > T(1) / dn_min_normal(best);
               const T y = T(1) / best;
 #pragma unroll
               for (int a = 0; a < A; ++a) {
                 const int row = tr + 16 * a;
                 const bool live = (row < s) & (pp[a] >= k) & (row != prow);
                 T qv;
-                if (tiny) {
+                if (direct) {
                   qv = x[kc][a] / best;
                 } else {
                   const T q0 = x[kc][a] * y;
@@ -558,7 +561,9 @@ __global__ __launch_bounds__(DN_THREADS) void k_chol_reg(const double* __restric
           } else {
             // row k of R: r_kj = g_kj / r_kk, each correctly rounded through one
             // reciprocal and Markstein's correction (as the LU multipliers), so
-            // the A quotients are independent three-operation chains
+            // the A quotients are independent three-operation chains. r_kk is a
+            // square root of a positive double, so it lies in [2^-537, 2^512]
+            // and its reciprocal is always normal (the theorem's condition).
             const double rkk = sqrt(d), y = 1.0 / rkk;
 #pragma unroll
             for (int a = 0; a < A; ++a) {

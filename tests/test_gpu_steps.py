@@ -48,7 +48,7 @@ def test_omega_normals_match(s, cols, j0, seed):
     # hardware log2, sqrt, sin and cos (in revolutions), measured within 8 float32
     # ulps of max(|z|, 1) of the float32 library transform
     err = np.abs(g - want)
-    assert np.all(err <= 16 * 2.0**-24 * np.maximum(np.abs(want), 1.0)), err.max()
+    assert np.all(err <= 8 * 2.0**-24 * np.maximum(np.abs(want), 1.0)), err.max()
 
 
 # ---------------------------------------------------------------- sketch
@@ -59,8 +59,8 @@ def test_sketch_matches_oracle(m, n, s, seed):
     y = to_host(_lib().sketch(to_dev(x), s, seed))
     want = oracle.sketch(x, s, seed)
     om = oracle.omega(s, m, seed)
-    # |dY| <= (16 float32 ulps of Omega, as for the normals) |Omega| |X| + summation error
-    bound = (16 * 2.0**-24 + 4 * m * oracle.U) * (np.abs(om) @ np.abs(x))
+    # |dY| <= (8 float32 ulps of Omega, as for the normals) |Omega| |X| + summation error
+    bound = (8 * 2.0**-24 + 4 * m * oracle.U) * (np.abs(om) @ np.abs(x))
     assert np.all(np.abs(y - want) <= bound)
 
 
@@ -127,6 +127,43 @@ def test_precond_lu_subnormal_pivots(s, n):
     assert info.cpu().tolist()[0] == 0 and io[0] == 0
     np.testing.assert_array_equal(perm.cpu().numpy(), po)
     np.testing.assert_array_equal(to_host(M), Mo)
+
+
+@pytest.mark.parametrize("s,n", [(64, 32), (128, 64), (256, 128)])
+def test_precond_lu_huge_pivots(s, n):
+    # entries near the overflow threshold: pivots above 2^1022 have a subnormal
+    # reciprocal, so those steps divide directly and M still equals the
+    # oracle's bit for bit. R_1 = R_0 N may overflow here, which the kernel
+    # reports after M is written.
+    y = np.asfortranarray(np.random.default_rng(s).standard_normal((s, n)) * 2.0**1021)
+    assert np.abs(y).max() > 2.0**1022 and np.all(np.isfinite(y))
+    _, perm, M, info = _lib().precond(to_dev(y), lu=True, want_m=True)
+    Mo, _, po, io = oracle.gepp(y)
+    assert io[0] == 0
+    assert info.cpu().tolist()[0] in (0, oracle.NONFINITE)
+    np.testing.assert_array_equal(perm.cpu().numpy(), po)
+    np.testing.assert_array_equal(to_host(M), Mo)
+
+
+@pytest.mark.parametrize("s,n", [(64, 32), (256, 128)])
+def test_precond_fp32_huge_pivot(s, n):
+    # FP32 LU with a first pivot above 2^126 (its reciprocal is subnormal in
+    # FP32): the step divides directly and R_1 keeps FP32 accuracy row by row
+    rng = np.random.default_rng(s + n)
+    y = rng.standard_normal((s, n))
+    y[:, 0] *= 2.0**120
+    y[3, 0] = 1.5 * 2.0**126
+    y = np.asfortranarray(y)
+    R1, _, _, info = _lib().precond(to_dev(y), lu=True, prec="fp32")
+    assert info.cpu().tolist()[0] == 0
+    Mo, No, _, _ = oracle.gepp(y)
+    r1o = oracle.trmm(oracle.house_r(Mo), No)
+    r1o = np.sign(np.diag(r1o))[:, None] * r1o
+    r1 = to_host(R1)
+    assert np.all(np.isfinite(r1)) and np.all(np.diag(r1) > 0)
+    kap = np.linalg.cond(Mo) * np.linalg.cond(No[1:, 1:])
+    for i in range(n):
+        assert np.linalg.norm(r1[i] - r1o[i]) <= 64 * 2.0**-24 * n * kap * np.linalg.norm(r1o[i]), i
 
 
 @pytest.mark.parametrize("s,n,seed", [(64, 32, 0), (128, 64, 1), (256, 128, 4), (512, 200, 6)])
