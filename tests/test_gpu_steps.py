@@ -129,17 +129,30 @@ def test_precond_lu_subnormal_pivots(s, n):
     np.testing.assert_array_equal(to_host(M), Mo)
 
 
+def _huge_pivot_sketch(s, n):
+    """Three columns with one entry of 1.5 2^1022 (the pivot of that column's
+    step) and the rest of order 2^1016; the other columns standard normal.
+    No elimination step can overflow (|multipliers| <= 1 and the updated
+    entries stay below 2^1019)."""
+    rng = np.random.default_rng(s + 3 * n)
+    y = rng.standard_normal((s, n))
+    for k, j in enumerate((0, n // 3, 2 * n // 3)):
+        y[:, j] *= 2.0**1016
+        y[5 + 7 * k, j] = (1.5 if k % 2 == 0 else -1.5) * 2.0**1022
+    return np.asfortranarray(y)
+
+
 @pytest.mark.parametrize("s,n", [(64, 32), (128, 64), (256, 128)])
 def test_precond_lu_huge_pivots(s, n):
     # entries near the overflow threshold: pivots above 2^1022 have a subnormal
     # reciprocal, so those steps divide directly and M still equals the
     # oracle's bit for bit. R_1 = R_0 N may overflow here, which the kernel
     # reports after M is written.
-    y = np.asfortranarray(np.random.default_rng(s).standard_normal((s, n)) * 2.0**1021)
-    assert np.abs(y).max() > 2.0**1022 and np.all(np.isfinite(y))
+    y = _huge_pivot_sketch(s, n)
     _, perm, M, info = _lib().precond(to_dev(y), lu=True, want_m=True)
-    Mo, _, po, io = oracle.gepp(y)
+    Mo, No, po, io = oracle.gepp(y)
     assert io[0] == 0
+    assert np.sum(np.abs(np.diag(No)) > 2.0**1022) >= 3  # those steps took the direct division
     assert info.cpu().tolist()[0] in (0, oracle.NONFINITE)
     np.testing.assert_array_equal(perm.cpu().numpy(), po)
     np.testing.assert_array_equal(to_host(M), Mo)
