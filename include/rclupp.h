@@ -65,7 +65,9 @@ typedef enum {
   RCLUPP_ERR_UNSUPPORTED = 2, /* valid but not supported (e.g. n > RCLUPP_MAX_N)      */
   RCLUPP_ERR_ALLOC = 3,       /* device memory could not be obtained                 */
   RCLUPP_ERR_HIP = 4,         /* a HIP runtime call or kernel launch failed          */
-  RCLUPP_ERR_WORKSPACE = 5    /* the caller's workspace is smaller than required     */
+  RCLUPP_ERR_WORKSPACE = 5,   /* the caller's workspace is smaller than required     */
+  RCLUPP_ERR_SCRATCH_LIMIT = 6 /* rclupp_qr_noalloc: the sizes need more workspace than
+                                  its fixed RCLUPP_NOALLOC_MAX_BYTES scratch             */
 } rclupp_status;
 
 /* Asynchronous numerical outcome, written on the device. */
@@ -186,6 +188,32 @@ int rclupp_workspace_size(int alg, int64_t m, int64_t n, int64_t s, const rclupp
 int rclupp_qr_ex(int alg, const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, uint64_t seed, double* Q,
                  double* R, const rclupp_opts* opts, void* ws, size_t ws_bytes, rclupp_info* d_info,
                  hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Allocation-free form, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation as rclupp_qr_ex, with the workspace taken
+ * from a fixed scratch array of RCLUPP_NOALLOC_MAX_BYTES bytes that the
+ * library holds in device memory on every device it runs on, until the
+ * process ends. The call allocates nothing (no hipMalloc, hipFree or pinned
+ * host memory); the caller passes X, Q, R and, optionally, d_info (device
+ * pointer; NULL means the outcome is not reported).
+ *   - The workspace layout is rclupp_qr_ex's, except that when it would exceed
+ *     the scratch the number of per-workgroup partial sums of the sketch and
+ *     of the Gram passes is halved until it fits (results then differ from
+ *     rclupp_qr_ex's by the order of those sums only). Sizes that still do not
+ *     fit (e.g. RCLUPPr or LC2 with a tall LU whose pivot vector alone needs
+ *     4m bytes) return RCLUPP_ERR_SCRATCH_LIMIT and enqueue nothing.
+ *   - Every call on a device shares that device's scratch, which keeps the
+ *     last call's contents (each call clears what it needs). Calls whose work
+ *     overlaps on one device race, and give wrong results: enqueue them on one
+ *     stream, or order them with events.
+ *   - Other arguments, errors and the outcome are as for rclupp_qr_ex.
+ * ------------------------------------------------------------------------- */
+#define RCLUPP_NOALLOC_MAX_BYTES ((size_t)128 << 20)
+
+int rclupp_qr_noalloc(int alg, const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, uint64_t seed,
+                      double* Q, double* R, const rclupp_opts* opts, rclupp_info* d_info, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Batched form: many independent problems in one call. h_probs is a HOST

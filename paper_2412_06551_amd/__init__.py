@@ -15,6 +15,7 @@ from .api import (  # noqa: F401
     precond,
     qr,
     qr_batched,
+    qr_noalloc,
     Batch,
     qr_simple,
     sketch,
@@ -23,5 +24,5 @@ from .api import (  # noqa: F401
     workspace_size,
 )
 
-__all__ = ["qr", "qr_simple", "qr_batched", "Batch", "workspace_size", "sketch", "omega", "philox", "precond",
-           "trsm_gram", "chol", "tall_lu", "colmajor", "new_colmajor", "QRResult"]
+__all__ = ["qr", "qr_simple", "qr_noalloc", "qr_batched", "Batch", "workspace_size", "sketch", "omega", "philox",
+           "precond", "trsm_gram", "chol", "tall_lu", "colmajor", "new_colmajor", "QRResult"]

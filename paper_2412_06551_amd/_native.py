@@ -14,7 +14,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librclupp.so")
 
 # status codes (rclupp_status)
-OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_ALLOC, ERR_HIP, ERR_WORKSPACE = 0, 1, 2, 3, 4, 5
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_ALLOC, ERR_HIP, ERR_WORKSPACE, ERR_SCRATCH_LIMIT = 0, 1, 2, 3, 4, 5, 6
+# fixed scratch of the allocation-free form (RCLUPP_NOALLOC_MAX_BYTES)
+NOALLOC_MAX_BYTES = 128 << 20
 # info codes and stages (rclupp_info_code, rclupp_stage)
 INFO_OK, INFO_LU_ZERO_PIVOT, INFO_CHOL_BREAKDOWN, INFO_NONFINITE, INFO_SINGULAR, INFO_SYNC_TIMEOUT = 0, 1, 2, 3, 4, 5
 STAGE_NONE, STAGE_LU, STAGE_QR, STAGE_PRECOND, STAGE_CHOL_A, STAGE_CHOL_B = 0, 1, 2, 3, 4, 5
@@ -29,7 +31,7 @@ EXPORTS = [
     "rclupp_last_info", "rclupp_status_string", "rclupp_workspace_size", "rclupp_qr_ex",
     "rclupp_batched_workspace_size", "rclupp_qr_batched", "rclupp_omega", "rclupp_philox",
     "rclupp_sketch", "rclupp_precond", "rclupp_trsm_gram", "rclupp_chol", "rclupp_tall_lu",
-    "rclupp_trace_enable", "rclupp_trace_read", "rclupp_release",
+    "rclupp_trace_enable", "rclupp_trace_read", "rclupp_release", "rclupp_qr_noalloc",
 ]
 
 
@@ -77,6 +79,7 @@ def load(path: str = LIB_PATH):
         "rclupp_last_info": [P, ctypes.POINTER(Info)],
         "rclupp_workspace_size": [ctypes.c_int, I64, I64, I64, ctypes.POINTER(Opts), ctypes.POINTER(SZ)],
         "rclupp_qr_ex": [ctypes.c_int, P, I64, I64, I64, I64, U64, P, P, ctypes.POINTER(Opts), P, SZ, P, P],
+        "rclupp_qr_noalloc": [ctypes.c_int, P, I64, I64, I64, I64, U64, P, P, ctypes.POINTER(Opts), P, P],
         "rclupp_batched_workspace_size": [ctypes.c_int, ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(Opts),
                                           ctypes.POINTER(SZ)],
         "rclupp_qr_batched": [ctypes.c_int, ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(Opts), P, SZ, P, P],

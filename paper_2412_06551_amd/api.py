@@ -120,6 +120,27 @@ def qr(X: torch.Tensor, alg: str = "rclupp", s: Optional[int] = None, seed: int 
     return QRResult(Q, R, info)
 
 
+def qr_noalloc(X: torch.Tensor, Q: torch.Tensor, R: torch.Tensor, alg: str = "rclupp", s: Optional[int] = None,
+               seed: int = 0, sketch_prec: str = "fp64", lu_prec: str = "fp64", info: Optional[torch.Tensor] = None,
+               stream=None) -> QRResult:
+    """X = Q R through rclupp_qr_noalloc: the library takes its workspace from its
+    fixed device scratch and allocates nothing; the caller provides Q (X's
+    leading dimension), R (n x n) and optionally info (int32[4] on the device)."""
+    _require_device()
+    m, n = X.shape
+    ld = _ld(X)
+    s = _default_s(alg, n, m, s)
+    if _ld(Q) != ld or tuple(Q.shape) != (m, n):
+        raise ValueError("Q must be m x n with the leading dimension of X")
+    if tuple(R.shape) != (n, n) or _ld(R) != n:
+        raise ValueError("R must be a column-major n x n matrix")
+    o = _opts(sketch_prec, lu_prec)
+    st = nat.load().rclupp_qr_noalloc(nat.ALG[alg], _ptr(X), m, n, ld, s, ctypes.c_uint64(seed), _ptr(Q), _ptr(R),
+                                      ctypes.byref(o), _ptr(info), _stream(stream))
+    nat.check(st, "rclupp_qr_noalloc(%s)" % alg)
+    return QRResult(Q, R, info)
+
+
 _SIMPLE = {"rclupp": "rclupp_qr", "rcluppr": "rcluppr_qr", "cholqr2": "cholqr2_qr", "scholqr3": "scholqr3_qr",
            "lc2": "lc2_qr", "rcholqr": "rcholqr_qr"}
 

@@ -29,6 +29,14 @@
 
 using namespace rclupp;
 
+// Workspace of the allocation-free entry point rclupp_qr_noalloc. Every device
+// the library runs on holds its own copy (loaded with the library's code
+// object, kept until the process ends). In host code this name is only a
+// stand-in for the symbol: the device address of the current device's copy
+// comes from hipGetSymbolAddress (noalloc_scratch below) and is the only form
+// passed to kernels.
+static __device__ __align__(256) unsigned char noalloc_ws[RCLUPP_NOALLOC_MAX_BYTES];
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -65,10 +73,15 @@ int validate(int alg, int64_t m, int64_t n, int64_t ld, int64_t s, const rclupp_
   return RCLUPP_OK;
 }
 
-Layout make_layout(int alg, int64_t m, int64_t n, int64_t s, const rclupp_opts* o) {
+// Grid hints: 0 = the planners' defaults (or the RCLUPP_TALL_GRID /
+// RCLUPP_SKETCH_GRID environment overrides); a positive value fixes the number
+// of workgroups of the tall passes or of the sketch, which sets the number of
+// per-workgroup partial sums kept in the workspace.
+Layout make_layout(int alg, int64_t m, int64_t n, int64_t s, const rclupp_opts* o, int tall_grid = 0,
+                   int sketch_grid = 0) {
   Layout L;
   const int sk_prec = o ? o->sketch_prec : 0;
-  L.tp = plan_tall(m, n, env_int("RCLUPP_TALL_GRID", 0));
+  L.tp = plan_tall(m, n, tall_grid > 0 ? tall_grid : env_int("RCLUPP_TALL_GRID", 0));
   const int np = L.tp.np;
   const size_t rbytes = align_up(padded_r_doubles(np) * sizeof(double));
   size_t off = 0;
@@ -79,7 +92,7 @@ Layout make_layout(int alg, int64_t m, int64_t n, int64_t s, const rclupp_opts* 
   };
   L.info = take(sizeof(rclupp_info));
   if (sketched(alg)) {
-    L.sk = plan_sketch(m, n, s, sk_prec, env_int("RCLUPP_SKETCH_GRID", 0));
+    L.sk = plan_sketch(m, n, s, sk_prec, sketch_grid > 0 ? sketch_grid : env_int("RCLUPP_SKETCH_GRID", 0));
     L.ypart = take(L.sk.part_bytes);
     L.y = take((size_t)s * n * sizeof(double));
   }
@@ -268,6 +281,26 @@ int run_method(int alg, const Layout& L, char* ws, const double* X, int64_t m, i
   }
 }
 
+// ---- allocation-free form: the device address of noalloc_ws per device ------------
+std::mutex g_noalloc_mu;
+std::map<int, char*> g_noalloc_addr;
+
+// Looked up once per device, with that device current (the caller's).
+int noalloc_scratch(char** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return RCLUPP_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  auto it = g_noalloc_addr.find(dev);
+  if (it == g_noalloc_addr.end()) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_ws)) != hipSuccess || p == nullptr) return RCLUPP_ERR_HIP;
+    if (((uintptr_t)p) % kAlign) return RCLUPP_ERR_HIP;
+    it = g_noalloc_addr.emplace(dev, (char*)p).first;
+  }
+  *out = it->second;
+  return RCLUPP_OK;
+}
+
 // ---- per-stream outcome of the 9-argument forms ---------------------------------
 std::mutex g_mu;
 std::map<hipStream_t, rclupp_info*> g_last;
@@ -304,6 +337,47 @@ int simple_entry(int alg, const double* X, int64_t m, int64_t n, int64_t ld, int
   return rc;
 }
 
+// Clears the outcome record and enqueues method `alg` in the workspace `w`
+// (laid out by L) on `st`.
+int run_in_workspace(int alg, const Layout& L, char* w, const double* X, int64_t m, int64_t n, int64_t ld, int64_t s,
+                     uint64_t seed, double* Q, double* R, const rclupp_opts* opts, rclupp_info* d_info,
+                     hipStream_t st) {
+  rclupp_info* info = d_info ? d_info : (rclupp_info*)(w + L.info);
+  hipLaunchKernelGGL(k_zero_info, dim3(1), dim3(64), 0, st, info);
+  if (hipGetLastError() != hipSuccess) return RCLUPP_ERR_HIP;
+  const int rc = run_method(alg, L, w, X, m, n, ld, s, seed, Q, R, opts, (int32_t*)info, st);
+  trace_mark(nullptr, st);
+  return rc;
+}
+
+// The layout of rclupp_qr_ex for these sizes, with the number of per-workgroup
+// partial sums (the grid of the sketch, then of the Gram passes, whichever
+// holds more bytes) halved until the whole workspace fits in `cap` bytes. The
+// passes without a Gram keep their own grid (they keep no partials). False if
+// nothing fits (e.g. the m-long pivot vector of the tall LU).
+bool fit_layout(int alg, int64_t m, int64_t n, int64_t s, const rclupp_opts* o, size_t cap, Layout* out) {
+  Layout L = make_layout(alg, m, n, s, o);
+  const int solve_grid = L.tp.gx_solve;
+  int tall_grid = L.tp.gx;
+  int sketch_grid = sketched(alg) ? L.sk.gx * L.sk.gy * L.sk.gz : 0;
+  while (L.total > cap) {
+    const size_t sb = sketched(alg) ? L.sk.part_bytes : 0;
+    if (sketched(alg) && sb >= L.tp.part_bytes && L.sk.gx > 1) {
+      sketch_grid = (L.sk.gx / 2) * L.sk.gy * L.sk.gz;
+    } else if (L.tp.gx > 1) {
+      tall_grid = L.tp.gx / 2;
+    } else if (sketched(alg) && L.sk.gx > 1) {
+      sketch_grid = (L.sk.gx / 2) * L.sk.gy * L.sk.gz;
+    } else {
+      return false;
+    }
+    L = make_layout(alg, m, n, s, o, tall_grid, sketch_grid);
+  }
+  L.tp.gx_solve = solve_grid;
+  *out = L;
+  return true;
+}
+
 template <typename F>
 int with_scratch(size_t bytes, hipStream_t st, F&& f) {
   void* p = nullptr;
@@ -326,6 +400,7 @@ const char* rclupp_status_string(int status) {
     case RCLUPP_ERR_ALLOC: return "device allocation failed";
     case RCLUPP_ERR_HIP: return "HIP runtime or launch error";
     case RCLUPP_ERR_WORKSPACE: return "workspace too small";
+    case RCLUPP_ERR_SCRATCH_LIMIT: return "sizes need more than the fixed scratch of rclupp_qr_noalloc";
     default: return "unknown status";
   }
 }
@@ -347,13 +422,19 @@ int rclupp_qr_ex(int alg, const double* X, int64_t m, int64_t n, int64_t ld, int
   if (((uintptr_t)ws) % kAlign) return RCLUPP_ERR_INVALID_ARG;
   const Layout L = make_layout(alg, m, n, s, opts);
   if (ws_bytes < L.total) return RCLUPP_ERR_WORKSPACE;
-  char* w = (char*)ws;
-  rclupp_info* info = d_info ? d_info : (rclupp_info*)(w + L.info);
-  hipLaunchKernelGGL(k_zero_info, dim3(1), dim3(64), 0, stream, info);
-  if (hipGetLastError() != hipSuccess) return RCLUPP_ERR_HIP;
-  const int rc2 = run_method(alg, L, w, X, m, n, ld, s, seed, Q, R, opts, (int32_t*)info, stream);
-  trace_mark(nullptr, stream);
-  return rc2;
+  return run_in_workspace(alg, L, (char*)ws, X, m, n, ld, s, seed, Q, R, opts, d_info, stream);
+}
+
+int rclupp_qr_noalloc(int alg, const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, uint64_t seed,
+                      double* Q, double* R, const rclupp_opts* opts, rclupp_info* d_info, hipStream_t stream) {
+  int rc = validate(alg, m, n, ld, s, opts);
+  if (rc) return rc;
+  if (!X || !Q || !R) return RCLUPP_ERR_INVALID_ARG;
+  Layout L;
+  if (!fit_layout(alg, m, n, s, opts, RCLUPP_NOALLOC_MAX_BYTES, &L)) return RCLUPP_ERR_SCRATCH_LIMIT;
+  char* w = nullptr;
+  if ((rc = noalloc_scratch(&w))) return rc;
+  return run_in_workspace(alg, L, w, X, m, n, ld, s, seed, Q, R, opts, d_info, stream);
 }
 
 int rclupp_trace_enable(int max_marks) {

@@ -1,0 +1,104 @@
+"""The allocation-free entry point rclupp_qr_noalloc, called through the C ABI,
+against rclupp_qr_ex on the same inputs. Several calls run back to back on one
+stream, each smaller than the one before, so every call finds the fixed scratch
+holding the previous call's contents. Each result must meet the parity bar
+against rclupp_qr_ex's (orthogonality <= 1e-12, relative residual <= 1e-13,
+R within 1e-14 kappa_2 of rclupp_qr_ex's R); where rclupp_qr_ex's workspace
+fits the scratch the layouts are the same and Q and R must be equal bit for
+bit."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2412_06551_amd as lib
+from paper_2412_06551_amd import _native as nat
+from gen import make_svd, make_svd_device
+from gpu_common import TOL_ORTH, TOL_R, TOL_RES, gpu, require_gpu, to_dev, to_host
+
+pytestmark = gpu
+
+
+@pytest.fixture(autouse=True)
+def _dev():
+    require_gpu()
+
+
+def _outputs(X):
+    m, n = X.shape
+    Q = lib.new_colmajor(m, n, device=X.device, ld=X.stride(1))
+    R = torch.empty((n, n), dtype=torch.float64, device=X.device).t()
+    info = torch.full((4,), -7, dtype=torch.int32, device=X.device)  # must be cleared by the call
+    return Q, R, info
+
+
+def _check(x_host, X, kappa, got, ref, same_layout):
+    Qn, Rn, infon = got
+    assert [int(v) for v in infon.cpu().tolist()] == [0, 0, 0, 0]
+    assert ref.info_host() == [0, 0, 0, 0]
+    q, r = to_host(Qn), to_host(Rn)
+    if x_host is None:
+        x_host = to_host(X)
+    met = oracle.metrics(x_host, q, r)
+    assert met["orth"] <= TOL_ORTH, met
+    assert met["rel_res"] <= TOL_RES, met
+    assert np.all(np.tril(r, -1) == 0) and np.all(np.diag(r) > 0)
+    r_ref = to_host(ref.R)
+    rerr = np.linalg.norm(r - r_ref) / np.linalg.norm(r_ref)
+    assert rerr <= TOL_R * kappa, (rerr, kappa)
+    if same_layout:
+        assert torch.equal(Rn, ref.R) and torch.equal(Qn, ref.Q)
+
+
+def test_noalloc_matches_qr_ex_on_successive_calls():
+    torch.cuda.set_device(0)
+    cases = [
+        # (alg, m, n, s, kappa, sketch_prec, lu_prec): decreasing sizes
+        ("rclupp", 262144 + 37, 256, 1024, 1e8, "fp64", "fp64"),  # workspace above the scratch: fitted grids
+        ("rclupp", 50003, 64, 128, 1e12, "fp32", "fp32"),
+        ("rcluppr", 4099, 20, 40, 1e10, "fp64", "fp64"),
+    ]
+    st = torch.cuda.current_stream()
+    inputs, got = [], []
+    for k, (alg, m, n, s, kappa, sp, lp) in enumerate(cases):
+        if m * n > 10 ** 7:
+            X = make_svd_device(m, n, kappa, seed=11 + k, orthonormal=False)
+            x_host = None
+        else:
+            x_host = make_svd(m, n, kappa, seed=11 + k)
+            X = to_dev(x_host)
+        inputs.append((X, x_host))
+    torch.cuda.synchronize()
+    print("noalloc: enqueueing %d calls back to back" % len(cases), flush=True)
+    for (alg, m, n, s, kappa, sp, lp), (X, _) in zip(cases, inputs):
+        Q, R, info = _outputs(X)
+        lib.qr_noalloc(X, Q, R, alg=alg, s=s, seed=3, sketch_prec=sp, lu_prec=lp, info=info, stream=st)
+        got.append((Q, R, info))
+    torch.cuda.synchronize()
+    for (alg, m, n, s, kappa, sp, lp), (X, x_host), g in zip(cases, inputs, got):
+        print("noalloc: checking %s m=%d n=%d s=%d %s/%s" % (alg, m, n, s, sp, lp), flush=True)
+        ref = lib.qr(X, alg=alg, s=s, seed=3, sketch_prec=sp, lu_prec=lp)
+        torch.cuda.synchronize()
+        same = lib.workspace_size(alg, m, n, s, sp, lp) <= nat.NOALLOC_MAX_BYTES
+        if (alg, m) == ("rclupp", 262144 + 37):
+            assert not same  # the first case exercises the fitted layout
+        _check(x_host, X, kappa, g, ref, same)
+
+
+def test_noalloc_repeated_and_without_info():
+    # the same call twice (second one without an outcome record) gives the
+    # same bits: the scratch's leftover contents do not leak into a result
+    torch.cuda.set_device(0)
+    m, n, s, kappa = 20011, 32, 64, 1e6
+    x = make_svd(m, n, kappa, seed=21)
+    X = to_dev(x)
+    Q1, R1, info1 = _outputs(X)
+    Q2, R2, _ = _outputs(X)
+    lib.qr_noalloc(X, Q1, R1, alg="rclupp", s=s, seed=9, info=info1)
+    lib.qr_noalloc(X, Q2, R2, alg="rclupp", s=s, seed=9, info=None)
+    torch.cuda.synchronize()
+    assert [int(v) for v in info1.cpu().tolist()] == [0, 0, 0, 0]
+    assert torch.equal(Q1, Q2) and torch.equal(R1, R2)
+    ref = lib.qr(X, alg="rclupp", s=s, seed=9)
+    torch.cuda.synchronize()
+    _check(x, X, kappa, (Q1, R1, info1), ref, True)
