@@ -89,16 +89,21 @@ typedef enum {
   RCLUPP_STAGE_QR = 2,      /* R factor of the (sketched) L factor, or chol(M^T M) in LC2 */
   RCLUPP_STAGE_PRECOND = 3, /* R_1 = R_0 N, or the first (shifted) Cholesky               */
   RCLUPP_STAGE_CHOL_A = 4,  /* Cholesky of the first Gram after preconditioning (R_2)     */
-  RCLUPP_STAGE_CHOL_B = 5   /* Cholesky of the second Gram (R_4)                          */
+  RCLUPP_STAGE_CHOL_B = 5,  /* Cholesky of the second Gram (R_4)                          */
+  RCLUPP_STAGE_CHOL_X = 6   /* Cholesky of the extra pass of an escalated mixed-precision call */
 } rclupp_stage;
 
-/* index = 1-based column at which the stage failed. */
+/* index = 1-based column at which the stage failed. reserved: bit 0
+ * (RCLUPP_NOTE_ESCALATED) is set when a mixed-precision RCLUPP or RCLUPPr call
+ * found its preconditioner too weak for CholeskyQR2 and ran Shifted
+ * CholeskyQR3's tail instead (see rclupp_opts). */
 typedef struct {
   int32_t code;
   int32_t stage;
   int32_t index;
   int32_t reserved;
 } rclupp_info;
+#define RCLUPP_NOTE_ESCALATED 1
 
 typedef enum { RCLUPP_PREC_FP64 = 0, RCLUPP_PREC_FP32 = 1, RCLUPP_PREC_BF16 = 2 } rclupp_prec;
 
@@ -107,7 +112,13 @@ typedef enum { RCLUPP_PREC_FP64 = 0, RCLUPP_PREC_FP32 = 1, RCLUPP_PREC_BF16 = 2 
  *                BF16 MFMA with FP32 accumulation (the cross-workgroup sum is FP64);
  *   lu_prec:     arithmetic of the LU + Householder preconditioner on the s x n
  *                sketch: FP64 or FP32 (the result R_1 is widened to FP64).
- * Everything else (triangular solves, Gram, Cholesky, the final pass) is FP64. */
+ * Everything else (triangular solves, Gram, Cholesky, the final pass) is FP64.
+ * With either option below FP64, RCLUPP and RCLUPPr check on the device that
+ * Q_1 = X R_1^{-1} is within CholeskyQR2's range: when the Cholesky of
+ * G_1 = Q_1^T Q_1 breaks down, or its diagonal spans more than a factor 1e7,
+ * the call takes Algorithm 4's shifted Cholesky of G_1 and one more
+ * CholeskyQR pass (Shifted CholeskyQR3 on Q_1; one extra pass over Q) and
+ * sets RCLUPP_NOTE_ESCALATED in the outcome. */
 typedef struct {
   int32_t sketch_prec;
   int32_t lu_prec;

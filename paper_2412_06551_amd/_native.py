@@ -19,7 +19,9 @@ OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_ALLOC, ERR_HIP, ERR_WORKSPACE, ERR_SCR
 NOALLOC_MAX_BYTES = 128 << 20
 # info codes and stages (rclupp_info_code, rclupp_stage)
 INFO_OK, INFO_LU_ZERO_PIVOT, INFO_CHOL_BREAKDOWN, INFO_NONFINITE, INFO_SINGULAR, INFO_SYNC_TIMEOUT = 0, 1, 2, 3, 4, 5
-STAGE_NONE, STAGE_LU, STAGE_QR, STAGE_PRECOND, STAGE_CHOL_A, STAGE_CHOL_B = 0, 1, 2, 3, 4, 5
+STAGE_NONE, STAGE_LU, STAGE_QR, STAGE_PRECOND, STAGE_CHOL_A, STAGE_CHOL_B, STAGE_CHOL_X = 0, 1, 2, 3, 4, 5, 6
+# outcome notes (rclupp_info.reserved bits)
+NOTE_ESCALATED = 1
 # precisions and algorithms (rclupp_prec, rclupp_alg)
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 ALG = {"rclupp": 0, "rcluppr": 1, "cholqr2": 2, "scholqr3": 3, "lc2": 4, "rcholqr": 5}

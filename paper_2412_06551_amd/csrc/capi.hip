@@ -52,8 +52,8 @@ bool sketched(int alg) { return alg == RCLUPP_ALG_RCLUPP || alg == RCLUPP_ALG_RC
 bool uses_tall_lu(int alg) { return alg == RCLUPP_ALG_RCLUPPR || alg == RCLUPP_ALG_LC2; }
 
 struct Layout {
-  size_t info = 0, ypart = 0, y = 0, r1 = 0, r2 = 0, r3 = 0, r4 = 0, gpart = 0, g = 0, small = 0, perm = 0,
-         nmat = 0, lu = 0, total = 0;
+  size_t info = 0, gates = 0, ypart = 0, y = 0, r1 = 0, r2 = 0, r3 = 0, r4 = 0, gpart = 0, g = 0, small = 0,
+         perm = 0, nmat = 0, lu = 0, total = 0;
   SketchPlan sk{};
   TallPlan tp{};
 };
@@ -91,6 +91,7 @@ Layout make_layout(int alg, int64_t m, int64_t n, int64_t s, const rclupp_opts* 
     return at;
   };
   L.info = take(sizeof(rclupp_info));
+  L.gates = take(3 * sizeof(rclupp_info));
   if (sketched(alg)) {
     L.sk = plan_sketch(m, n, s, sk_prec, sketch_grid > 0 ? sketch_grid : env_int("RCLUPP_SKETCH_GRID", 0));
     L.ypart = take(L.sk.part_bytes);
@@ -200,6 +201,127 @@ int tail_cholqr1(const Layout& L, char* ws, const double* X, int64_t m, int64_t 
   return RCLUPP_OK;
 }
 
+// ---- escalation of the mixed-precision forms ------------------------------------
+// An FP32 or BF16 sketch rounds X (or M) before the product, so R_1 is the R
+// factor of a perturbed matrix and kappa(Q_1) grows like kappa(X) times the
+// rounding unit of the sketch (about 2^-9 kappa(X) for BF16). Past CholeskyQR2's
+// range (Lemma 3.1) the first Cholesky breaks down, or its factor spans many
+// orders of magnitude. Then the tail takes Algorithm 4's shifted Cholesky of
+// G_1 instead (which always succeeds for kappa(Q_1) up to about u^{-1}) and one
+// more CholeskyQR pass, i.e. Shifted CholeskyQR3 applied to Q_1. The decision
+// is taken on the device: the stages it controls are launched every time and
+// return at once when their gate record is closed, so the launch sequence is
+// fixed (graph-capturable). info->reserved bit 0 records that it happened.
+constexpr int32_t kGateClosed = -1;      // a gate record that makes its stages return at once
+// max/min diag(R_2) (a lower bound of kappa(Q_1)) beyond which the tail
+// escalates: about a tenth of u^{-1/2}, where the Gram's condition number
+// kappa(Q_1)^2 reaches u^{-1} and the Cholesky can no longer be trusted
+constexpr double kEscalateRatio = 1e7;
+
+__global__ void k_gate_copy(const rclupp_info* info, rclupp_info* g) {
+  if (threadIdx.x == 0) *g = *info;
+}
+
+// After the unshifted Cholesky of G_1 (outcome gA, factor in the padded
+// triangle r2): open gate gS for the shifted Cholesky when gA reports a
+// breakdown or diag(R_2) spans more than `ratio`; any other failure of gA
+// becomes the call's outcome. One wave.
+__global__ void k_escalate_decide(rclupp_info* info, const rclupp_info* gA, rclupp_info* gS, const double* r2, int np,
+                                  int n, double ratio) {
+  const int t = threadIdx.x;
+  double mx = 0.0, mn = __builtin_inf();
+  for (int j = t; j < n; j += 64) {
+    const double d = r2[(size_t)j * np + j];
+    mx = fmax(mx, d);
+    mn = fmin(mn, d);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, o));
+    mn = fmin(mn, __shfl_xor(mn, o));
+  }
+  if (t != 0) return;
+  *gS = rclupp_info{kGateClosed, 0, 0, 0};
+  if (info->code != 0) return;
+  const bool broke = gA->code == RCLUPP_INFO_CHOL_BREAKDOWN;
+  const bool weak = gA->code == 0 && !(mx <= ratio * mn);
+  if (broke || weak) {
+    *gS = rclupp_info{0, 0, 0, 0};
+    info->reserved |= 1;
+  } else if (gA->code != 0) {
+    *info = *gA;
+  }
+}
+
+// Gate g is open when nothing has failed and the call escalated.
+__global__ void k_gate_open(const rclupp_info* info, rclupp_info* g) {
+  if (threadIdx.x == 0) {
+    const bool run = info->code == 0 && (info->reserved & 1);
+    *g = run ? rclupp_info{0, 0, 0, 0} : rclupp_info{kGateClosed, 0, 0, 0};
+  }
+}
+
+// A failure recorded by the stages behind gate g becomes the call's outcome.
+__global__ void k_gate_close(const rclupp_info* g, rclupp_info* info) {
+  if (threadIdx.x == 0 && g->code > 0 && info->code == 0) *info = *g;
+}
+
+// dst = src (count doubles) when gate g is open.
+__global__ void k_copy_gated(const double* src, double* dst, int count, const rclupp_info* g) {
+  if (g->code != 0) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+// The CholeskyQR2 tail with the escalation above (mixed-precision forms).
+int tail_cholqr2_escalating(const Layout& L, char* ws, const double* X, int64_t m, int64_t n, int64_t ld, double* Q,
+                            double* R, int32_t* info32, hipStream_t st) {
+  rclupp_info* info = (rclupp_info*)info32;
+  rclupp_info* gA = (rclupp_info*)(ws + L.gates);
+  rclupp_info* gS = gA + 1;
+  rclupp_info* gX = gA + 2;
+  double* r1 = (double*)(ws + L.r1);
+  double* r2 = (double*)(ws + L.r2);
+  double* r3 = (double*)(ws + L.r3);
+  double* r4 = (double*)(ws + L.r4);
+  double* gpart = (double*)(ws + L.gpart);
+  double* g = (double*)(ws + L.g);
+  double* small = (double*)(ws + L.small);
+  const int np = L.tp.np;
+  STAGE("trsm_gram");
+  HIPCHK(launch_tall_pass(L.tp, X, ld, m, n, r1, Q, ld, gpart, info32, st));
+  STAGE("gram_reduce");
+  HIPCHK(launch_gram_reduce(L.tp, gpart, n, g, info32, st));
+  STAGE("chol");
+  hipLaunchKernelGGL(k_gate_copy, dim3(1), dim3(64), 0, st, info, gA);
+  HIPCHK(hipGetLastError());
+  HIPCHK(launch_chol(g, np, n, m, 0, r2, r3, 0, r1, nullptr, 0, small, (int32_t*)gA, RCLUPP_STAGE_CHOL_A, st));
+  hipLaunchKernelGGL(k_escalate_decide, dim3(1), dim3(64), 0, st, info, gA, gS, r2, np, (int)n, kEscalateRatio);
+  HIPCHK(hipGetLastError());
+  HIPCHK(launch_chol(g, np, n, m, 1, r2, r3, 0, r1, nullptr, 0, small, (int32_t*)gS, RCLUPP_STAGE_CHOL_A, st));
+  hipLaunchKernelGGL(k_gate_close, dim3(1), dim3(64), 0, st, gS, info);
+  HIPCHK(hipGetLastError());
+  STAGE("trsm_gram");
+  HIPCHK(launch_tall_pass(L.tp, Q, ld, m, n, r2, Q, ld, gpart, info32, st));
+  STAGE("gram_reduce");
+  HIPCHK(launch_gram_reduce(L.tp, gpart, n, g, info32, st));
+  // the extra CholeskyQR pass (gate gX): R_x = chol(G_2), R_3 <- R_x R_3, Q <- Q R_x^{-1}, G
+  STAGE("escalation");
+  hipLaunchKernelGGL(k_gate_open, dim3(1), dim3(64), 0, st, info, gX);
+  HIPCHK(hipGetLastError());
+  HIPCHK(launch_chol(g, np, n, m, 0, r2, r4, 0, r3, nullptr, 0, small, (int32_t*)gX, RCLUPP_STAGE_CHOL_X, st));
+  HIPCHK(launch_tall_pass(L.tp, Q, ld, m, n, r2, Q, ld, gpart, (int32_t*)gX, st));
+  HIPCHK(launch_gram_reduce(L.tp, gpart, n, g, (int32_t*)gX, st));
+  const int pad_count = (int)padded_r_doubles(np);
+  hipLaunchKernelGGL(k_copy_gated, dim3((pad_count + 255) / 256), dim3(256), 0, st, r4, r3, pad_count, gX);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_gate_close, dim3(1), dim3(64), 0, st, gX, info);
+  HIPCHK(hipGetLastError());
+  STAGE("chol");
+  HIPCHK(launch_chol(g, np, n, m, 0, r4, R, 1, r3, nullptr, 0, small, info32, RCLUPP_STAGE_CHOL_B, st));
+  STAGE("trsm_final");
+  HIPCHK(launch_tall_pass(L.tp, Q, ld, m, n, r4, Q, ld, nullptr, info32, st));
+  return RCLUPP_OK;
+}
+
 int sketch_into(const Layout& L, char* ws, const double* A, int64_t m, int64_t n, int64_t lda, int64_t s,
                 uint64_t seed, int prec, int32_t* info, hipStream_t st) {
   double* ypart = (double*)(ws + L.ypart);
@@ -220,6 +342,8 @@ int run_method(int alg, const Layout& L, char* ws, const double* X, int64_t m, i
   double* gpart = (double*)(ws + L.gpart);
   double* g = (double*)(ws + L.g);
   double* small = (double*)(ws + L.small);
+  // reduced-precision preconditioners take the escalating tail
+  auto tail2 = (sk_prec != RCLUPP_PREC_FP64 || lu_prec != RCLUPP_PREC_FP64) ? tail_cholqr2_escalating : tail_cholqr2;
   int rc;
   switch (alg) {
     case RCLUPP_ALG_RCLUPP:
@@ -227,7 +351,7 @@ int run_method(int alg, const Layout& L, char* ws, const double* X, int64_t m, i
       STAGE("precond");
       HIPCHK(launch_precond((double*)(ws + L.y), s, n, 1, lu_prec, nullptr, 0, r1, nullptr, nullptr, nullptr, small,
                             info, RCLUPP_STAGE_QR, st));
-      return tail_cholqr2(L, ws, X, m, n, ld, Q, R, info, st);
+      return tail2(L, ws, X, m, n, ld, Q, R, info, st);
     case RCLUPP_ALG_RCHOLQR:
       if ((rc = sketch_into(L, ws, X, m, n, ld, s, seed, sk_prec, info, st))) return rc;
       STAGE("precond");
@@ -244,7 +368,7 @@ int run_method(int alg, const Layout& L, char* ws, const double* X, int64_t m, i
       STAGE("precond");
       HIPCHK(launch_precond((double*)(ws + L.y), s, n, 0, lu_prec, nmat, n, r1, nullptr, nullptr, nullptr, small, info,
                             RCLUPP_STAGE_QR, st));
-      return tail_cholqr2(L, ws, X, m, n, ld, Q, R, info, st);
+      return tail2(L, ws, X, m, n, ld, Q, R, info, st);
     }
     case RCLUPP_ALG_CHOLQR2:
       STAGE("gram");

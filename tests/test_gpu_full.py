@@ -6,15 +6,16 @@ size (the CPU oracle would need minutes per run at these sizes; the
   * orthogonality ||Q^T Q - I||_F <= 1e-12 and relative residual
     ||Q R - X||_F / ||X||_F <= 1e-13 (Section 4's targets, as for every
     method test), computed on the device in FP64;
-  * the mixed-precision forms give the FP64 form's R to 1e-13 relative
-    (both are the unique R with a positive diagonal of the same X) where the
-    rounded sketch still leaves Q_1 in CholeskyQR2's range.
+  * the mixed-precision forms give the FP64 form's R to the parity bar
+    1e-14 kappa_2 relative (both are the unique R with a positive diagonal of
+    the same X); BF16 at kappa = 1e14 takes the escalated tail (shifted
+    Cholesky and one more CholeskyQR pass).
 Inputs are generated on the device with the recipes of gen.matrices."""
 import pytest
 import torch
 
 from gen import make_krylov_device, make_svd_device
-from gpu_common import TOL_ORTH, TOL_RES, gpu, require_gpu
+from gpu_common import TOL_ORTH, TOL_R, TOL_RES, gpu, require_gpu
 
 pytestmark = gpu
 
@@ -62,13 +63,13 @@ def test_full_size_mixed_workload(kappa):
     X = make_svd_device(m, n, kappa, seed=0, orthonormal=False)
     ref = _lib().qr(X, alg="rclupp", s=s, seed=0)
     _props(X, ref)
-    forms = [("fp32", "fp32")] + ([("bf16", "fp32")] if kappa <= 1e8 else [])
-    for sk, lu in forms:
+    for sk, lu in (("fp32", "fp32"), ("bf16", "fp32")):
         res = _lib().qr(X, alg="rclupp", s=s, seed=0, sketch_prec=sk, lu_prec=lu)
         _props(X, res)
-        if kappa <= 1e8:
-            d = float(torch.linalg.matrix_norm(res.R - ref.R) / torch.linalg.matrix_norm(ref.R))
-            assert d <= 1e-13, (sk, lu, d)
+        d = float(torch.linalg.matrix_norm(res.R - ref.R) / torch.linalg.matrix_norm(ref.R))
+        assert d <= TOL_R * kappa, (sk, lu, d)
+        if sk == "bf16" and kappa >= 1e14:
+            assert res.info_host()[3] == 1  # escalated: kappa(Q_1) near 1e11
         del res
     del ref, X
 

@@ -307,14 +307,28 @@ def test_batched_sequential_fallback_matches_single():
 # Cholesky factors and the last CholeskyQR pass stay FP64, so the final Q and R
 # must meet the same bar against the FP64 oracle wherever the rounded
 # preconditioner still brings Q_1 into CholeskyQR2's range.
+# Beyond that range (a BF16 sketch of X leaves kappa(Q_1) near 2^-9 kappa(X))
+# the call escalates to the shifted Cholesky and one more CholeskyQR pass, and
+# the same bar applies.
 @pytest.mark.parametrize("sk,lu,kappa", [("fp32", "fp32", 1e2), ("fp32", "fp32", 1e8), ("fp32", "fp32", 1e14),
-                                         ("fp32", "fp64", 1e14), ("bf16", "fp32", 1e2), ("bf16", "fp32", 1e6),
-                                         ("bf16", "fp64", 1e6)])
+                                         ("fp32", "fp64", 1e14), ("fp32", "fp32", 1e15), ("bf16", "fp32", 1e2),
+                                         ("bf16", "fp32", 1e6), ("bf16", "fp64", 1e6), ("bf16", "fp32", 1e10),
+                                         ("bf16", "fp32", 1e12), ("bf16", "fp32", 1e14), ("bf16", "fp32", 1e15)])
 def test_mixed_rclupp(sk, lu, kappa):
     m, n, s = 40000 + 11, 64, 256
     x = make_svd(m, n, kappa, seed=21)
     res = _lib().qr(to_dev(x), alg="rclupp", s=s, seed=4, sketch_prec=sk, lu_prec=lu)
     method_parity(x, "rclupp", s, 4, kappa, res)
+    notes = res.info_host()[3]
+    if kappa <= 1e6 or sk == "fp32" and kappa <= 1e8:
+        assert notes == 0  # well inside CholeskyQR2's range: no extra pass
+    if sk == "bf16" and kappa >= 1e12:
+        assert notes == _nat().NOTE_ESCALATED  # kappa(Q_1) near 1e9 or more
+
+
+def _nat():
+    from paper_2412_06551_amd import _native
+    return _native
 
 
 @pytest.mark.parametrize("kappa", [1e4, 1e10, 1e15])
@@ -327,13 +341,31 @@ def test_mixed_rcluppr_bf16(kappa):
 
 
 @pytest.mark.parametrize("sk", ["fp32", "bf16"])
-@pytest.mark.parametrize("kappa", [1e2, 1e8])
+@pytest.mark.parametrize("kappa", [1e2, 1e8, 1e14])
 def test_mixed_wide(sk, kappa):
     # the n = 256, s = 4n shape of the mixed-precision workload at reduced m
     m, n, s = 20000 + 3, 256, 1024
     x = make_svd(m, n, kappa, seed=23)
     res = _lib().qr(to_dev(x), alg="rclupp", s=s, seed=0, sketch_prec=sk, lu_prec="fp32")
     method_parity(x, "rclupp", s, 0, kappa, res)
+
+
+_ORACLE_R = {}
+
+
+@pytest.mark.parametrize("kappa", [1e2, 1e8, 1e14])
+@pytest.mark.parametrize("sk,lu", [("fp64", "fp64"), ("fp32", "fp32"), ("bf16", "fp32")])
+def test_mixed_workload_shape_vs_oracle(kappa, sk, lu):
+    # the mixed-precision workload's n = 256 and s = 4n = 1024 with a quarter of
+    # a million rows (m + 5 for a ragged last tile): every form against the
+    # FP64 oracle (one oracle run per kappa)
+    m, n, s = 262144 + 5, 256, 1024
+    x = make_svd(m, n, kappa, seed=24)
+    if kappa not in _ORACLE_R:
+        _ORACLE_R[kappa] = oracle.run("rclupp", x, s=s, seed=7)
+    res = _lib().qr(to_dev(x), alg="rclupp", s=s, seed=7, sketch_prec=sk, lu_prec=lu)
+    method_parity(x, "rclupp", s, 7, kappa, res, orc=_ORACLE_R[kappa])
+    print("mixed %s/%s kappa=%.0e notes=%d" % (sk, lu, kappa, res.info_host()[3]))
 
 
 # ------------------------------------------------------------------ full size
