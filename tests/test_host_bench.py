@@ -49,13 +49,39 @@ def test_stage_rates_both_ceilings(bench):
     assert set(r) == {"sketch", "trsm_final"}
     sk = r["sketch"]
     assert abs(sk["GB_s"] - 8 * m * n / 0.4e-3 / 1e9) < 0.1
-    assert abs(sk["fp64_TFLOP_s"] - 2 * s * m * n / 0.4e-3 / 1e12) < 0.01
-    assert abs(sk["frac_fp64"] - sk["fp64_TFLOP_s"] / bench.FP64_PEAK_TFLOPS) < 1e-3
+    assert abs(sk["TFLOP_s"] - 2 * s * m * n / 0.4e-3 / 1e12) < 0.01
+    assert abs(sk["frac_matrix"] - sk["TFLOP_s"] / bench.FP64_PEAK_TFLOPS) < 1e-3
+    # a BF16 sketch is priced against the BF16 matrix peak
+    r2 = bench.stage_rates({"sketch": (0.4, 1)}, m, n, s, sketch_prec="bf16")
+    assert r2["sketch"]["prec"] == "bf16"
+    assert abs(r2["sketch"]["frac_matrix"] - r2["sketch"]["TFLOP_s"] / 2500.0) < 1e-4
+
+
+def test_sketch_bound_follows_its_precision(bench):
+    # s = 1024: arithmetic intensity s/4 = 256 flop/B, past the FP64 (9.8) and
+    # FP32 (19.7) ridges, below the BF16 ridge (312.5)
+    m, n, s = 4194304, 256, 1024
+    st = {"sketch": (10.0, 1)}
+    e64 = bench.rate_entry("sketch", 10.0, 1, m, n, s, "fp64")
+    e32 = bench.rate_entry("sketch", 10.0, 1, m, n, s, "fp32")
+    e16 = bench.rate_entry("sketch", 10.0, 1, m, n, s, "bf16")
+    assert (e64["bound"], e64["peak"]) == ("mfma", 78.6)
+    assert (e32["bound"], e32["peak"]) == ("mfma", 157.3)
+    assert (e16["bound"], e16["unit"]) == ("hbm", "GB/s")
+    assert abs(e16["achieved"] - 8 * m * n / 10e-3 / 1e9) < 0.1
+    assert bench.roofline_entry(st, m, n, s)["kernel"] == "sketch"
+
+
+def test_attainable_time_matches_the_closed_form(bench):
+    # max(bytes / 8 TB/s, flops / 78.6 TFLOP/s) per tall pass
+    assert abs(bench.attainable_ms(1 << 20, 64, 128) - 0.62) < 0.01
+    assert abs(bench.attainable_ms(4194304, 256, 1024) - 45.5) < 0.1
 
 
 def test_traffic_lookup_is_keyed_to_the_source(bench):
     # a kernel with no source mapping, or an entry not in the file: no traffic figure
     assert bench.measured_traffic("precond") is None
+    assert bench.measured_traffic("sketch", workload="no such workload") is None
     assert bench.kernel_source_hash("precond") is None
     h = bench.kernel_source_hash("trsm_gram")
     assert isinstance(h, str) and len(h) == 16
