@@ -27,9 +27,9 @@
  *     then keep lines cached between neighbouring row segments);
  *   - X is read only; X and Q must not overlap; Q and R are written only;
  *   - the sketch is S = G / sqrt(s) with G_ij a standard normal drawn from
- *     Philox4x32-10 (counter = (j lo, j hi, floor(i/4), 0), key = (seed lo,
- *     seed hi), Box-Muller on the four 23-bit uniforms), a pure function of
- *     (seed, i, j); see rclupp_omega;
+ *     Philox4x32-10 (counter = (q lo, q hi, i, 0) with q = floor(j/4), key =
+ *     (seed lo, seed hi), Box-Muller on the four 23-bit uniforms giving tall
+ *     rows 4q .. 4q+3), a pure function of (seed, i, j); see rclupp_omega;
  *   - all work is enqueued on `stream` (a hipStream_t; NULL = default
  *     stream); calls return before the work finishes and never synchronize
  *     the device, except rclupp_last_info, rclupp_release and the first
@@ -115,7 +115,7 @@ typedef enum { RCLUPP_PREC_FP64 = 0, RCLUPP_PREC_FP32 = 1, RCLUPP_PREC_BF16 = 2 
  * Everything else (triangular solves, Gram, Cholesky, the final pass) is FP64.
  * With either option below FP64, RCLUPP and RCLUPPr check on the device that
  * Q_1 = X R_1^{-1} is within CholeskyQR2's range: when the Cholesky of
- * G_1 = Q_1^T Q_1 breaks down, or its diagonal spans more than a factor 1e7,
+ * G_1 = Q_1^T Q_1 breaks down, or its diagonal spans more than a factor 1e9,
  * the call takes Algorithm 4's shifted Cholesky of G_1 and one more
  * CholeskyQR pass (Shifted CholeskyQR3 on Q_1; one extra pass over Q) and
  * sets RCLUPP_NOTE_ESCALATED in the outcome. */

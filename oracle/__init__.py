@@ -148,10 +148,10 @@ def philox4x32_10(ctr, key) -> np.ndarray:
     return out
 
 
-def normals4(seed: int, j: int, q: int) -> np.ndarray:
-    """The four float32 normals for tall row j and sketch rows 4q..4q+3."""
+def normals4(seed: int, q: int, i: int) -> np.ndarray:
+    """The four float32 normals of sketch row i for tall rows 4q..4q+3."""
     z = np.zeros(4, dtype=np.float32)
-    _load().orc_normals4(ctypes.c_uint64(seed), ctypes.c_uint64(j), ctypes.c_uint32(q), _ptr(z))
+    _load().orc_normals4(ctypes.c_uint64(seed), ctypes.c_uint64(q), ctypes.c_uint32(i), _ptr(z))
     return z
 
 

@@ -17,10 +17,11 @@
  * Readings where the paper is silent (they are listed with reasons in the
  * design notes of the repository):
  *   - the sketch S = G / sqrt(s) (Section 3, Gaussian sketch) uses
- *     G_ij = z(seed, j, i) from Philox4x32-10 (Salmon et al., SC'11) with
- *     counter (j lo, j hi, floor(i/4), 0) and key (seed lo, seed hi); the four
- *     output words give u_t = (floor(w_t / 2^9) + 1/2) * 2^-23 and the
- *     Box-Muller pairs (u0,u1), (u2,u3); each normal is rounded to float32;
+ *     G_ij = z(seed, i, j) from Philox4x32-10 (Salmon et al., SC'11) with
+ *     counter (q lo, q hi, i, 0), q = floor(j/4), and key (seed lo, seed hi);
+ *     the four output words give u_t = (floor(w_t / 2^9) + 1/2) * 2^-23 and
+ *     the Box-Muller pairs (u0,u1) -> tall rows 4q, 4q+1 and (u2,u3) -> 4q+2,
+ *     4q+3; each normal is rounded to float32;
  *   - sums over the tall dimension (sketch, Gram, norms) are taken
  *     sequentially inside blocks of ORC_BLOCK rows, and the block partial sums
  *     are added in block order;
@@ -118,10 +119,10 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
   out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
 }
 
-/* Four standard normals for tall row j and sketch rows 4q..4q+3 (Box-Muller).
+/* Four standard normals of sketch row i for tall rows 4q..4q+3 (Box-Muller).
  * The transform is evaluated in double and each normal rounded to float. */
-void orc_normals4(uint64_t seed, uint64_t j, uint32_t q, float z[4]) {
-  uint32_t ctr[4] = {(uint32_t)j, (uint32_t)(j >> 32), q, 0u};
+void orc_normals4(uint64_t seed, uint64_t q, uint32_t i, float z[4]) {
+  uint32_t ctr[4] = {(uint32_t)q, (uint32_t)(q >> 32), i, 0u};
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
   uint32_t w[4];
   orc_philox4x32_10(ctr, key, w);
@@ -136,20 +137,26 @@ void orc_normals4(uint64_t seed, uint64_t j, uint32_t q, float z[4]) {
   z[3] = (float)(r1 * sin(two_pi * u[3]));
 }
 
-/* Column j of Omega = G / sqrt(s): out[i] = z(seed, j, i) / sqrt(s), i < s. */
-static void omega_column(uint64_t seed, uint64_t j, int64_t s, double* out) {
+/* Columns 4q .. 4q+3 of Omega = G / sqrt(s): out[t*s + i] = z(seed, i, 4q+t) / sqrt(s). */
+static void omega_group(uint64_t seed, uint64_t q, int64_t s, double* out) {
   double scale = 1.0 / sqrt((double)s);
-  for (int64_t q = 0; 4 * q < s; ++q) {
+  for (int64_t i = 0; i < s; ++i) {
     float z[4];
-    orc_normals4(seed, j, (uint32_t)q, z);
-    for (int t = 0; t < 4 && 4 * q + t < s; ++t) out[4 * q + t] = (double)z[t] * scale;
+    orc_normals4(seed, q, (uint32_t)i, z);
+    for (int t = 0; t < 4; ++t) out[t * s + i] = (double)z[t] * scale;
   }
 }
 
 /* Omega[:, j0 .. j0+cols) materialised (s x cols, ld s). */
 void orc_omega(uint64_t seed, int64_t s, int64_t j0, int64_t cols, double* Om) {
 #pragma omp parallel for schedule(static)
-  for (int64_t c = 0; c < cols; ++c) omega_column(seed, (uint64_t)(j0 + c), s, Om + c * s);
+  for (int64_t c = 0; c < cols; ++c) {
+    double* om4 = (double*)malloc(sizeof(double) * 4 * (size_t)s);
+    const uint64_t j = (uint64_t)(j0 + c);
+    omega_group(seed, j / 4, s, om4);
+    memcpy(Om + c * s, om4 + (j % 4) * s, sizeof(double) * (size_t)s);
+    free(om4);
+  }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -167,19 +174,20 @@ void orc_sketch(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s, u
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t bb = 0; bb < nb; ++bb) {
       double* P = part + (size_t)bb * psz;
-      double* om = (double*)malloc(sizeof(double) * (size_t)s);
+      double* om4 = (double*)malloc(sizeof(double) * 4 * (size_t)s);
       for (size_t e = 0; e < psz; ++e) P[e] = 0.0;
-      int64_t r0 = (b0 + bb) * ORC_BLOCK;
+      int64_t r0 = (b0 + bb) * ORC_BLOCK; /* a multiple of 4 */
       int64_t r1 = r0 + ORC_BLOCK < m ? r0 + ORC_BLOCK : m;
       for (int64_t j = r0; j < r1; ++j) {
-        omega_column(seed, (uint64_t)j, s, om);
+        if (j % 4 == 0) omega_group(seed, (uint64_t)j / 4, s, om4);
+        const double* om = om4 + (j % 4) * s;
         for (int64_t k = 0; k < n; ++k) {
           double xjk = X[j + k * ldx];
           double* Pk = P + k * s;
           for (int64_t i = 0; i < s; ++i) Pk[i] += om[i] * xjk;
         }
       }
-      free(om);
+      free(om4);
     }
     for (int64_t bb = 0; bb < nb; ++bb) {
       const double* P = part + (size_t)bb * psz;

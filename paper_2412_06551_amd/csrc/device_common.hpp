@@ -31,11 +31,14 @@ __device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
 // Gaussian sketch entries. Section 3 takes S = G / sqrt(s) with G i.i.d.
 // standard normal; here G_ij = z(seed, i, j) is a pure function of its indices:
 //   Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) with
-//   counter = (j mod 2^32, j div 2^32, floor(i / 4), 0), key = (seed lo, seed hi);
+//   counter = (floor(j/4) mod 2^32, floor(j/4) div 2^32, i, 0), key = (seed lo, seed hi);
 //   each 32-bit word w gives u = (floor(w / 2^9) + 1/2) 2^-23, an odd multiple
 //   of 2^-24 in (0, 1) that float32 holds exactly;
-//   Box-Muller: (u0, u1) -> rows 4q, 4q+1 and (u2, u3) -> rows 4q+2, 4q+3:
+//   Box-Muller: (u0, u1) -> tall rows 4q, 4q+1 and (u2, u3) -> 4q+2, 4q+3 of
+//   sketch row i (q = floor(j/4)):
 //     z = sqrt(-2 ln u_a) * (cos 2 pi u_b, sin 2 pi u_b), in float32.
+// One call thus gives one sketch row's entries for four consecutive tall rows,
+// which is the run of the K index that one lane holds in the MFMA operands.
 // ---------------------------------------------------------------------------
 struct philox_out {
   uint32_t w0, w1, w2, w3;
@@ -63,9 +66,9 @@ __device__ __forceinline__ float word_to_uniform(uint32_t w) {
   return (float)(w >> 9) * 0x1p-23f + 0x1p-24f;  // exact: (2k+1) 2^-24
 }
 
-// The four normals of (tall row j, group q): sketch rows 4q .. 4q+3.
-__device__ __forceinline__ f32x4 normals4(uint64_t seed, uint64_t j, uint32_t q) {
-  const philox_out w = philox4x32_10((uint32_t)j, (uint32_t)(j >> 32), q, 0u, (uint32_t)seed, (uint32_t)(seed >> 32));
+// The four normals of (sketch row i, tall-row group q): G[i][4q .. 4q+3].
+__device__ __forceinline__ f32x4 normals4(uint64_t seed, uint64_t q, uint32_t i) {
+  const philox_out w = philox4x32_10((uint32_t)q, (uint32_t)(q >> 32), i, 0u, (uint32_t)seed, (uint32_t)(seed >> 32));
   const float u0 = word_to_uniform(w.w0), u1 = word_to_uniform(w.w1);
   const float u2 = word_to_uniform(w.w2), u3 = word_to_uniform(w.w3);
   // Box-Muller on the hardware transcendentals: log2, square root, and sine

@@ -68,16 +68,16 @@ hipError_t launch_partial_sum(const double* part, int nparts, int64_t stride, in
 
 // ---- sketch (k_sketch.hip) --------------------------------------------------
 struct SketchPlan {
-  int sm;          // sketch rows per workgroup (64, 128 or 256)
-  int nn;          // columns per workgroup (16, 32, 64 or 128)
-  int gx;          // row-chunk workgroups
-  int gy, gz;      // sketch-row groups, column groups
-  bool wm;         // each wave owns its own sm sketch rows (a workgroup covers nw sm)
-  int nw;          // waves per workgroup (4; 2 for the FP64 form with wave-owned rows)
-  int64_t s_pad;   // padded sketch rows (gy * sm, times nw when wm)
-  int64_t n_pad;   // padded columns (gz * nn)
-  int64_t ntiles;  // 64-row tiles of the tall operand
-  size_t part_bytes;  // bytes of the per-workgroup partial sums
+  int sm;          // sketch rows per wave (16: one M-block)
+  int nn;          // columns (all of them, padded: 16 .. 256)
+  int gx;          // row chunks (workgroups per sketch-row group)
+  int gy, gz;      // sketch-row groups, column groups (gz = 1)
+  bool wm;         // each wave owns its own sketch rows (always)
+  int nw;          // waves per workgroup (8, or 4 when s_pad is not a multiple of 128)
+  int64_t s_pad;   // padded sketch rows (gy * nw * sm)
+  int64_t n_pad;   // padded columns (nn)
+  int64_t ntiles;  // 32-row tiles of the tall operand
+  size_t part_bytes;  // bytes of the per-chunk partial sums and their level-1 sums
 };
 SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int gx_hint);
 // Ypart[gx][s_pad x n_pad] partial sums of G[:, rows] X[rows, :] (G unscaled).

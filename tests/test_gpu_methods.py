@@ -322,8 +322,8 @@ def test_mixed_rclupp(sk, lu, kappa):
     notes = res.info_host()[3]
     if kappa <= 1e6 or sk == "fp32" and kappa <= 1e8:
         assert notes == 0  # well inside CholeskyQR2's range: no extra pass
-    if sk == "bf16" and kappa >= 1e12:
-        assert notes == _nat().NOTE_ESCALATED  # kappa(Q_1) near 1e9 or more
+    if sk == "bf16" and kappa >= 1e14:
+        assert notes == _nat().NOTE_ESCALATED  # kappa(Q_1) near 1e11: the first Cholesky breaks down
 
 
 def _nat():

@@ -53,7 +53,8 @@ def test_omega_normals_match(s, cols, j0, seed):
 
 # ---------------------------------------------------------------- sketch
 @pytest.mark.parametrize("m,n,s,seed", [(2048, 32, 64, 0), (5000 + 37, 64, 128, 3), (700, 16, 40, 1),
-                                        (3000, 100, 200, 2), (1025, 5, 5, 4), (3001, 16, 1000, 6)])
+                                        (3000, 100, 200, 2), (1025, 5, 5, 4), (3001, 16, 1000, 6),
+                                        (40000 + 3, 256, 1024, 8), (50000 + 1, 48, 96, 9)])
 def test_sketch_matches_oracle(m, n, s, seed):
     x = make_svd(m, n, 1e6, seed=seed)
     y = to_host(_lib().sketch(to_dev(x), s, seed))
@@ -66,7 +67,7 @@ def test_sketch_matches_oracle(m, n, s, seed):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("m,n,s,seed", [(2048, 32, 64, 0), (5000 + 37, 64, 128, 3), (3000, 100, 200, 2),
-                                        (4099, 256, 512, 5), (700, 16, 40, 1)])
+                                        (4099, 256, 512, 5), (700, 16, 40, 1), (40000 + 3, 256, 1024, 8)])
 def test_sketch_low_precision(prec, m, n, s, seed):
     x = make_svd(m, n, 1e6, seed=seed)
     y = to_host(_lib().sketch(to_dev(x), s, seed, prec=prec))
@@ -79,6 +80,20 @@ def test_sketch_low_precision(prec, m, n, s, seed):
     # the typical error is at the rounding level: a misplaced row or column would be O(1)
     rel = np.abs(y - want) / ab
     assert np.median(rel) <= 4 * uin + 4 * np.sqrt(m) * 2.0**-24
+
+
+@pytest.mark.parametrize("grid", ["43", "200"])
+def test_sketch_grid_hint(grid, monkeypatch):
+    # row chunks not a multiple of 8 (plain workgroup order) and a smaller grid:
+    # the same sketch up to summation order
+    m, n, s, seed = 30000 + 9, 64, 256, 12
+    x = make_svd(m, n, 1e4, seed=seed)
+    want = oracle.sketch(x, s, seed)
+    monkeypatch.setenv("RCLUPP_SKETCH_GRID", grid)
+    y = to_host(_lib().sketch(to_dev(x), s, seed))
+    om = oracle.omega(s, m, seed)
+    bound = (8 * 2.0**-24 + 4 * m * oracle.U) * (np.abs(om) @ np.abs(x))
+    assert np.all(np.abs(y - want) <= bound)
 
 
 def test_sketch_leading_dimension():

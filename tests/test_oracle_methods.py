@@ -229,23 +229,34 @@ def test_arrowhead_family_rcluppr(beta):
 @pytest.mark.parametrize("beta", [1e-25, 1e-30])
 def test_arrowhead_beyond_sufficient_condition(beta):
     # kappa(N) ~ 1/beta far beyond eq. (s4). The outcome depends on how the
-    # multiply-adds of the LU elimination and the substitution round:
+    # multiply-adds of the LU elimination and the substitution round, and for
+    # some readings on the sketch; pinned here for sketch seeds 0, 1, 2:
     #  - fused (the oracle's reading): X R_1^{-1} loses its conditioning and
-    #    the Cholesky of the first Gram breaks down at the last column, so
-    #    Section 5.1.3's stated outcome (RCLUPPr accurate down to 1e-30) is not
-    #    reproduced; RCLUPP, by contrast, succeeds;
+    #    RCLUPPr's first Cholesky breaks down at the last column for every
+    #    seed, so Section 5.1.3's stated outcome (RCLUPPr accurate down to
+    #    1e-30) is not reproduced; RCLUPP succeeds for seeds 1 and 2;
     #  - product and sum rounded separately: RCLUPPr is exact to rounding (the
-    #    stated outcome) and RCLUPP is the one that breaks down.
+    #    stated outcome) for seeds 1 and 2 and breaks down for seed 0; RCLUPP
+    #    succeeds for seed 2 only.
     x = make_arrowhead(beta)
-    r = oracle.rcluppr(x, 100, seed=0)
-    assert r.info.tolist()[:3] == [oracle.CHOL_BREAKDOWN, oracle.ST_CHOL_A, 50]
-    r = oracle.rclupp(x, 100, seed=0)
-    assert r.ok and oracle.orthogonality(r.Q) < 1e-14
-    r = oracle.run("rcluppr", x, s=100, seed=0, variant="separate_muladd")
-    m = check_qr(x, r)
-    assert m["orth"] < 1e-28
-    r = oracle.run("rclupp", x, s=100, seed=0, variant="separate_muladd")
-    assert r.info.tolist()[:3] == [oracle.CHOL_BREAKDOWN, oracle.ST_CHOL_A, 50]
+    breakdown = [oracle.CHOL_BREAKDOWN, oracle.ST_CHOL_A, 50]
+    for seed in (0, 1, 2):
+        assert oracle.rcluppr(x, 100, seed=seed).info.tolist()[:3] == breakdown
+        r = oracle.rclupp(x, 100, seed=seed)
+        if seed == 0:
+            assert r.info.tolist()[:3] == breakdown
+        else:
+            assert r.ok and oracle.orthogonality(r.Q) < 1e-15
+        r = oracle.run("rcluppr", x, s=100, seed=seed, variant="separate_muladd")
+        if seed == 0:
+            assert r.info.tolist()[:3] == breakdown
+        else:
+            assert check_qr(x, r)["orth"] < 1e-28
+        r = oracle.run("rclupp", x, s=100, seed=seed, variant="separate_muladd")
+        if seed == 2:
+            assert r.ok and oracle.orthogonality(r.Q) < 1e-15
+        else:
+            assert r.info.tolist()[:3] == breakdown
 
 
 def test_separate_muladd_variant_agrees_inside_the_conditions():

@@ -44,12 +44,24 @@ def _words_to_normals(w):
                      r1 * math.cos(2 * math.pi * u[3]), r1 * math.sin(2 * math.pi * u[3])], dtype=np.float32)
 
 
-@pytest.mark.parametrize("seed,j,q", [(0, 0, 0), (0, 5, 3), (12345678901234, (1 << 33) + 7, 17), (2**64 - 1, 2**40, 255)])
-def test_counter_and_key_layout(seed, j, q):
-    # the counter is (j lo, j hi, q, 0) and the key (seed lo, seed hi)
-    w = oracle.philox4x32_10([j & 0xFFFFFFFF, j >> 32, q, 0], [seed & 0xFFFFFFFF, seed >> 32])
-    z = oracle.normals4(seed, j, q)
+@pytest.mark.parametrize("seed,q,i", [(0, 0, 0), (0, 5, 3), (12345678901234, (1 << 33) + 7, 17), (2**64 - 1, 2**40, 4095)])
+def test_counter_and_key_layout(seed, q, i):
+    # the counter is (q lo, q hi, i, 0) for sketch row i and tall rows 4q..4q+3,
+    # and the key (seed lo, seed hi)
+    w = oracle.philox4x32_10([q & 0xFFFFFFFF, q >> 32, i, 0], [seed & 0xFFFFFFFF, seed >> 32])
+    z = oracle.normals4(seed, q, i)
     np.testing.assert_allclose(z, _words_to_normals(w), rtol=2e-7, atol=1e-7)
+
+
+def test_omega_entries_follow_the_counter_layout():
+    # Omega[i, j] * sqrt(s) is output j mod 4 of the call for (q = j // 4, i)
+    s, cols, j0, seed = 6, 11, 5, 21
+    om = oracle.omega(s, cols, seed=seed, j0=j0)
+    for c in range(cols):
+        j = j0 + c
+        for i in range(s):
+            z = oracle.normals4(seed, j // 4, i)
+            assert om[i, c] * math.sqrt(s) == pytest.approx(float(z[j % 4]), rel=1e-15)
 
 
 def test_uniforms_exact_and_open_interval():
@@ -72,6 +84,10 @@ def test_normals_distribution():
         assert abs(z[t].var() - 1.0) < 0.03
     c = np.corrcoef(z)
     assert np.max(np.abs(c - np.eye(4))) < 0.02
+    # the four tall rows of one call (the Box-Muller outputs) are uncorrelated too
+    w = z.reshape(4, cols // 4, 4).transpose(2, 0, 1).reshape(4, -1)
+    cw = np.corrcoef(w)
+    assert np.max(np.abs(cw - np.eye(4))) < 0.02
 
 
 def test_omega_scaling_and_rows():
@@ -79,7 +95,7 @@ def test_omega_scaling_and_rows():
     om = oracle.omega(s, cols, seed=3)
     # E ||Omega[:, j]||^2 = 1 (Omega = G / sqrt(s))
     assert abs(np.mean(np.sum(om * om, axis=0)) - 1.0) < 0.02
-    # rows are uncorrelated (sketch rows 4q+t for different q come from different counters)
+    # rows are uncorrelated (every sketch row has its own counters)
     c = np.corrcoef(om)
     off = c - np.eye(s)
     assert np.max(np.abs(off)) < 0.08
