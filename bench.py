@@ -19,9 +19,10 @@ Reported (one JSON line):
   stage_rates = each tall stage against both ceilings (HBM and the matrix peak
                 of its precision);
   mixed       = the same shape at kappa in {1e2, 1e8, 1e14}: plain FP64 against
-                the FP32 (sketch and LU) and BF16 (sketch; FP32 LU) forms, each
-                with its time, accuracy, sketch roofline and whether the call
-                escalated to the extra shifted-Cholesky pass;
+                the FP32 (sketch and LU) and BF16 (sketch; FP32 LU) forms and the
+                CountSketch (FP64 sums; FP32 LU), each with its time, accuracy,
+                sketch roofline and whether the call escalated to the extra
+                shifted-Cholesky pass;
   c2          = m = 1,048,576, n = 64, s = 2n, kappa = 1e15 (FP64 RCLUPP, with
                 its roofline, the other five methods and the oracle comparison);
   batched     = 512 problems (m in [1e4, 5e5], n in {16, 32, 64, 128}, kappa
@@ -198,21 +199,21 @@ def gpu_accuracy(X, Q, R):
 class Runner:
     """Q, R, outcome record and workspace for repeated calls on one input."""
 
-    def __init__(self, lib, X, alg, s, seed, sketch_prec="fp64", lu_prec="fp64"):
+    def __init__(self, lib, X, alg, s, seed, sketch_prec="fp64", lu_prec="fp64", sketch="gaussian"):
         import torch
         m, n = X.shape
         self.lib, self.X, self.alg, self.s, self.seed = lib, X, alg, s, seed
-        self.sp, self.lp = sketch_prec, lu_prec
+        self.sp, self.lp, self.kind = sketch_prec, lu_prec, sketch
         self.stream = torch.cuda.current_stream()
         self.Q = torch.empty((n, m), dtype=torch.float64, device=X.device).t()
         self.R = torch.empty((n, n), dtype=torch.float64, device=X.device).t()
         self.info = torch.zeros(4, dtype=torch.int32, device=X.device)
-        self.ws = torch.empty(max(lib.workspace_size(alg, m, n, s, sketch_prec, lu_prec), 256), dtype=torch.uint8,
-                              device=X.device)
+        self.ws = torch.empty(max(lib.workspace_size(alg, m, n, s, sketch_prec, lu_prec, sketch), 256),
+                              dtype=torch.uint8, device=X.device)
 
     def __call__(self):
         self.lib.qr(self.X, alg=self.alg, s=self.s, seed=self.seed, sketch_prec=self.sp, lu_prec=self.lp, Q=self.Q,
-                    R=self.R, workspace=self.ws, info=self.info, stream=self.stream)
+                    R=self.R, workspace=self.ws, info=self.info, stream=self.stream, sketch=self.kind)
 
     def time(self, reps, warmup=1):
         import torch
@@ -261,17 +262,26 @@ def bench_mixed(lib, reps=3, x_headline=None):
             X = make_svd_device(m, n, kappa, seed=SEED)
         row = {}
         r64 = None
-        for tag, sk, lu in (("fp64", "fp64", "fp64"), ("fp32", "fp32", "fp32"), ("bf16", "bf16", "fp32")):
-            run = Runner(lib, X, "rclupp", s, SEED, sk, lu)
+        for tag, sk, lu, kind in (("fp64", "fp64", "fp64", "gaussian"), ("fp32", "fp32", "fp32", "gaussian"),
+                                  ("bf16", "bf16", "fp32", "gaussian"), ("count", "fp64", "fp32", "count")):
+            run = Runner(lib, X, "rclupp", s, SEED, sk, lu, kind)
             ms = run.time(reps)
             stages = run.trace(1)
             info = run.info_host()
             orth, res = gpu_accuracy(X, run.Q, run.R)
-            ent = {"sketch_prec": sk, "lu_prec": lu, "ms": round(ms, 3), "GB_s": round(by / (ms / 1e3) / 1e9, 1),
+            ent = {"sketch": kind, "sketch_prec": sk, "lu_prec": lu, "ms": round(ms, 3),
+                   "GB_s": round(by / (ms / 1e3) / 1e9, 1),
                    "fp64_tflops": round(fl / (ms / 1e3) / 1e12, 3), "info": info,
                    "escalated": bool(info[3] & 1), "orth": orth, "rel_res": res}
-            if "sketch" in stages:
+            if "sketch" in stages and kind == "gaussian":
                 ent["sketch_roofline"] = rate_entry("sketch", *stages["sketch"], m, n, s, sk)
+            elif "sketch" in stages:
+                # CountSketch: one read of X (8mn bytes) against HBM
+                t = stages["sketch"][0] / stages["sketch"][1] / 1e3
+                gbs = 8 * m * n / t / 1e9
+                ent["sketch_roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                                          "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                          "avg_launch_ms": round(t * 1e3, 5)}
             if tag == "fp64":
                 r64 = run.R.clone()
             else:

@@ -123,8 +123,22 @@ typedef struct {
   int32_t sketch_prec;
   int32_t lu_prec;
   int32_t batch_flags; /* rclupp_qr_batched only: RCLUPP_BATCH_* bits       */
-  int32_t reserved[5];
+  int32_t sketch_kind; /* RCLUPP_SKETCH_GAUSSIAN (0) or RCLUPP_SKETCH_COUNT  */
+  int32_t reserved[4];
 } rclupp_opts;
+
+/* sketch_kind (RCLUPP, RCLUPPr, randomized CholeskyQR):
+ *   RCLUPP_SKETCH_GAUSSIAN: S = G / sqrt(s), G i.i.d. standard normal
+ *     (Section 3's Gaussian sketch; the default);
+ *   RCLUPP_SKETCH_COUNT: the CountSketch (Section 3 lists it among the common
+ *     choices): column j of S holds one entry sigma_j = +-1 in row h_j, drawn
+ *     from Philox4x32-10 with counter (q lo, q hi, 0, 1), q = floor(j/4), key
+ *     (seed lo, seed hi); word j mod 4 gives h_j = floor(w s / 2^32) and
+ *     sigma_j = -1 for odd w, +1 for even. Y = S X is summed in FP64 (X read
+ *     once, no generation cost); requires sketch_prec = FP64 and s <= 1792
+ *     (else RCLUPP_ERR_UNSUPPORTED). Batches with it run problem by problem. */
+#define RCLUPP_SKETCH_GAUSSIAN 0
+#define RCLUPP_SKETCH_COUNT 1
 
 /* batch_flags:
  *   RCLUPP_BATCH_GRAPH: capture the batch's launch sequence into a hipGraph
@@ -282,6 +296,11 @@ int rclupp_philox(const uint32_t* ctr, int64_t count, uint32_t k0, uint32_t k1, 
  * per-workgroup partial sums in FP64 in a fixed order. */
 int rclupp_sketch(const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, uint64_t seed, int prec, double* Y,
                   hipStream_t stream);
+
+/* Y = S X (s x n, ld s) for the CountSketch S of RCLUPP_SKETCH_COUNT (FP64
+ * sums, s <= 1792). */
+int rclupp_countsketch(const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, uint64_t seed, double* Y,
+                       hipStream_t stream);
 
 /* Preconditioner of the sketch (Algorithm 2 steps 2-4, Algorithm 6 step 2):
  * from Y (s x n, ld s) compute R1 (n x n, ld n) = D R_0 N with

@@ -100,6 +100,11 @@ def _load(variant: str = ""):
         "orc_scholqr3_shift": ([I64, I64, D], D),
         "orc_lc2": ([P, I64, I64, I64, P, I64, P, P, P, P], ctypes.c_int),
         "orc_rcholqr": ([P, I64, I64, I64, I64, U64, P, I64, P, P, P, P], ctypes.c_int),
+        "orc_rclupp_f": ([P, I64, I64, I64, I64, U64, P, I64, P, P, P, P, P, ctypes.c_int], ctypes.c_int),
+        "orc_rcluppr_f": ([P, I64, I64, I64, I64, U64, P, I64, P, P, P, P, P, ctypes.c_int], ctypes.c_int),
+        "orc_rcholqr_f": ([P, I64, I64, I64, I64, U64, P, I64, P, P, P, P, ctypes.c_int], ctypes.c_int),
+        "orc_countsketch_hash": ([U64, U64, I64, P, P], None),
+        "orc_countsketch": ([P, I64, I64, I64, I64, U64, P], None),
         "chk_orthogonality": ([P, I64, I64, I64], D),
         "chk_residual": ([P, I64, P, I64, P, I64, I64, P, P], None),
     }
@@ -160,6 +165,23 @@ def omega(s: int, cols: int, seed: int, j0: int = 0) -> np.ndarray:
     om = np.zeros((s, cols), order="F")
     _load().orc_omega(ctypes.c_uint64(seed), s, j0, cols, _ptr(om))
     return om
+
+
+def countsketch_hash(seed: int, j: int, s: int):
+    """(h_j, sigma_j): the row and sign of column j of the CountSketch."""
+    h = np.zeros(1, dtype=np.int64)
+    sg = np.zeros(1)
+    _load().orc_countsketch_hash(ctypes.c_uint64(seed), ctypes.c_uint64(j), s, _ptr(h), _ptr(sg))
+    return int(h[0]), float(sg[0])
+
+
+def countsketch(x, s: int, seed: int) -> np.ndarray:
+    """Y = S X for the CountSketch S (s x m, one +-1 per column)."""
+    x = _f64(x)
+    m, n = x.shape
+    y = np.zeros((s, n), order="F")
+    _load().orc_countsketch(_ptr(x), m, n, _ld(x), s, ctypes.c_uint64(seed), _ptr(y))
+    return y
 
 
 def sketch(x, s: int, seed: int) -> np.ndarray:
@@ -260,7 +282,11 @@ class Result:
         return int(self.info[0]) == OK
 
 
-def _run(name: str, x, s=None, seed=None, variant: str = "") -> Result:
+# method flags: the sketch (Gaussian by default)
+SKETCH_FLAGS = {"gaussian": 0, "count": 1}
+
+
+def _run(name: str, x, s=None, seed=None, variant: str = "", sketch: str = "gaussian") -> Result:
     x = _f64(x)
     m, n = x.shape
     Q = np.zeros((m, n), order="F")
@@ -271,15 +297,18 @@ def _run(name: str, x, s=None, seed=None, variant: str = "") -> Result:
     info = np.zeros(4, dtype=np.int32)
     lib = _load(variant)
     f = getattr(lib, "orc_" + name)
+    flags = SKETCH_FLAGS[sketch]
     if name in ("rclupp", "rcluppr"):
         if not (n <= s <= m):
             raise ValueError("need n <= s <= m")
+        f = getattr(lib, "orc_" + name + "_f")
         f(_ptr(x), m, n, _ld(x), s, ctypes.c_uint64(seed), _ptr(Q), m, _ptr(R), _ptr(info), _ptr(R1), _ptr(R2),
-          _ptr(R4))
+          _ptr(R4), flags)
     elif name == "rcholqr":
         if not (n <= s <= m):
             raise ValueError("need n <= s <= m")
-        f(_ptr(x), m, n, _ld(x), s, ctypes.c_uint64(seed), _ptr(Q), m, _ptr(R), _ptr(info), _ptr(R1), _ptr(R2))
+        f = getattr(lib, "orc_rcholqr_f")
+        f(_ptr(x), m, n, _ld(x), s, ctypes.c_uint64(seed), _ptr(Q), m, _ptr(R), _ptr(info), _ptr(R1), _ptr(R2), flags)
     elif name == "scholqr3":
         f(_ptr(x), m, n, _ld(x), _ptr(Q), m, _ptr(R), _ptr(info), _ptr(R1), _ptr(R2), _ptr(R4))
     else:  # cholqr2, lc2
@@ -321,9 +350,14 @@ METHODS = {"rclupp": rclupp, "rcluppr": rcluppr, "cholqr2": cholqr2, "scholqr3":
            "rcholqr": rcholqr}
 
 
-def run(method: str, x, s=None, seed: int = 0, variant: str = "") -> Result:
+def run(method: str, x, s=None, seed: int = 0, variant: str = "", sketch: str = "gaussian") -> Result:
     """Run one method; variant "separate_muladd" takes the other rounding
-    reading of the LU elimination and the substitution (see VARIANTS)."""
+    reading of the LU elimination and the substitution (see VARIANTS); sketch
+    "count" takes the CountSketch for the sketched methods."""
+    if sketch != "gaussian":
+        if method not in ("rclupp", "rcluppr", "rcholqr"):
+            raise ValueError("only the sketched methods take a sketch")
+        return _run(method, x, s, seed, variant, sketch)
     if variant:
         if method in ("rclupp", "rcluppr", "rcholqr"):
             return _run(method, x, s, seed, variant)

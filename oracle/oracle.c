@@ -198,6 +198,67 @@ void orc_sketch(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s, u
 }
 
 /* ------------------------------------------------------------------------ */
+/* CountSketch (Section 3 names it among the common choices of S): column j  */
+/* of S has a single entry sigma_j = +-1, in row h_j, so Y = S X adds +-row  */
+/* j of X into row h_j of Y (no scaling: E[S^T S] = I). h_j and sigma_j are  */
+/* drawn from Philox4x32-10 with counter (q lo, q hi, 0, 1), q = floor(j/4)  */
+/* (the Gaussian sketch's counters end in 0), key (seed lo, seed hi): word t */
+/* belongs to tall row 4q+t and gives h = floor(w s / 2^32), sigma = +1 for  */
+/* even w and -1 for odd w.                                                  */
+/* ------------------------------------------------------------------------ */
+void orc_countsketch_hash(uint64_t seed, uint64_t j, int64_t s, int64_t* h, double* sigma) {
+  uint64_t q = j / 4;
+  uint32_t ctr[4] = {(uint32_t)q, (uint32_t)(q >> 32), 0u, 1u};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  orc_philox4x32_10(ctr, key, w);
+  uint32_t word = w[j % 4];
+  *h = (int64_t)(((uint64_t)word * (uint64_t)s) >> 32);
+  *sigma = (word & 1u) ? -1.0 : 1.0;
+}
+
+/* Y = S X with the rows added in increasing order inside blocks of ORC_BLOCK
+ * rows and the block sums added in block order (as the Gaussian sketch). */
+void orc_countsketch(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s, uint64_t seed, double* Y) {
+  int64_t nblk = (m + ORC_BLOCK - 1) / ORC_BLOCK;
+  int64_t batch = 2 * (int64_t)orc_max_threads();
+  size_t psz = (size_t)s * (size_t)n;
+  double* part = (double*)malloc(sizeof(double) * psz * (size_t)batch);
+  for (size_t e = 0; e < psz; ++e) Y[e] = 0.0;
+  for (int64_t b0 = 0; b0 < nblk; b0 += batch) {
+    int64_t nb = (nblk - b0 < batch) ? (nblk - b0) : batch;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t bb = 0; bb < nb; ++bb) {
+      double* P = part + (size_t)bb * psz;
+      for (size_t e = 0; e < psz; ++e) P[e] = 0.0;
+      int64_t r0 = (b0 + bb) * ORC_BLOCK;
+      int64_t r1 = r0 + ORC_BLOCK < m ? r0 + ORC_BLOCK : m;
+      for (int64_t j = r0; j < r1; ++j) {
+        int64_t h;
+        double sg;
+        orc_countsketch_hash(seed, (uint64_t)j, s, &h, &sg);
+        for (int64_t k = 0; k < n; ++k) P[h + k * s] += sg * X[j + k * ldx];
+      }
+    }
+    for (int64_t bb = 0; bb < nb; ++bb) {
+      const double* P = part + (size_t)bb * psz;
+      for (size_t e = 0; e < psz; ++e) Y[e] += P[e];
+    }
+  }
+  free(part);
+}
+
+/* The sketch of a method: Gaussian (flags without ORC_SKETCH_COUNT) or CountSketch. */
+#define ORC_SKETCH_COUNT 1
+static void method_sketch(int flags, const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s, uint64_t seed,
+                          double* Y) {
+  if (flags & ORC_SKETCH_COUNT)
+    orc_countsketch(X, m, n, ldx, s, seed, Y);
+  else
+    orc_sketch(X, m, n, ldx, s, seed, Y);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Gram matrix G = W^T W (Algorithm 1, first step), upper triangle summed,   */
 /* then mirrored.                                                           */
 /* ------------------------------------------------------------------------ */
@@ -495,8 +556,8 @@ static int make_r1(const double* R0, const double* N, int64_t n, double* R1, int
 /* ------------------------------------------------------------------------ */
 /* Algorithm 2: RCLUPP.                                                      */
 /* ------------------------------------------------------------------------ */
-int orc_rclupp(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s, uint64_t seed, double* Q, int64_t ldq,
-               double* R, int32_t* info, double* R1_out, double* R2_out, double* R4_out) {
+int orc_rclupp_f(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s, uint64_t seed, double* Q, int64_t ldq,
+                 double* R, int32_t* info, double* R1_out, double* R2_out, double* R4_out, int flags) {
   orc_aux aux = {R1_out, R2_out, R4_out};
   size_t nn = (size_t)(n * n);
   int rc = 0;
@@ -507,7 +568,7 @@ int orc_rclupp(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s, ui
   double* N = (double*)calloc(nn, sizeof(double));
   double* R0 = (double*)calloc(nn, sizeof(double));
   double* R1 = (double*)calloc(nn, sizeof(double));
-  orc_sketch(X, m, n, ldx, s, seed, Y);                       /* X_s = S X          */
+  method_sketch(flags, X, m, n, ldx, s, seed, Y);             /* X_s = S X          */
   rc = orc_gepp(Y, s, n, s, perm, info, ORC_ST_LU);           /* [M, N, P] = LU(X_s) */
   if (!rc) {
     unpack_m(Y, s, n, s, Mf);
@@ -534,8 +595,8 @@ int orc_rclupp(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s, ui
 /* Algorithm 7: RCLUPPr (LU of X first, then the sketch of its L factor).   */
 /* The sketch's column index is the row position in the pivoted order.      */
 /* ------------------------------------------------------------------------ */
-int orc_rcluppr(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s, uint64_t seed, double* Q, int64_t ldq,
-                double* R, int32_t* info, double* R1_out, double* R2_out, double* R4_out) {
+int orc_rcluppr_f(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s, uint64_t seed, double* Q,
+                  int64_t ldq, double* R, int32_t* info, double* R1_out, double* R2_out, double* R4_out, int flags) {
   orc_aux aux = {R1_out, R2_out, R4_out};
   size_t nn = (size_t)(n * n);
   int rc = 0;
@@ -556,7 +617,7 @@ int orc_rcluppr(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s, u
       for (int64_t i = 0; i < j; ++i) A[i + j * m] = 0.0;
       A[j + j * m] = 1.0;
     }
-    orc_sketch(A, m, n, m, s, seed, Ms);                      /* M_s = S M           */
+    method_sketch(flags, A, m, n, m, s, seed, Ms);            /* M_s = S M           */
     int64_t col;
     if (any_nonfinite(Ms, s, n, s, &col)) {
       set_info(info, ORC_NONFINITE, ORC_ST_QR, col + 1);
@@ -674,15 +735,15 @@ int orc_lc2(const double* X, int64_t m, int64_t n, int64_t ldx, double* Q, int64
 /* ------------------------------------------------------------------------ */
 /* Algorithm 6: randomized CholeskyQR (single Gaussian sketch).             */
 /* ------------------------------------------------------------------------ */
-int orc_rcholqr(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s, uint64_t seed, double* Q, int64_t ldq,
-                double* R, int32_t* info, double* R1_out, double* R2_out) {
+int orc_rcholqr_f(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s, uint64_t seed, double* Q,
+                  int64_t ldq, double* R, int32_t* info, double* R1_out, double* R2_out, int flags) {
   orc_aux aux = {R1_out, R2_out, NULL};
   size_t nn = (size_t)(n * n);
   int rc = 0;
   if (info) memset(info, 0, 4 * sizeof(int32_t));
   double* K = (double*)malloc(sizeof(double) * (size_t)(s * n));
   double* R1 = (double*)calloc(nn, sizeof(double));
-  orc_sketch(X, m, n, ldx, s, seed, K);                       /* K = S X             */
+  method_sketch(flags, X, m, n, ldx, s, seed, K);             /* K = S X             */
   int64_t col;
   if (any_nonfinite(K, s, n, s, &col)) {
     set_info(info, ORC_NONFINITE, ORC_ST_QR, col + 1);
@@ -699,4 +760,18 @@ int orc_rcholqr(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s, u
   free(K);
   free(R1);
   return rc;
+}
+
+/* The methods with the Gaussian sketch (flags = 0). */
+int orc_rclupp(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s, uint64_t seed, double* Q, int64_t ldq,
+               double* R, int32_t* info, double* R1_out, double* R2_out, double* R4_out) {
+  return orc_rclupp_f(X, m, n, ldx, s, seed, Q, ldq, R, info, R1_out, R2_out, R4_out, 0);
+}
+int orc_rcluppr(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s, uint64_t seed, double* Q, int64_t ldq,
+                double* R, int32_t* info, double* R1_out, double* R2_out, double* R4_out) {
+  return orc_rcluppr_f(X, m, n, ldx, s, seed, Q, ldq, R, info, R1_out, R2_out, R4_out, 0);
+}
+int orc_rcholqr(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s, uint64_t seed, double* Q, int64_t ldq,
+                double* R, int32_t* info, double* R1_out, double* R2_out) {
+  return orc_rcholqr_f(X, m, n, ldx, s, seed, Q, ldq, R, info, R1_out, R2_out, 0);
 }

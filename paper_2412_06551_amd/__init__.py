@@ -9,6 +9,7 @@ from .api import (  # noqa: F401
     QRResult,
     chol,
     colmajor,
+    countsketch,
     new_colmajor,
     omega,
     philox,
@@ -24,5 +25,5 @@ from .api import (  # noqa: F401
     workspace_size,
 )
 
-__all__ = ["qr", "qr_simple", "qr_noalloc", "qr_batched", "Batch", "workspace_size", "sketch", "omega", "philox",
-           "precond", "trsm_gram", "chol", "tall_lu", "colmajor", "new_colmajor", "QRResult"]
+__all__ = ["qr", "qr_simple", "qr_noalloc", "qr_batched", "Batch", "workspace_size", "sketch", "countsketch", "omega",
+           "philox", "precond", "trsm_gram", "chol", "tall_lu", "colmajor", "new_colmajor", "QRResult"]

@@ -33,7 +33,7 @@ EXPORTS = [
     "rclupp_last_info", "rclupp_status_string", "rclupp_workspace_size", "rclupp_qr_ex",
     "rclupp_batched_workspace_size", "rclupp_qr_batched", "rclupp_omega", "rclupp_philox",
     "rclupp_sketch", "rclupp_precond", "rclupp_trsm_gram", "rclupp_chol", "rclupp_tall_lu",
-    "rclupp_trace_enable", "rclupp_trace_read", "rclupp_release", "rclupp_qr_noalloc",
+    "rclupp_trace_enable", "rclupp_trace_read", "rclupp_release", "rclupp_qr_noalloc", "rclupp_countsketch",
 ]
 
 
@@ -46,9 +46,13 @@ BATCH_GRAPH = 1
 BATCH_AUTOTUNE = 2
 
 
+# sketch kinds (rclupp_opts.sketch_kind)
+SKETCH = {"gaussian": 0, "count": 1}
+
+
 class Opts(ctypes.Structure):
     _fields_ = [("sketch_prec", ctypes.c_int32), ("lu_prec", ctypes.c_int32), ("batch_flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("sketch_kind", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class Problem(ctypes.Structure):
@@ -88,6 +92,7 @@ def load(path: str = LIB_PATH):
         "rclupp_omega": [U64, I64, I64, I64, P, P],
         "rclupp_philox": [P, I64, ctypes.c_uint32, ctypes.c_uint32, P, P],
         "rclupp_sketch": [P, I64, I64, I64, I64, U64, ctypes.c_int, P, P],
+        "rclupp_countsketch": [P, I64, I64, I64, I64, U64, P, P],
         "rclupp_precond": [P, I64, I64, ctypes.c_int, ctypes.c_int, P, P, P, P, P],
         "rclupp_trsm_gram": [P, I64, I64, I64, P, P, I64, P, P],
         "rclupp_chol": [P, I64, I64, ctypes.c_int, P, P, P, I32, P, P],

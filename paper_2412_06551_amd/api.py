@@ -55,10 +55,11 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _opts(sketch_prec="fp64", lu_prec="fp64") -> nat.Opts:
+def _opts(sketch_prec="fp64", lu_prec="fp64", sketch="gaussian") -> nat.Opts:
     o = nat.Opts()
     o.sketch_prec = nat.PREC[sketch_prec]
     o.lu_prec = nat.PREC[lu_prec]
+    o.sketch_kind = nat.SKETCH[sketch]
     return o
 
 
@@ -76,10 +77,11 @@ class QRResult:
         return self.info_host()[0] == nat.INFO_OK
 
 
-def workspace_size(alg: str, m: int, n: int, s: Optional[int] = None, sketch_prec="fp64", lu_prec="fp64") -> int:
+def workspace_size(alg: str, m: int, n: int, s: Optional[int] = None, sketch_prec="fp64", lu_prec="fp64",
+                   sketch="gaussian") -> int:
     nat.load()
     s = _default_s(alg, n, m, s)
-    o = _opts(sketch_prec, lu_prec)
+    o = _opts(sketch_prec, lu_prec, sketch)
     b = ctypes.c_size_t()
     nat.check(nat.load().rclupp_workspace_size(nat.ALG[alg], m, n, s, ctypes.byref(o), ctypes.byref(b)),
               "rclupp_workspace_size")
@@ -96,8 +98,10 @@ def _default_s(alg, n, m, s):
 
 def qr(X: torch.Tensor, alg: str = "rclupp", s: Optional[int] = None, seed: int = 0, sketch_prec: str = "fp64",
        lu_prec: str = "fp64", Q: Optional[torch.Tensor] = None, R: Optional[torch.Tensor] = None,
-       workspace: Optional[torch.Tensor] = None, info: Optional[torch.Tensor] = None, stream=None) -> QRResult:
-    """X = Q R by one of the six methods (rclupp_qr_ex). Q shares X's leading dimension."""
+       workspace: Optional[torch.Tensor] = None, info: Optional[torch.Tensor] = None, stream=None,
+       sketch: str = "gaussian") -> QRResult:
+    """X = Q R by one of the six methods (rclupp_qr_ex). Q shares X's leading
+    dimension; sketch is "gaussian" or "count" (CountSketch)."""
     _require_device()
     m, n = X.shape
     ld = _ld(X)
@@ -110,10 +114,10 @@ def qr(X: torch.Tensor, alg: str = "rclupp", s: Optional[int] = None, seed: int 
         R = torch.empty((n, n), dtype=torch.float64, device=X.device).t()
     if info is None:
         info = torch.zeros(4, dtype=torch.int32, device=X.device)
-    nbytes = workspace_size(alg, m, n, s, sketch_prec, lu_prec)
+    nbytes = workspace_size(alg, m, n, s, sketch_prec, lu_prec, sketch)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=X.device)
-    o = _opts(sketch_prec, lu_prec)
+    o = _opts(sketch_prec, lu_prec, sketch)
     st = nat.load().rclupp_qr_ex(nat.ALG[alg], _ptr(X), m, n, ld, s, ctypes.c_uint64(seed), _ptr(Q), _ptr(R),
                                  ctypes.byref(o), _ptr(workspace), workspace.numel(), _ptr(info), _stream(stream))
     nat.check(st, "rclupp_qr_ex(%s)" % alg)
@@ -237,6 +241,16 @@ def sketch(X: torch.Tensor, s: int, seed: int = 0, prec: str = "fp64") -> torch.
     Y = new_colmajor(s, n)
     nat.check(nat.load().rclupp_sketch(_ptr(X), m, n, _ld(X), s, ctypes.c_uint64(seed), nat.PREC[prec], _ptr(Y),
                                        _stream()), "rclupp_sketch")
+    return Y
+
+
+def countsketch(X: torch.Tensor, s: int, seed: int = 0) -> torch.Tensor:
+    """Y = S X for the CountSketch S (s x n, column-major)."""
+    _require_device()
+    m, n = X.shape
+    Y = new_colmajor(s, n)
+    nat.check(nat.load().rclupp_countsketch(_ptr(X), m, n, _ld(X), s, ctypes.c_uint64(seed), _ptr(Y), _stream()),
+              "rclupp_countsketch")
     return Y
 
 

@@ -69,6 +69,12 @@ int validate(int alg, int64_t m, int64_t n, int64_t ld, int64_t s, const rclupp_
   if (m + 3 * ld >= ((int64_t)1 << 29)) return RCLUPP_ERR_UNSUPPORTED;
   if (o) {
     if (o->sketch_prec < 0 || o->sketch_prec > 2 || o->lu_prec < 0 || o->lu_prec > 1) return RCLUPP_ERR_INVALID_ARG;
+    if (o->sketch_kind != RCLUPP_SKETCH_GAUSSIAN && o->sketch_kind != RCLUPP_SKETCH_COUNT)
+      return RCLUPP_ERR_INVALID_ARG;
+    if (o->sketch_kind == RCLUPP_SKETCH_COUNT && sketched(alg)) {
+      if (o->sketch_prec != RCLUPP_PREC_FP64) return RCLUPP_ERR_UNSUPPORTED;
+      if (plan_countsketch(m, n, s, 0).nn == 0) return RCLUPP_ERR_UNSUPPORTED;
+    }
   }
   return RCLUPP_OK;
 }
@@ -93,7 +99,9 @@ Layout make_layout(int alg, int64_t m, int64_t n, int64_t s, const rclupp_opts* 
   L.info = take(sizeof(rclupp_info));
   L.gates = take(3 * sizeof(rclupp_info));
   if (sketched(alg)) {
-    L.sk = plan_sketch(m, n, s, sk_prec, sketch_grid > 0 ? sketch_grid : env_int("RCLUPP_SKETCH_GRID", 0));
+    const int grid_hint = sketch_grid > 0 ? sketch_grid : env_int("RCLUPP_SKETCH_GRID", 0);
+    L.sk = (o && o->sketch_kind == RCLUPP_SKETCH_COUNT) ? plan_countsketch(m, n, s, grid_hint)
+                                                        : plan_sketch(m, n, s, sk_prec, grid_hint);
     L.ypart = take(L.sk.part_bytes);
     L.y = take((size_t)s * n * sizeof(double));
   }
@@ -330,6 +338,12 @@ int sketch_into(const Layout& L, char* ws, const double* A, int64_t m, int64_t n
   double* ypart = (double*)(ws + L.ypart);
   double* y = (double*)(ws + L.y);
   STAGE("sketch");
+  if (L.sk.kind == 1) {
+    HIPCHK(launch_countsketch_partials(L.sk, A, m, n, lda, s, seed, ypart, info, st));
+    STAGE("sketch_reduce");
+    HIPCHK(launch_sketch_reduce(L.sk, ypart, s, n, 1.0, y, info, st));
+    return RCLUPP_OK;
+  }
   HIPCHK(launch_sketch_partials(L.sk, A, m, n, lda, seed, prec, ypart, info, st));
   STAGE("sketch_reduce");
   HIPCHK(launch_sketch_reduce(L.sk, ypart, s, n, 1.0 / std::sqrt((double)s), y, info, st));
@@ -486,15 +500,18 @@ bool fit_layout(int alg, int64_t m, int64_t n, int64_t s, const rclupp_opts* o, 
   Layout L = make_layout(alg, m, n, s, o);
   const int solve_grid = L.tp.gx_solve;
   int tall_grid = L.tp.gx;
-  int sketch_grid = sketched(alg) ? L.sk.gx * L.sk.gy * L.sk.gz : 0;
+  int sketch_grid = 0;
   while (L.total > cap) {
     const size_t sb = sketched(alg) ? L.sk.part_bytes : 0;
+    // (the Gaussian plan reads its hint as workgroups in all, the CountSketch
+    // plan as row chunks)
+    const int sk_half = L.sk.kind == 1 ? L.sk.gx / 2 : (L.sk.gx / 2) * L.sk.gy * L.sk.gz;
     if (sketched(alg) && sb >= L.tp.part_bytes && L.sk.gx > 1) {
-      sketch_grid = (L.sk.gx / 2) * L.sk.gy * L.sk.gz;
+      sketch_grid = sk_half;
     } else if (L.tp.gx > 1) {
       tall_grid = L.tp.gx / 2;
     } else if (sketched(alg) && L.sk.gx > 1) {
-      sketch_grid = (L.sk.gx / 2) * L.sk.gy * L.sk.gz;
+      sketch_grid = sk_half;
     } else {
       return false;
     }
@@ -688,9 +705,9 @@ struct BatchPlan {
 
 bool batch_groupable(int alg, const rclupp_problem* h, int batch, const rclupp_opts* o) {
   if (alg != RCLUPP_ALG_RCLUPP || batch <= 0) return false;
+  if (o && o->sketch_kind != RCLUPP_SKETCH_GAUSSIAN) return false;
   for (int b = 0; b < batch; ++b)
     if (!precond_reg_fits(h[b].s, h[b].n)) return false;
-  (void)o;
   return true;
 }
 
@@ -987,7 +1004,7 @@ uint64_t shape_key(const rclupp_problem* h, int batch, const rclupp_opts* o) {
     const int64_t v[3] = {h[b].n, h[b].s, (h[b].m + 4095) / 4096};
     k = fnv1a(k, v, sizeof(v));
   }
-  const int32_t pr[2] = {o ? o->sketch_prec : 0, o ? o->lu_prec : 0};
+  const int32_t pr[3] = {o ? o->sketch_prec : 0, o ? o->lu_prec : 0, o ? o->sketch_kind : 0};
   return fnv1a(k, pr, sizeof(pr));
 }
 
@@ -1269,6 +1286,20 @@ int rclupp_sketch(const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, 
       return (int)RCLUPP_ERR_HIP;
     if (launch_sketch_reduce(sk, (double*)p, s, n, 1.0 / std::sqrt((double)s), Y, nullptr, stream) != hipSuccess)
       return (int)RCLUPP_ERR_HIP;
+    return (int)RCLUPP_OK;
+  });
+}
+
+int rclupp_countsketch(const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, uint64_t seed, double* Y,
+                       hipStream_t stream) {
+  if (!X || !Y || n < 1 || m < 1 || ld < m || s < 1) return RCLUPP_ERR_INVALID_ARG;
+  if (n > RCLUPP_MAX_N) return RCLUPP_ERR_UNSUPPORTED;
+  const SketchPlan sk = plan_countsketch(m, n, s, env_int("RCLUPP_SKETCH_GRID", 0));
+  if (sk.nn == 0) return RCLUPP_ERR_UNSUPPORTED;
+  return with_scratch(sk.part_bytes, stream, [&](char* p) {
+    if (launch_countsketch_partials(sk, X, m, n, ld, s, seed, (double*)p, nullptr, stream) != hipSuccess)
+      return (int)RCLUPP_ERR_HIP;
+    if (launch_sketch_reduce(sk, (double*)p, s, n, 1.0, Y, nullptr, stream) != hipSuccess) return (int)RCLUPP_ERR_HIP;
     return (int)RCLUPP_OK;
   });
 }

@@ -185,6 +185,164 @@ __global__ __launch_bounds__(64 * NW) void k_sketch(const double* __restrict__ X
     }
 }
 
+// ---------------------------------------------------------------------------
+// CountSketch (Section 3 lists it among the common sketches): column j of S
+// has one entry sigma_j = +-1, in row h_j, so Y = S X adds +-row j of X into
+// row h_j of Y (no scaling). h_j and sigma_j come from Philox4x32-10 with
+// counter (q lo, q hi, 0, 1), q = floor(j/4), key (seed lo, seed hi): word t
+// belongs to tall row 4q+t, h = floor(w s / 2^32), sigma = -1 for odd w.
+// The pass is HBM-bound (X read once, one add per entry). A workgroup owns a
+// row chunk and a slice of NC columns, keeps its s_pad x NC partial of Y in LDS
+// and walks tiles of TK = 4096 / NC rows of its slice. Every (row of Y,
+// column) sum has one owner, which adds its terms in increasing row order, so
+// the result is deterministic without atomics: thread (c, r) owns column c and
+// the rows h of Y with h mod R = r (R = 256 / NC). Per tile the rows are
+// listed by residue in increasing order (a counting sort: per 64-row chunk a
+// ballot per residue gives the counts and each row's rank, one scan the
+// offsets), then every thread walks its residue's list.
+// The per-chunk partials go through the Gaussian sketch's fixed-order
+// reduction with scale 1.
+// ---------------------------------------------------------------------------
+constexpr int CS_THREADS = 256;
+constexpr int CS_TILE = 4096;  // entries of X per tile (TK x NC)
+
+__device__ __forceinline__ void countsketch_hash4(uint64_t seed, uint64_t q, uint32_t s, int h[4], double sg[4]) {
+  const philox_out w = philox4x32_10((uint32_t)q, (uint32_t)(q >> 32), 0u, 1u, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const uint32_t ws[4] = {w.w0, w.w1, w.w2, w.w3};
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    h[t] = (int)(((uint64_t)ws[t] * (uint64_t)s) >> 32);
+    sg[t] = (ws[t] & 1u) ? -1.0 : 1.0;
+  }
+}
+
+constexpr int cs_tk(int nc) { return CS_TILE / nc; }
+
+size_t countsketch_lds_bytes(int64_t s_pad, int nc) {
+  const int R = CS_THREADS / nc, TK = cs_tk(nc), NCH = TK / 64;
+  return (size_t)s_pad * nc * 8 + (size_t)TK * (nc + 1) * 8 + (size_t)TK * 8 + (size_t)TK * 4 * 2 +
+         (size_t)R * NCH * 4 * 2;
+}
+
+template <int NC>
+__global__ __launch_bounds__(CS_THREADS) void k_countsketch(const double* __restrict__ X, int64_t m, int n, int64_t ld,
+                                                            int64_t ntiles, uint64_t seed, int s,
+                                                            double* __restrict__ Ypart, int64_t s_pad, int64_t n_pad,
+                                                            const int32_t* info) {
+  if (info_failed(info)) return;
+  constexpr int R = CS_THREADS / NC, TK = cs_tk(NC), LDT = NC + 1, NCH = TK / 64;
+  constexpr int EPT = CS_TILE / CS_THREADS;  // tile entries loaded per thread
+  constexpr int CPW = (NCH + 3) / 4;         // 64-row chunks listed per wave
+  static_assert(TK % 64 == 0 && R * NC == CS_THREADS, "tile shape");
+  extern __shared__ __align__(16) unsigned char cs_smem[];
+  double* Y = (double*)cs_smem;         // [s_pad][NC]
+  double* xt = Y + s_pad * NC;          // [TK][LDT]
+  double* sgn = xt + TK * LDT;          // [TK]
+  int* hb = (int*)(sgn + TK);           // [TK] row of Y of each tile row
+  int* lst = hb + TK;                   // [TK] tile rows listed by residue
+  int* ccnt = lst + TK;                 // [R][NCH] rows of residue q in chunk b
+  int* coff = ccnt + R * NCH;           // [R][NCH] their first list position
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t chunk = blockIdx.x, nchunks = gridDim.x;
+  const int col0 = (int)blockIdx.y * NC;
+  const int c = tid % NC, r = tid / NC;
+  for (int64_t e = tid; e < s_pad * NC; e += CS_THREADS) Y[e] = 0.0;
+  double pre[EPT];
+  auto load = [&](int64_t t) {
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int e = tid + CS_THREADS * k, rr = e % TK, cc = e / TK;
+      const int64_t row = t * TK + rr;
+      const int col = col0 + cc;
+      pre[k] = (row < m && col < n) ? X[row + (int64_t)col * ld] : 0.0;
+    }
+  };
+  int64_t t = chunk;
+  if (t < ntiles) load(t);
+  for (; t < ntiles; t += nchunks) {
+    __syncthreads();  // the previous tile's entries and lists are consumed
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int e = tid + CS_THREADS * k;
+      xt[(e % TK) * LDT + e / TK] = pre[k];
+    }
+    for (int g = tid; g < TK / 4; g += CS_THREADS) {
+      int h4[4];
+      double s4[4];
+      countsketch_hash4(seed, (uint64_t)(t * TK) / 4 + g, (uint32_t)s, h4, s4);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        hb[4 * g + u] = h4[u];
+        sgn[4 * g + u] = s4[u];
+      }
+    }
+    __syncthreads();
+    // counting sort by residue: counts and ranks per 64-row chunk
+    int rank[CPW];
+#pragma unroll
+    for (int k = 0; k < CPW; ++k) {
+      const int b = wave + 4 * k;
+      rank[k] = 0;
+      if (b < NCH) {
+        const int res = hb[64 * b + lane] & (R - 1);
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const uint64_t mask = __ballot(res == q);
+          if (res == q) rank[k] = __popcll(mask & ((1ull << lane) - 1ull));
+          if (lane == 0) ccnt[q * NCH + b] = __popcll(mask);
+        }
+      }
+    }
+    __syncthreads();
+    if (wave == 0) {  // exclusive scan of the counts in (residue, chunk) order
+      constexpr int PER = (R * NCH + 63) / 64;
+      int v[PER], sum = 0;
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = lane * PER + i;
+        v[i] = e < R * NCH ? ccnt[e] : 0;
+        sum += v[i];
+      }
+      int incl = sum;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+      }
+      int run = incl - sum;
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = lane * PER + i;
+        if (e < R * NCH) coff[e] = run;
+        run += v[i];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < CPW; ++k) {
+      const int b = wave + 4 * k;
+      if (b < NCH) {
+        const int row = 64 * b + lane, res = hb[row] & (R - 1);
+        lst[coff[res * NCH + b] + rank[k]] = row;
+      }
+    }
+    if (t + nchunks < ntiles) load(t + nchunks);  // in flight during the adds
+    __syncthreads();
+    const int k0 = coff[r * NCH], k1 = (r + 1 < R) ? coff[(r + 1) * NCH] : TK;
+    for (int k = k0; k < k1; ++k) {
+      const int jj = lst[k];
+      double* yp = Y + hb[jj] * NC + c;
+      *yp = __builtin_fma(sgn[jj], xt[jj * LDT + c], *yp);  // +-x exactly, then one rounding
+    }
+  }
+  __syncthreads();
+  double* out = Ypart + chunk * s_pad * n_pad + (int64_t)col0 * s_pad;
+  for (int64_t e = tid; e < s_pad * NC; e += CS_THREADS) {
+    const int64_t i = e % s_pad, cc = e / s_pad;
+    out[i + cc * s_pad] = Y[i * NC + cc];
+  }
+}
+
 // Y[i + j*s] = scale * sum_y lvl[y][i + j*s_pad] (the level-1 sums of the
 // per-workgroup partials, added in split order).
 __global__ void k_sketch_final(const double* __restrict__ lvl, int splits, int64_t s, int64_t n, int64_t s_pad,
@@ -359,6 +517,64 @@ hipError_t launch_philox(const uint32_t* ctr, int64_t count, uint32_t k0, uint32
   hipLaunchKernelGGL(k_philox, dim3((unsigned)((count + threads - 1) / threads)), dim3(threads), 0, st, ctr, count,
                      k0, k1, out);
   return hipGetLastError();
+}
+
+SketchPlan plan_countsketch(int64_t m, int64_t n, int64_t s, int gx_hint) {
+  SketchPlan p{};
+  p.kind = 1;
+  p.s_pad = pad_sketch_rows(s);
+  p.sm = 0;
+  p.nw = 4;
+  p.wm = false;
+  p.gy = 1;
+  const int n16 = pad_cols(n);
+  // the widest column slice whose LDS (partial of Y, tile, lists) leaves room
+  // for two workgroups per CU, else for one (160 KB)
+  int nc = 0;
+  for (int cand = 64; cand >= 8 && nc == 0; cand /= 2)
+    if (cand <= n16 && countsketch_lds_bytes(p.s_pad, cand) <= 80 * 1024) nc = cand;
+  for (int cand = 64; cand >= 8 && nc == 0; cand /= 2)
+    if (cand <= n16 && countsketch_lds_bytes(p.s_pad, cand) <= 160 * 1024) nc = cand;
+  if (nc == 0) return p;  // nn = 0: unsupported (s above 1792)
+  p.nn = nc;
+  p.gz = (int)((n + nc - 1) / nc);
+  p.n_pad = (int64_t)p.gz * nc;
+  p.ntiles = (m + cs_tk(nc) - 1) / cs_tk(nc);
+  // about 2048 workgroups, with the partials kept below a sixteenth of X
+  int64_t gx = gx_hint > 0 ? gx_hint : (2048 + p.gz - 1) / p.gz;
+  const int64_t cap = (m * n) / (16 * p.s_pad * p.n_pad);
+  if (gx_hint <= 0 && gx > cap) gx = cap > 8 ? cap : 8;
+  if (gx > p.ntiles) gx = p.ntiles;
+  if (gx < 1) gx = 1;
+  p.gx = (int)gx;
+  p.part_bytes = ((size_t)p.gx + reduce_splits(p.gx)) * (size_t)p.s_pad * (size_t)p.n_pad * sizeof(double);
+  return p;
+}
+
+template <int NC>
+static hipError_t launch_cs(const SketchPlan& p, const double* X, int64_t m, int64_t n, int64_t ld, int64_t s,
+                            uint64_t seed, double* Ypart, const int32_t* info, hipStream_t st) {
+  const size_t lds = countsketch_lds_bytes(p.s_pad, NC);
+  if (lds > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_countsketch<NC>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_countsketch<NC>, dim3((unsigned)p.gx, (unsigned)p.gz), dim3(CS_THREADS), lds, st, X, m,
+                     (int)n, ld, p.ntiles, seed, (int)s, Ypart, p.s_pad, p.n_pad, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_countsketch_partials(const SketchPlan& p, const double* X, int64_t m, int64_t n, int64_t ld,
+                                       int64_t s, uint64_t seed, double* Ypart, const int32_t* info, hipStream_t st) {
+  if (p.kind != 1 || p.gx < 1 || p.ntiles < 1 || (int64_t)p.gz * p.nn < n || s > p.s_pad) return hipErrorInvalidValue;
+  switch (p.nn) {
+    case 8: return launch_cs<8>(p, X, m, n, ld, s, seed, Ypart, info, st);
+    case 16: return launch_cs<16>(p, X, m, n, ld, s, seed, Ypart, info, st);
+    case 32: return launch_cs<32>(p, X, m, n, ld, s, seed, Ypart, info, st);
+    case 64: return launch_cs<64>(p, X, m, n, ld, s, seed, Ypart, info, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace rclupp

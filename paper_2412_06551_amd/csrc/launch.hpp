@@ -76,10 +76,16 @@ struct SketchPlan {
   int nw;          // waves per workgroup (8, or 4 when s_pad is not a multiple of 128)
   int64_t s_pad;   // padded sketch rows (gy * nw * sm)
   int64_t n_pad;   // padded columns (nn)
-  int64_t ntiles;  // 32-row tiles of the tall operand
+  int64_t ntiles;  // 32-row tiles of the tall operand (CountSketch: 4096 / nn rows)
   size_t part_bytes;  // bytes of the per-chunk partial sums and their level-1 sums
+  int kind;        // 0 Gaussian, 1 CountSketch (nn = column slice, gz slices; nn = 0: unsupported)
 };
 SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int gx_hint);
+SketchPlan plan_countsketch(int64_t m, int64_t n, int64_t s, int gx_hint);
+// CountSketch partials Ypart[gx][s_pad x n_pad] (the same layout and reduction
+// as the Gaussian sketch's, with scale 1).
+hipError_t launch_countsketch_partials(const SketchPlan& p, const double* X, int64_t m, int64_t n, int64_t ld,
+                                       int64_t s, uint64_t seed, double* Ypart, const int32_t* info, hipStream_t st);
 // Ypart[gx][s_pad x n_pad] partial sums of G[:, rows] X[rows, :] (G unscaled).
 hipError_t launch_sketch_partials(const SketchPlan& p, const double* X, int64_t m, int64_t n, int64_t ld, uint64_t seed,
                                   int prec, double* Ypart, const int32_t* info, hipStream_t st);

@@ -368,6 +368,39 @@ def test_mixed_workload_shape_vs_oracle(kappa, sk, lu):
     print("mixed %s/%s kappa=%.0e notes=%d" % (sk, lu, kappa, res.info_host()[3]))
 
 
+# ------------------------------------------------------------------ CountSketch
+# The CountSketch in place of the Gaussian sketch (FP64 sums; FP64 or FP32
+# preconditioner): the same bar against the oracle run with the same sketch.
+@pytest.mark.parametrize("method", ["rclupp", "rcluppr", "rcholqr"])
+@pytest.mark.parametrize("kappa,lu", [(1e4, "fp64"), (1e12, "fp64"), (1e15, "fp64"), (1e8, "fp32"), (1e14, "fp32")])
+def test_countsketch_methods(method, kappa, lu):
+    if method == "rcholqr" and lu == "fp32" and kappa > 1e8:
+        # Algorithm 6 has one CholeskyQR after the preconditioner: an FP32 R_1
+        # leaves kappa(Q_1) near 1e-7 kappa(X), beyond one CholeskyQR's reach
+        pytest.skip("randomized CholeskyQR with an FP32 preconditioner is limited to kappa(X) near 1e8")
+    m, n, s = 30000 + 7, 64, 128
+    x = make_svd(m, n, kappa, seed=41)
+    orc = oracle.run(method, x, s=s, seed=6, sketch="count")
+    res = _lib().qr(to_dev(x), alg=method, s=s, seed=6, sketch="count", lu_prec=lu)
+    method_parity(x, method, s, 6, kappa, res, orc=orc)
+
+
+@pytest.mark.parametrize("kappa", [1e2, 1e14])
+def test_countsketch_wide(kappa):
+    # the n = 256, s = 4n shape (8-column slices)
+    m, n, s = 20000 + 3, 256, 1024
+    x = make_svd(m, n, kappa, seed=42)
+    res = _lib().qr(to_dev(x), alg="rclupp", s=s, seed=1, sketch="count", lu_prec="fp32")
+    method_parity(x, "rclupp", s, 1, kappa, res)
+
+
+def test_countsketch_rejects_reduced_precision_sums():
+    x = make_svd(5000, 16, 1e3, seed=43)
+    with pytest.raises(Exception) as e:
+        _lib().qr(to_dev(x), alg="rclupp", s=32, sketch="count", sketch_prec="bf16")
+    assert getattr(e.value, "status", None) == _nat().ERR_UNSUPPORTED
+
+
 # ------------------------------------------------------------------ full size
 @pytest.mark.parametrize("kappa", [1e4, 1e8, 1e12, 1e15])
 def test_full_size_rclupp(kappa):

@@ -96,6 +96,21 @@ def test_sketch_grid_hint(grid, monkeypatch):
     assert np.all(np.abs(y - want) <= bound)
 
 
+@pytest.mark.parametrize("m,n,s,seed", [(2048, 32, 64, 0), (5000 + 37, 64, 128, 3), (40000 + 3, 256, 1024, 8),
+                                        (3001, 5, 40, 1), (7000 + 1, 16, 1792, 2), (20000 + 11, 100, 200, 4)])
+def test_countsketch_matches_oracle(m, n, s, seed):
+    # every slice width (64, 32, 16, 8 columns), the largest s and a ragged last
+    # tile; the sums
+    # differ from the oracle's only in their association
+    x = make_svd(m, n, 1e6, seed=seed)
+    y = to_host(_lib().countsketch(to_dev(x), s, seed))
+    want = oracle.countsketch(x, s, seed)
+    colsum = np.sum(np.abs(x), axis=0)
+    assert np.all(np.abs(y - want) <= 4 * m * oracle.U * colsum[None, :])
+    # a misplaced row or sign would be O(|x|): the typical error is at rounding level
+    assert np.max(np.abs(y - want)) <= 1e-12 * np.max(colsum)
+
+
 def test_sketch_leading_dimension():
     x = make_svd(3000, 24, 1e3, seed=5)
     a = to_host(_lib().sketch(to_dev(x, ld=3072), 48, 9))
