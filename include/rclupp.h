@@ -124,8 +124,23 @@ typedef struct {
   int32_t lu_prec;
   int32_t batch_flags; /* rclupp_qr_batched only: RCLUPP_BATCH_* bits       */
   int32_t sketch_kind; /* RCLUPP_SKETCH_GAUSSIAN (0) or RCLUPP_SKETCH_COUNT  */
-  int32_t reserved[4];
+  int32_t tall_lu;     /* RCLUPP_TALL_LU_PARTIAL (0) or RCLUPP_TALL_LU_TOURNAMENT */
+  int32_t reserved[3];
 } rclupp_opts;
+
+/* tall_lu (RCLUPPr, LU-CholeskyQR2): the pivoting of the LU of X.
+ *   RCLUPP_TALL_LU_PARTIAL: partial pivoting (LAPACK getrf order), as the
+ *     paper's LU of X; M keeps the pivoted row order (the default);
+ *   RCLUPP_TALL_LU_TOURNAMENT: tournament pivoting (TSLU, Grigori, Demmel and
+ *     Xiang 2011), n <= 128 (else RCLUPP_ERR_UNSUPPORTED): the pivot rows are
+ *     chosen by a tree of partial-pivoting eliminations over 256-row blocks
+ *     (leaves: ceil(m / 256) blocks of consecutive rows; each node keeps its
+ *     first n pivot rows; floor(256 / n) sets merge per node); N and the unit
+ *     lower L_11 come from the root; M = P X N^{-1} is one substitution pass
+ *     and is kept in X's row order (RCLUPPr's sketch then sees M through a
+ *     column permutation of S, a Gaussian matrix of the same distribution). */
+#define RCLUPP_TALL_LU_PARTIAL 0
+#define RCLUPP_TALL_LU_TOURNAMENT 1
 
 /* sketch_kind (RCLUPP, RCLUPPr, randomized CholeskyQR):
  *   RCLUPP_SKETCH_GAUSSIAN: S = G / sqrt(s), G i.i.d. standard normal
@@ -330,6 +345,14 @@ int rclupp_chol(const double* G, int64_t n, int64_t m, int scholqr_shift, double
  * LAPACK getrf), perm (device int32[m]: position -> original row). */
 int rclupp_tall_lu(const double* X, int64_t m, int64_t n, int64_t ldx, double* M, int64_t ldm, int32_t* perm,
                    rclupp_info* d_info, hipStream_t stream);
+
+/* Tournament pivoting of a tall X (m x n, n <= 128; see RCLUPP_TALL_LU_TOURNAMENT):
+ * sel (device int32[n]) = the pivot rows in pivot order (original indices),
+ * N (device, n x n, ld n) = the upper factor, M (m x n, ld ldm, X's row order)
+ * = X N^{-1} with rows sel[k] equal to row k of the unit lower L_11, so that
+ * X[sel, :] = L_11 N. */
+int rclupp_tall_lu_tournament(const double* X, int64_t m, int64_t n, int64_t ldx, double* M, int64_t ldm,
+                              int32_t* sel, double* N, rclupp_info* d_info, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Stage timing (profiling aid). rclupp_trace_enable(max_marks > 0) makes every

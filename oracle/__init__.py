@@ -105,6 +105,8 @@ def _load(variant: str = ""):
         "orc_rcholqr_f": ([P, I64, I64, I64, I64, U64, P, I64, P, P, P, P, ctypes.c_int], ctypes.c_int),
         "orc_countsketch_hash": ([U64, U64, I64, P, P], None),
         "orc_countsketch": ([P, I64, I64, I64, I64, U64, P], None),
+        "orc_tslu": ([P, I64, I64, I64, P, P, P, P, I64, P], ctypes.c_int),
+        "orc_lc2_f": ([P, I64, I64, I64, P, I64, P, P, P, P, ctypes.c_int], ctypes.c_int),
         "chk_orthogonality": ([P, I64, I64, I64], D),
         "chk_residual": ([P, I64, P, I64, P, I64, I64, P, P], None),
     }
@@ -165,6 +167,20 @@ def omega(s: int, cols: int, seed: int, j0: int = 0) -> np.ndarray:
     om = np.zeros((s, cols), order="F")
     _load().orc_omega(ctypes.c_uint64(seed), s, j0, cols, _ptr(om))
     return om
+
+
+def tslu(x):
+    """Tournament pivoting of a tall x (n <= 128): (sel, N, L11, M, info) with
+    x[sel] = L11 N and M = x N^{-1} in x's row order, rows sel equal to L11."""
+    x = _f64(x)
+    m, n = x.shape
+    sel = np.zeros(n, dtype=np.int64)
+    N = np.zeros((n, n), order="F")
+    L11 = np.zeros((n, n), order="F")
+    M = np.zeros((m, n), order="F")
+    info = np.zeros(4, dtype=np.int32)
+    _load().orc_tslu(_ptr(x), m, n, _ld(x), _ptr(sel), _ptr(N), _ptr(L11), _ptr(M), m, _ptr(info))
+    return sel, N, L11, M, info
 
 
 def countsketch_hash(seed: int, j: int, s: int):
@@ -282,11 +298,12 @@ class Result:
         return int(self.info[0]) == OK
 
 
-# method flags: the sketch (Gaussian by default)
+# method flags: the sketch (Gaussian by default) and the pivoting of the LU of X
 SKETCH_FLAGS = {"gaussian": 0, "count": 1}
+LU_FLAGS = {"partial": 0, "tournament": 2}
 
 
-def _run(name: str, x, s=None, seed=None, variant: str = "", sketch: str = "gaussian") -> Result:
+def _run(name: str, x, s=None, seed=None, variant: str = "", sketch: str = "gaussian", lu: str = "partial") -> Result:
     x = _f64(x)
     m, n = x.shape
     Q = np.zeros((m, n), order="F")
@@ -297,7 +314,7 @@ def _run(name: str, x, s=None, seed=None, variant: str = "", sketch: str = "gaus
     info = np.zeros(4, dtype=np.int32)
     lib = _load(variant)
     f = getattr(lib, "orc_" + name)
-    flags = SKETCH_FLAGS[sketch]
+    flags = SKETCH_FLAGS[sketch] | LU_FLAGS[lu]
     if name in ("rclupp", "rcluppr"):
         if not (n <= s <= m):
             raise ValueError("need n <= s <= m")
@@ -311,7 +328,9 @@ def _run(name: str, x, s=None, seed=None, variant: str = "", sketch: str = "gaus
         f(_ptr(x), m, n, _ld(x), s, ctypes.c_uint64(seed), _ptr(Q), m, _ptr(R), _ptr(info), _ptr(R1), _ptr(R2), flags)
     elif name == "scholqr3":
         f(_ptr(x), m, n, _ld(x), _ptr(Q), m, _ptr(R), _ptr(info), _ptr(R1), _ptr(R2), _ptr(R4))
-    else:  # cholqr2, lc2
+    elif name == "lc2":
+        lib.orc_lc2_f(_ptr(x), m, n, _ld(x), _ptr(Q), m, _ptr(R), _ptr(info), _ptr(R1), _ptr(R2), flags)
+    else:  # cholqr2
         f(_ptr(x), m, n, _ld(x), _ptr(Q), m, _ptr(R), _ptr(info), _ptr(R1), _ptr(R2))
     return Result(Q, R, info, R1, R2, R4)
 
@@ -350,14 +369,18 @@ METHODS = {"rclupp": rclupp, "rcluppr": rcluppr, "cholqr2": cholqr2, "scholqr3":
            "rcholqr": rcholqr}
 
 
-def run(method: str, x, s=None, seed: int = 0, variant: str = "", sketch: str = "gaussian") -> Result:
+def run(method: str, x, s=None, seed: int = 0, variant: str = "", sketch: str = "gaussian",
+        lu: str = "partial") -> Result:
     """Run one method; variant "separate_muladd" takes the other rounding
     reading of the LU elimination and the substitution (see VARIANTS); sketch
-    "count" takes the CountSketch for the sketched methods."""
-    if sketch != "gaussian":
-        if method not in ("rclupp", "rcluppr", "rcholqr"):
+    "count" takes the CountSketch for the sketched methods; lu "tournament"
+    takes tournament pivoting for the LU of X (RCLUPPr, LC2)."""
+    if lu != "partial" and method not in ("rcluppr", "lc2"):
+        raise ValueError("only RCLUPPr and LC2 factor X")
+    if sketch != "gaussian" or lu != "partial":
+        if sketch != "gaussian" and method not in ("rclupp", "rcluppr", "rcholqr"):
             raise ValueError("only the sketched methods take a sketch")
-        return _run(method, x, s, seed, variant, sketch)
+        return _run(method, x, s, seed, variant, sketch, lu)
     if variant:
         if method in ("rclupp", "rcluppr", "rcholqr"):
             return _run(method, x, s, seed, variant)

@@ -250,6 +250,7 @@ void orc_countsketch(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t
 
 /* The sketch of a method: Gaussian (flags without ORC_SKETCH_COUNT) or CountSketch. */
 #define ORC_SKETCH_COUNT 1
+#define ORC_LU_TOURNAMENT 2 /* RCLUPPr, LC2: tournament pivoting (orc_tslu) */
 static void method_sketch(int flags, const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s, uint64_t seed,
                           double* Y) {
   if (flags & ORC_SKETCH_COUNT)
@@ -347,6 +348,129 @@ int orc_gepp(double* A, int64_t r, int64_t n, int64_t lda, int64_t* perm, int32_
     }
   }
   return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tournament pivoting (TSLU: Grigori, Demmel and Xiang, SIAM J. Matrix     */
+/* Anal. Appl. 2011) for the LU of a tall X with n <= 128, as an alternative */
+/* to partial pivoting in Algorithm 7 step 1 and Algorithm 5 step 1:         */
+/*   leaves: L = ceil(m / 256) blocks of consecutive rows, block g holding   */
+/*     rows floor(g m / L) .. floor((g+1) m / L) - 1; each is factored with  */
+/*     partial pivoting (ties to the smaller position) and its first n pivot */
+/*     rows are its candidates;                                              */
+/*   tree: F = floor(256 / n) consecutive candidate sets stacked in set      */
+/*     order are factored the same way, keeping their first n pivot rows,    */
+/*     until one set is left;                                                */
+/*   root: the last factorization gives sel (pivot order), L_11 and N.       */
+/* A column whose candidates are all zero keeps its pivot at position k and  */
+/* eliminates nothing below the root; at the root it is a zero pivot.        */
+/* ------------------------------------------------------------------------ */
+static int tslu_factor(double* A, int64_t r, int64_t n, int64_t* idx, int root, int32_t* info) {
+  for (int64_t k = 0; k < n; ++k) {
+    double* ak = A + k * r;
+    int64_t p = k;
+    double best = -1.0;
+    for (int64_t i = k; i < r; ++i) {
+      if (!isfinite(ak[i])) {
+        set_info(info, ORC_NONFINITE, ORC_ST_LU, k + 1);
+        return 1;
+      }
+      if (fabs(ak[i]) > best) {
+        best = fabs(ak[i]);
+        p = i;
+      }
+    }
+    if (best == 0.0) {
+      if (root) {
+        set_info(info, ORC_LU_ZERO_PIVOT, ORC_ST_LU, k + 1);
+        return 1;
+      }
+      continue;
+    }
+    if (p != k) {
+      for (int64_t j = 0; j < n; ++j) {
+        double t = A[k + j * r];
+        A[k + j * r] = A[p + j * r];
+        A[p + j * r] = t;
+      }
+      int64_t t = idx[k];
+      idx[k] = idx[p];
+      idx[p] = t;
+    }
+    double piv = ak[k];
+    for (int64_t i = k + 1; i < r; ++i) ak[i] = ak[i] / piv;
+    for (int64_t j = k + 1; j < n; ++j) {
+      double akj = A[k + j * r];
+      double* aj = A + j * r;
+      for (int64_t i = k + 1; i < r; ++i) aj[i] = ORC_MULADD(-ak[i], akj, aj[i]);
+    }
+  }
+  return 0;
+}
+
+/* One tournament node: the r rows idx[0..r) of X (in that order) factored;
+ * out[0..n) = its first n pivot rows; the root also gives N and L_11. */
+static int tslu_node(const double* X, int64_t ldx, int64_t n, const int64_t* rows, int64_t r, int root, int64_t* out,
+                     double* N, double* L11, int32_t* info) {
+  double* A = (double*)malloc(sizeof(double) * (size_t)(r * n));
+  int64_t* idx = (int64_t*)malloc(sizeof(int64_t) * (size_t)r);
+  for (int64_t i = 0; i < r; ++i) {
+    idx[i] = rows[i];
+    for (int64_t k = 0; k < n; ++k) A[i + k * r] = X[rows[i] + k * ldx];
+  }
+  int rc = tslu_factor(A, r, n, idx, root, info);
+  if (!rc) {
+    for (int64_t p = 0; p < n; ++p) out[p] = idx[p];
+    if (root)
+      for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i) {
+          N[i + j * n] = (i <= j) ? A[i + j * r] : 0.0;
+          L11[i + j * n] = (i > j) ? A[i + j * r] : (i == j ? 1.0 : 0.0);
+        }
+  }
+  free(A);
+  free(idx);
+  return rc;
+}
+
+void orc_trsm(const double* X, int64_t m, int64_t n, int64_t ldx, const double* R, double* W, int64_t ldw);
+
+/* sel (n), N, L_11 (n x n) of the tournament; M (m x n, ld ldm, X's row order)
+ * = X N^{-1} by row-wise substitution, rows sel[k] replaced by row k of L_11. */
+int orc_tslu(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t* sel, double* N, double* L11, double* M,
+             int64_t ldm, int32_t* info) {
+  const int64_t L = (m + 255) / 256, F = 256 / n;
+  int64_t nsets = L;
+  int64_t* sets = (int64_t*)malloc(sizeof(int64_t) * (size_t)(L * n));
+  int64_t* next = (int64_t*)malloc(sizeof(int64_t) * (size_t)(L * n));
+  int64_t* rows = (int64_t*)malloc(sizeof(int64_t) * 256);
+  int rc = 0;
+  for (int64_t g = 0; g < L && !rc; ++g) {
+    const int64_t r0 = g * m / L, r1 = (g + 1) * m / L;
+    for (int64_t i = r0; i < r1; ++i) rows[i - r0] = i;
+    rc = tslu_node(X, ldx, n, rows, r1 - r0, L == 1, L == 1 ? sel : sets + g * n, N, L11, info);
+  }
+  while (!rc && nsets > 1) {
+    const int64_t nodes = (nsets + F - 1) / F;
+    for (int64_t g = 0; g < nodes && !rc; ++g) {
+      const int64_t s0 = g * F, s1 = (s0 + F < nsets) ? s0 + F : nsets;
+      rc = tslu_node(X, ldx, n, sets + s0 * n, (s1 - s0) * n, nodes == 1, nodes == 1 ? sel : next + g * n, N, L11,
+                     info);
+    }
+    int64_t* t = sets;
+    sets = next;
+    next = t;
+    nsets = nodes;
+  }
+  if (!rc && M) {
+    orc_trsm(X, m, n, ldx, N, M, ldm);
+    for (int64_t k = 0; k < n; ++k)
+      for (int64_t j = 0; j < n; ++j) M[sel[k] + j * ldm] = L11[k + j * n];
+  }
+  free(sets);
+  free(next);
+  free(rows);
+  return rc;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -607,16 +731,25 @@ int orc_rcluppr_f(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s,
   double* Ms = (double*)malloc(sizeof(double) * (size_t)(s * n));
   double* R0 = (double*)calloc(nn, sizeof(double));
   double* R1 = (double*)calloc(nn, sizeof(double));
-  copy_tall(X, m, n, ldx, A, m);
-  rc = orc_gepp(A, m, n, m, perm, info, ORC_ST_LU);          /* [M, N, P] = LU(X)   */
-  if (!rc) {
-    unpack_n(A, n, m, N);
-    /* M in place: unit diagonal, zeros above (the packed U part is not M). */
+  if (flags & ORC_LU_TOURNAMENT) {
+    /* [M, N, P] by tournament pivoting; M in X's row order */
+    double* L11 = (double*)malloc(sizeof(double) * nn);
+    rc = orc_tslu(X, m, n, ldx, perm, N, L11, A, m, info);
+    free(L11);
+  } else {
+    copy_tall(X, m, n, ldx, A, m);
+    rc = orc_gepp(A, m, n, m, perm, info, ORC_ST_LU);        /* [M, N, P] = LU(X)   */
+    if (!rc) {
+      unpack_n(A, n, m, N);
+      /* M in place: unit diagonal, zeros above (the packed U part is not M). */
 #pragma omp parallel for schedule(static)
-    for (int64_t j = 0; j < n; ++j) {
-      for (int64_t i = 0; i < j; ++i) A[i + j * m] = 0.0;
-      A[j + j * m] = 1.0;
+      for (int64_t j = 0; j < n; ++j) {
+        for (int64_t i = 0; i < j; ++i) A[i + j * m] = 0.0;
+        A[j + j * m] = 1.0;
+      }
     }
+  }
+  if (!rc) {
     method_sketch(flags, A, m, n, m, s, seed, Ms);            /* M_s = S M           */
     int64_t col;
     if (any_nonfinite(Ms, s, n, s, &col)) {
@@ -696,8 +829,8 @@ int orc_scholqr3(const double* X, int64_t m, int64_t n, int64_t ldx, double* Q, 
 /* Algorithm 5: LU-CholeskyQR2 (LC2). The Cholesky factor of M^T M is named  */
 /* S_c here (the paper reuses the letter S).                                 */
 /* ------------------------------------------------------------------------ */
-int orc_lc2(const double* X, int64_t m, int64_t n, int64_t ldx, double* Q, int64_t ldq, double* R, int32_t* info,
-            double* R1_out, double* R2_out) {
+int orc_lc2_f(const double* X, int64_t m, int64_t n, int64_t ldx, double* Q, int64_t ldq, double* R, int32_t* info,
+              double* R1_out, double* R2_out, int flags) {
   orc_aux aux = {R1_out, R2_out, NULL};
   size_t nn = (size_t)(n * n);
   int rc = 0;
@@ -708,15 +841,23 @@ int orc_lc2(const double* X, int64_t m, int64_t n, int64_t ldx, double* Q, int64
   double* G = (double*)malloc(sizeof(double) * nn);
   double* Sc = (double*)calloc(nn, sizeof(double));
   double* R1 = (double*)calloc(nn, sizeof(double));
-  copy_tall(X, m, n, ldx, A, m);
-  rc = orc_gepp(A, m, n, m, perm, info, ORC_ST_LU);          /* [M, N, P] = LU(X)   */
-  if (!rc) {
-    unpack_n(A, n, m, N);
+  if (flags & ORC_LU_TOURNAMENT) {
+    double* L11 = (double*)malloc(sizeof(double) * nn);
+    rc = orc_tslu(X, m, n, ldx, perm, N, L11, A, m, info);   /* M in X's row order  */
+    free(L11);
+  } else {
+    copy_tall(X, m, n, ldx, A, m);
+    rc = orc_gepp(A, m, n, m, perm, info, ORC_ST_LU);        /* [M, N, P] = LU(X)   */
+    if (!rc) {
+      unpack_n(A, n, m, N);
 #pragma omp parallel for schedule(static)
-    for (int64_t j = 0; j < n; ++j) {
-      for (int64_t i = 0; i < j; ++i) A[i + j * m] = 0.0;
-      A[j + j * m] = 1.0;
+      for (int64_t j = 0; j < n; ++j) {
+        for (int64_t i = 0; i < j; ++i) A[i + j * m] = 0.0;
+        A[j + j * m] = 1.0;
+      }
     }
+  }
+  if (!rc) {
     orc_gram(A, m, n, m, G);                                  /* G = M^T M           */
     rc = orc_chol(G, n, 0.0, Sc, info, ORC_ST_QR);            /* S_c = chol(G)       */
     if (!rc) rc = make_r1(Sc, N, n, R1, info);                /* R_1 = S_c N         */
@@ -774,4 +915,8 @@ int orc_rcluppr(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s, u
 int orc_rcholqr(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s, uint64_t seed, double* Q, int64_t ldq,
                 double* R, int32_t* info, double* R1_out, double* R2_out) {
   return orc_rcholqr_f(X, m, n, ldx, s, seed, Q, ldq, R, info, R1_out, R2_out, 0);
+}
+int orc_lc2(const double* X, int64_t m, int64_t n, int64_t ldx, double* Q, int64_t ldq, double* R, int32_t* info,
+            double* R1_out, double* R2_out) {
+  return orc_lc2_f(X, m, n, ldx, Q, ldq, R, info, R1_out, R2_out, 0);
 }

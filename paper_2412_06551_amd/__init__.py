@@ -21,9 +21,11 @@ from .api import (  # noqa: F401
     qr_simple,
     sketch,
     tall_lu,
+    tall_lu_tournament,
     trsm_gram,
     workspace_size,
 )
 
 __all__ = ["qr", "qr_simple", "qr_noalloc", "qr_batched", "Batch", "workspace_size", "sketch", "countsketch", "omega",
-           "philox", "precond", "trsm_gram", "chol", "tall_lu", "colmajor", "new_colmajor", "QRResult"]
+           "philox", "precond", "trsm_gram", "chol", "tall_lu", "tall_lu_tournament", "colmajor", "new_colmajor",
+           "QRResult"]

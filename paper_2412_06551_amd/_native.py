@@ -34,6 +34,7 @@ EXPORTS = [
     "rclupp_batched_workspace_size", "rclupp_qr_batched", "rclupp_omega", "rclupp_philox",
     "rclupp_sketch", "rclupp_precond", "rclupp_trsm_gram", "rclupp_chol", "rclupp_tall_lu",
     "rclupp_trace_enable", "rclupp_trace_read", "rclupp_release", "rclupp_qr_noalloc", "rclupp_countsketch",
+    "rclupp_tall_lu_tournament",
 ]
 
 
@@ -50,9 +51,13 @@ BATCH_AUTOTUNE = 2
 SKETCH = {"gaussian": 0, "count": 1}
 
 
+# pivoting of the LU of X (rclupp_opts.tall_lu)
+TALL_LU = {"partial": 0, "tournament": 1}
+
+
 class Opts(ctypes.Structure):
     _fields_ = [("sketch_prec", ctypes.c_int32), ("lu_prec", ctypes.c_int32), ("batch_flags", ctypes.c_int32),
-                ("sketch_kind", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("sketch_kind", ctypes.c_int32), ("tall_lu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Problem(ctypes.Structure):
@@ -97,6 +102,7 @@ def load(path: str = LIB_PATH):
         "rclupp_trsm_gram": [P, I64, I64, I64, P, P, I64, P, P],
         "rclupp_chol": [P, I64, I64, ctypes.c_int, P, P, P, I32, P, P],
         "rclupp_tall_lu": [P, I64, I64, I64, P, I64, P, P, P],
+        "rclupp_tall_lu_tournament": [P, I64, I64, I64, P, I64, P, P, P, P],
         "rclupp_trace_enable": [ctypes.c_int],
         "rclupp_trace_read": [ctypes.c_int, ctypes.c_char_p, ctypes.c_int, P, P, P],
         "rclupp_release": [],

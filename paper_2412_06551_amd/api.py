@@ -55,11 +55,12 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _opts(sketch_prec="fp64", lu_prec="fp64", sketch="gaussian") -> nat.Opts:
+def _opts(sketch_prec="fp64", lu_prec="fp64", sketch="gaussian", tall_lu="partial") -> nat.Opts:
     o = nat.Opts()
     o.sketch_prec = nat.PREC[sketch_prec]
     o.lu_prec = nat.PREC[lu_prec]
     o.sketch_kind = nat.SKETCH[sketch]
+    o.tall_lu = nat.TALL_LU[tall_lu]
     return o
 
 
@@ -78,10 +79,10 @@ class QRResult:
 
 
 def workspace_size(alg: str, m: int, n: int, s: Optional[int] = None, sketch_prec="fp64", lu_prec="fp64",
-                   sketch="gaussian") -> int:
+                   sketch="gaussian", tall_lu="partial") -> int:
     nat.load()
     s = _default_s(alg, n, m, s)
-    o = _opts(sketch_prec, lu_prec, sketch)
+    o = _opts(sketch_prec, lu_prec, sketch, tall_lu)
     b = ctypes.c_size_t()
     nat.check(nat.load().rclupp_workspace_size(nat.ALG[alg], m, n, s, ctypes.byref(o), ctypes.byref(b)),
               "rclupp_workspace_size")
@@ -99,9 +100,10 @@ def _default_s(alg, n, m, s):
 def qr(X: torch.Tensor, alg: str = "rclupp", s: Optional[int] = None, seed: int = 0, sketch_prec: str = "fp64",
        lu_prec: str = "fp64", Q: Optional[torch.Tensor] = None, R: Optional[torch.Tensor] = None,
        workspace: Optional[torch.Tensor] = None, info: Optional[torch.Tensor] = None, stream=None,
-       sketch: str = "gaussian") -> QRResult:
+       sketch: str = "gaussian", tall_lu: str = "partial") -> QRResult:
     """X = Q R by one of the six methods (rclupp_qr_ex). Q shares X's leading
-    dimension; sketch is "gaussian" or "count" (CountSketch)."""
+    dimension; sketch is "gaussian" or "count" (CountSketch); tall_lu (RCLUPPr,
+    LC2) is "partial" or "tournament" pivoting."""
     _require_device()
     m, n = X.shape
     ld = _ld(X)
@@ -114,10 +116,10 @@ def qr(X: torch.Tensor, alg: str = "rclupp", s: Optional[int] = None, seed: int 
         R = torch.empty((n, n), dtype=torch.float64, device=X.device).t()
     if info is None:
         info = torch.zeros(4, dtype=torch.int32, device=X.device)
-    nbytes = workspace_size(alg, m, n, s, sketch_prec, lu_prec, sketch)
+    nbytes = workspace_size(alg, m, n, s, sketch_prec, lu_prec, sketch, tall_lu)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=X.device)
-    o = _opts(sketch_prec, lu_prec, sketch)
+    o = _opts(sketch_prec, lu_prec, sketch, tall_lu)
     st = nat.load().rclupp_qr_ex(nat.ALG[alg], _ptr(X), m, n, ld, s, ctypes.c_uint64(seed), _ptr(Q), _ptr(R),
                                  ctypes.byref(o), _ptr(workspace), workspace.numel(), _ptr(info), _stream(stream))
     nat.check(st, "rclupp_qr_ex(%s)" % alg)
@@ -312,3 +314,16 @@ def tall_lu(X: torch.Tensor):
     nat.check(nat.load().rclupp_tall_lu(_ptr(X), m, n, _ld(X), _ptr(M), m, _ptr(perm), _ptr(info), _stream()),
               "rclupp_tall_lu")
     return M, perm, info
+
+
+def tall_lu_tournament(X: torch.Tensor):
+    """(M in X's row order, sel int32[n], N (n x n), info) of tournament pivoting."""
+    _require_device()
+    m, n = X.shape
+    M = new_colmajor(m, n)
+    sel = torch.empty(n, dtype=torch.int32, device="cuda")
+    N = torch.empty((n, n), dtype=torch.float64, device="cuda").t()
+    info = torch.zeros(4, dtype=torch.int32, device="cuda")
+    nat.check(nat.load().rclupp_tall_lu_tournament(_ptr(X), m, n, _ld(X), _ptr(M), m, _ptr(sel), _ptr(N), _ptr(info),
+                                                   _stream()), "rclupp_tall_lu_tournament")
+    return M, sel, N, info

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librclupp.so")
-SOURCES = ["k_sketch.hip", "k_tall.hip", "k_small.hip", "k_dense.hip", "k_tall_lu.hip", "capi.hip"]
+SOURCES = ["k_sketch.hip", "k_tall.hip", "k_small.hip", "k_dense.hip", "k_tall_lu.hip", "k_tslu.hip", "capi.hip"]
 ARCH = os.environ.get("RCLUPP_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=" + ARCH,

@@ -56,6 +56,7 @@ struct Layout {
          perm = 0, nmat = 0, lu = 0, total = 0;
   SketchPlan sk{};
   TallPlan tp{};
+  bool tslu = false;  // the tall LU takes tournament pivoting
 };
 
 int validate(int alg, int64_t m, int64_t n, int64_t ld, int64_t s, const rclupp_opts* o) {
@@ -71,6 +72,8 @@ int validate(int alg, int64_t m, int64_t n, int64_t ld, int64_t s, const rclupp_
     if (o->sketch_prec < 0 || o->sketch_prec > 2 || o->lu_prec < 0 || o->lu_prec > 1) return RCLUPP_ERR_INVALID_ARG;
     if (o->sketch_kind != RCLUPP_SKETCH_GAUSSIAN && o->sketch_kind != RCLUPP_SKETCH_COUNT)
       return RCLUPP_ERR_INVALID_ARG;
+    if (o->tall_lu != RCLUPP_TALL_LU_PARTIAL && o->tall_lu != RCLUPP_TALL_LU_TOURNAMENT) return RCLUPP_ERR_INVALID_ARG;
+    if (o->tall_lu == RCLUPP_TALL_LU_TOURNAMENT && uses_tall_lu(alg) && n > 128) return RCLUPP_ERR_UNSUPPORTED;
     if (o->sketch_kind == RCLUPP_SKETCH_COUNT && sketched(alg)) {
       if (o->sketch_prec != RCLUPP_PREC_FP64) return RCLUPP_ERR_UNSUPPORTED;
       if (plan_countsketch(m, n, s, 0).nn == 0) return RCLUPP_ERR_UNSUPPORTED;
@@ -118,9 +121,10 @@ Layout make_layout(int alg, int64_t m, int64_t n, int64_t s, const rclupp_opts* 
   }
   L.small = take(small);
   if (uses_tall_lu(alg)) {
-    L.perm = take((size_t)m * sizeof(int32_t));
+    L.tslu = o && o->tall_lu == RCLUPP_TALL_LU_TOURNAMENT;
+    L.perm = take((size_t)(L.tslu ? n : m) * sizeof(int32_t));
     L.nmat = take((size_t)n * n * sizeof(double));
-    L.lu = take(tall_lu_scratch_bytes(m, n));
+    L.lu = take(L.tslu ? tslu_scratch_bytes(m, n) : tall_lu_scratch_bytes(m, n));
   }
   L.total = off;
   return L;
@@ -350,6 +354,18 @@ int sketch_into(const Layout& L, char* ws, const double* A, int64_t m, int64_t n
   return RCLUPP_OK;
 }
 
+// The LU of X for RCLUPPr and LC2: M into Q (pivoted row order for partial
+// pivoting, X's row order for tournament pivoting), N into the workspace.
+hipError_t tall_lu_into(const Layout& L, char* ws, const double* X, int64_t m, int64_t n, int64_t ld, double* Q,
+                        int32_t* info, hipStream_t st) {
+  int32_t* perm = (int32_t*)(ws + L.perm);
+  double* nmat = (double*)(ws + L.nmat);
+  if (L.tslu) return launch_tslu(X, m, n, ld, Q, ld, perm, nmat, (double*)(ws + L.lu), info, st);
+  hipError_t e = launch_tall_lu(X, m, n, ld, Q, ld, perm, nmat, (double*)(ws + L.lu), info, st);
+  if (e != hipSuccess) return e;
+  return launch_unit_lower(Q, m, n, ld, info, st);
+}
+
 int run_method(int alg, const Layout& L, char* ws, const double* X, int64_t m, int64_t n, int64_t ld, int64_t s,
                uint64_t seed, double* Q, double* R, const rclupp_opts* o, int32_t* info, hipStream_t st) {
   const int sk_prec = o ? o->sketch_prec : 0;
@@ -376,11 +392,9 @@ int run_method(int alg, const Layout& L, char* ws, const double* X, int64_t m, i
                             info, RCLUPP_STAGE_QR, st));
       return tail_cholqr1(L, ws, X, m, n, ld, Q, R, info, st);
     case RCLUPP_ALG_RCLUPPR: {
-      int32_t* perm = (int32_t*)(ws + L.perm);
       double* nmat = (double*)(ws + L.nmat);
       STAGE("tall_lu");
-      HIPCHK(launch_tall_lu(X, m, n, ld, Q, ld, perm, nmat, (double*)(ws + L.lu), info, st));
-      HIPCHK(launch_unit_lower(Q, m, n, ld, info, st));
+      HIPCHK(tall_lu_into(L, ws, X, m, n, ld, Q, info, st));
       if ((rc = sketch_into(L, ws, Q, m, n, ld, s, seed, sk_prec, info, st))) return rc;
       STAGE("precond");
       HIPCHK(launch_precond((double*)(ws + L.y), s, n, 0, lu_prec, nmat, n, r1, nullptr, nullptr, nullptr, small, info,
@@ -404,11 +418,9 @@ int run_method(int alg, const Layout& L, char* ws, const double* X, int64_t m, i
       HIPCHK(launch_chol(g, np, n, m, 1, r1, nullptr, 0, nullptr, nullptr, 0, small, info, RCLUPP_STAGE_PRECOND, st));
       return tail_cholqr2(L, ws, X, m, n, ld, Q, R, info, st);
     case RCLUPP_ALG_LC2: {
-      int32_t* perm = (int32_t*)(ws + L.perm);
       double* nmat = (double*)(ws + L.nmat);
       STAGE("tall_lu");
-      HIPCHK(launch_tall_lu(X, m, n, ld, Q, ld, perm, nmat, (double*)(ws + L.lu), info, st));
-      HIPCHK(launch_unit_lower(Q, m, n, ld, info, st));
+      HIPCHK(tall_lu_into(L, ws, X, m, n, ld, Q, info, st));
       STAGE("gram");
       HIPCHK(launch_tall_pass(L.tp, Q, ld, m, n, nullptr, nullptr, ld, gpart, info, st));
       STAGE("gram_reduce");
@@ -1373,6 +1385,20 @@ int rclupp_chol(const double* G, int64_t n, int64_t m, int scholqr_shift, double
                     (double*)(p + 2 * rb), info, stage, stream) != hipSuccess)
       return (int)RCLUPP_ERR_HIP;
     if (launch_unpad(rpad, n, R, stream) != hipSuccess) return (int)RCLUPP_ERR_HIP;
+    return (int)RCLUPP_OK;
+  });
+}
+
+int rclupp_tall_lu_tournament(const double* X, int64_t m, int64_t n, int64_t ldx, double* M, int64_t ldm,
+                              int32_t* sel, double* N, rclupp_info* d_info, hipStream_t stream) {
+  if (!X || !M || !sel || !N || n < 1 || m < n || ldx < m || ldm < m) return RCLUPP_ERR_INVALID_ARG;
+  if (n > 128 || m > (int64_t)INT32_MAX) return RCLUPP_ERR_UNSUPPORTED;
+  if (m + 3 * ldx >= ((int64_t)1 << 29) || m + 3 * ldm >= ((int64_t)1 << 29)) return RCLUPP_ERR_UNSUPPORTED;
+  const size_t sb = tslu_scratch_bytes(m, n);
+  return with_scratch(sb + kAlign, stream, [&](char* p) {
+    int32_t* info = d_info ? (int32_t*)d_info : (int32_t*)(p + sb);
+    if (!d_info) hipLaunchKernelGGL(k_zero_info, dim3(1), dim3(64), 0, stream, (rclupp_info*)info);
+    if (launch_tslu(X, m, n, ldx, M, ldm, sel, N, (double*)p, info, stream) != hipSuccess) return (int)RCLUPP_ERR_HIP;
     return (int)RCLUPP_OK;
   });
 }

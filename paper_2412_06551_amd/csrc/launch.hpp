@@ -159,6 +159,13 @@ size_t tall_lu_scratch_bytes(int64_t m, int64_t n);
 // (user layout n x n, ld n) if Nout != nullptr.
 hipError_t launch_tall_lu(const double* X, int64_t m, int64_t n, int64_t ldx, double* M, int64_t ldm, int32_t* perm,
                           double* Nout, double* scratch, int32_t* info, hipStream_t st);
+// Tournament pivoting (k_tslu.hip), n <= 128: sel[0..n) = the pivot rows (original
+// indices, pivot order), Nout (nullable, n x n, ld n) = N, W (m x n, ld ldw, X's
+// row order) = X N^{-1} with the rows sel[k] holding L_11's rows exactly.
+int64_t tslu_leaves(int64_t m);
+size_t tslu_scratch_bytes(int64_t m, int64_t n);
+hipError_t launch_tslu(const double* X, int64_t m, int64_t n, int64_t ldx, double* W, int64_t ldw, int32_t* sel,
+                       double* Nout, double* scratch, int32_t* info, hipStream_t st);
 // M <- unit lower trapezoid of the packed LU (zero above, one on the diagonal).
 hipError_t launch_unit_lower(double* M, int64_t m, int64_t n, int64_t ldm, const int32_t* info, hipStream_t st);
 

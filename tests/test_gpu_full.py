@@ -86,6 +86,15 @@ def test_full_size_krylov_rcluppr():
     del X
 
 
+def test_full_size_krylov_rcluppr_tournament():
+    # the same workload with tournament pivoting for the LU of X
+    m, n, s = 16777216, 128, 256
+    X = make_krylov_device(m, n, seed=0)
+    res = _lib().qr(X, alg="rcluppr", s=s, seed=0, tall_lu="tournament")
+    _props(X, res)
+    del res, X
+
+
 def test_full_size_batch():
     # the 512-problem batch as the benchmark runs it (grouped by (n, s), graph
     # replay, autotuned rows per workgroup), every problem checked, on the

@@ -401,6 +401,32 @@ def test_countsketch_rejects_reduced_precision_sums():
     assert getattr(e.value, "status", None) == _nat().ERR_UNSUPPORTED
 
 
+# ------------------------------------------------------------------ tournament pivoting
+@pytest.mark.parametrize("method", ["rcluppr", "lc2"])
+@pytest.mark.parametrize("kappa", [1e4, 1e12, 1e15])
+def test_tournament_methods(method, kappa):
+    m, n, s = 30000 + 9, 64, 128
+    x = make_svd(m, n, kappa, seed=44)
+    orc = oracle.run(method, x, s=s, seed=5, lu="tournament")
+    res = _lib().qr(to_dev(x), alg=method, s=s, seed=5, tall_lu="tournament")
+    method_parity(x, method, s, 5, kappa, res, orc=orc)
+
+
+@pytest.mark.parametrize("n", [16, 100, 128])
+def test_tournament_rcluppr_shapes(n):
+    m, s = 50000 + 1, 2 * n
+    x = make_svd(m, n, 1e10, seed=45)
+    res = _lib().qr(to_dev(x), alg="rcluppr", s=s, seed=2, tall_lu="tournament")
+    method_parity(x, "rcluppr", s, 2, 1e10, res, orc=oracle.run("rcluppr", x, s=s, seed=2, lu="tournament"))
+
+
+def test_tournament_rejects_wide():
+    x = make_svd(5000, 200, 1e3, seed=46)
+    with pytest.raises(Exception) as e:
+        _lib().qr(to_dev(x), alg="rcluppr", s=400, tall_lu="tournament")
+    assert getattr(e.value, "status", None) == _nat().ERR_UNSUPPORTED
+
+
 # ------------------------------------------------------------------ full size
 @pytest.mark.parametrize("kappa", [1e4, 1e8, 1e12, 1e15])
 def test_full_size_rclupp(kappa):

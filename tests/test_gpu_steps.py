@@ -418,6 +418,40 @@ def test_tall_lu_matches_oracle(m, n):
     np.testing.assert_allclose(np.triu(lu[:n]), No, rtol=0, atol=1e-12 * np.abs(No).max())
 
 
+# ---------------------------------------------------------------- tournament pivoting
+@pytest.mark.parametrize("m,n,kappa", [(5000, 16, 1e6), (9001, 40, 1e10), (3000, 64, 1e4), (2600, 100, 1e8),
+                                       (70000 + 3, 8, 1e3), (300, 128, 1e2), (256, 30, 1e5), (40000 + 7, 128, 1e12)])
+def test_tournament_lu_matches_oracle(m, n, kappa):
+    # the selection is integer work: pivot rows identical; the tree's
+    # eliminations use the same operations, so N and L_11 equal the oracle's bit
+    # for bit; M = X N^{-1} by the tall substitution meets its row-wise bound
+    x = make_svd(m, n, kappa, seed=m % 97)
+    M, sel, N, info = _lib().tall_lu_tournament(to_dev(x))
+    sel_o, N_o, L_o, M_o, info_o = oracle.tslu(x)
+    assert info.cpu().tolist()[0] == 0 and info_o[0] == 0
+    sel_h = sel.cpu().numpy()
+    np.testing.assert_array_equal(sel_h, sel_o)
+    np.testing.assert_array_equal(to_host(N), N_o)
+    m_h = to_host(M)
+    np.testing.assert_array_equal(m_h[sel_h], L_o)
+    bound = 2 * (n + 3) * oracle.U * (np.abs(m_h) @ np.abs(N_o))
+    assert np.all(np.abs(m_h @ N_o - x) <= bound + 1e-300)
+
+
+def test_tournament_lu_singular_leaf_and_zero_column():
+    m, n = 2048, 12
+    x = make_svd(m, n, 1e3, seed=7)
+    x[:256] = x[0]  # a rank-one leaf
+    M, sel, N, info = _lib().tall_lu_tournament(to_dev(x))
+    sel_o, N_o, _, _, _ = oracle.tslu(x)
+    assert info.cpu().tolist()[0] == 0
+    np.testing.assert_array_equal(sel.cpu().numpy(), sel_o)
+    y = make_svd(3000, 10, 1e2, seed=8)
+    y[:, 4] = 0.0  # a zero column: the root's zero pivot
+    _, _, _, info = _lib().tall_lu_tournament(to_dev(y))
+    assert info.cpu().tolist()[:3] == [oracle.LU_ZERO_PIVOT, 1, 5]
+
+
 def test_tall_lu_zero_pivot():
     x = np.asfortranarray(np.random.default_rng(2).standard_normal((3000, 12)))
     x[:, 7] = 0.0
