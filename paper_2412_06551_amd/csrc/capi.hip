@@ -16,7 +16,10 @@
 // R_4 = chol(G_2), R = R_4 R_3 -> Q = Q_2 R_4^{-1} in place.
 #include <hip/hip_runtime.h>
 
+#include <sys/stat.h>
+
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -694,8 +697,15 @@ namespace {
 // passes are chosen per batch shape by timing the candidates once. Other
 // methods, and shapes beyond the register-resident small kernels, run one
 // problem after another with the single-problem pipeline.
-constexpr int kTuneTpw[] = {4, 8, 16};  // tall tiles per workgroup (sketch: twice as many)
-constexpr int kDefaultTpw = 8;
+// Tuning knobs of a grouped batch: tall tiles (64 or 128 rows) per workgroup
+// of the tall passes, and 32-row tiles per workgroup of the sketch.
+struct BatchTune {
+  int tall_tpw;
+  int sk_tpw;
+};
+constexpr int kTuneTall[] = {4, 8, 16};
+constexpr int kTuneSketch[] = {16, 32, 64};
+constexpr BatchTune kDefaultTune = {8, 32};
 
 struct BatchProbPlan {
   int b;             // index in the caller's array
@@ -725,7 +735,8 @@ bool batch_groupable(int alg, const rclupp_problem* h, int batch, const rclupp_o
 
 int64_t tall_tiles(int64_t m, int np) { return (m + (np > 128 ? 64 : 128) - 1) / (np > 128 ? 64 : 128); }
 
-BatchPlan make_batch_plan(const rclupp_problem* h, int batch, const rclupp_opts* o, int tpw) {
+BatchPlan make_batch_plan(const rclupp_problem* h, int batch, const rclupp_opts* o, BatchTune tune) {
+  const int tpw = tune.tall_tpw;
   BatchPlan P;
   const int prec = o ? o->sketch_prec : 0;
   std::map<std::pair<int64_t, int64_t>, int> gi;
@@ -744,7 +755,7 @@ BatchPlan make_batch_plan(const rclupp_problem* h, int batch, const rclupp_opts*
     BatchProbPlan pp{};
     pp.b = b;
     pp.sk = plan_sketch(h[b].m, h[b].n, h[b].s, prec, 0);
-    int64_t skw = (pp.sk.ntiles + 4 * tpw - 1) / (4 * tpw);  // 128 tpw rows per sketch workgroup
+    int64_t skw = (pp.sk.ntiles + tune.sk_tpw - 1) / tune.sk_tpw;
     if (skw > 1024) skw = 1024;
     pp.sk.gx = (int)(skw < 1 ? 1 : skw);
     pp.sk.part_bytes = ((size_t)pp.sk.gx + reduce_splits(pp.sk.gx)) * pp.sk.s_pad * pp.sk.n_pad * sizeof(double);
@@ -880,6 +891,37 @@ __global__ void k_zero_infos(rclupp_info* info, int count) {
   if (i < count) info[i] = rclupp_info{0, 0, 0, 0};
 }
 
+// Side streams of the grouped batch (one set per device, default priority):
+// the (n, s) groups are independent, so each runs on its own stream between a
+// fork and a join event; one group's small stages (one workgroup per problem)
+// then overlap with another group's tall passes. Also inside a captured graph,
+// where the events become the branches' dependencies.
+constexpr int kSideStreams = 4;
+struct SideStreams {
+  hipStream_t s[kSideStreams] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kSideStreams] = {};
+  bool ok = false;  // all created (else the groups run one after another on the caller's stream)
+};
+std::map<int, SideStreams> g_side;  // guarded by g_batch_mu
+
+SideStreams* side_streams() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  auto it = g_side.find(dev);
+  if (it != g_side.end()) return it->second.ok ? &it->second : nullptr;
+  SideStreams ss;
+  bool ok = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; i < kSideStreams && ok; ++i) {
+    ok = hipStreamCreateWithFlags(&ss.s[i], hipStreamNonBlocking) == hipSuccess;
+    if (ok) ok = hipEventCreateWithFlags(&ss.join[i], hipEventDisableTiming) == hipSuccess;
+  }
+  ss.ok = ok;
+  auto& slot = g_side[dev];
+  slot = ss;  // kept (and freed by rclupp_release) even if incomplete
+  return ok ? &slot : nullptr;
+}
+
 // The launch sequence of a grouped batch (tables already in place on `st`).
 int batch_launch(const BatchPlan& P, const std::vector<GroupTables>& GT, char* tab, rclupp_info* infos, int batch,
                  const rclupp_opts* o, hipStream_t st) {
@@ -887,7 +929,14 @@ int batch_launch(const BatchPlan& P, const std::vector<GroupTables>& GT, char* t
   const int lu_prec = o ? o->lu_prec : 0;
   hipLaunchKernelGGL(k_zero_infos, dim3((batch + 255) / 256), dim3(256), 0, st, infos, batch);
   HIPCHK(hipGetLastError());
+  SideStreams* side = P.groups.size() > 1 ? side_streams() : nullptr;
+  if (side) HIPCHK(hipEventRecord(side->fork, st));
+  const hipStream_t main_st = st;
   for (size_t gi = 0; gi < P.groups.size(); ++gi) {
+    if (side) {
+      st = side->s[gi % kSideStreams];
+      if (gi < (size_t)kSideStreams) HIPCHK(hipStreamWaitEvent(st, side->fork, 0));
+    }
     const BatchGroupPlan& g = P.groups[gi];
     const GroupTables& T = GT[gi];
     const int cnt = (int)g.probs.size();
@@ -913,6 +962,13 @@ int batch_launch(const BatchPlan& P, const std::vector<GroupTables>& GT, char* t
     HIPCHK(launch_gram_final_batch(g.np, g.n, gj, cnt, st));
     HIPCHK(launch_chol_batch(g.n, g.np, 1, (const CholJob*)J(T.c2), cnt, RCLUPP_STAGE_CHOL_B, st));
     HIPCHK(launch_tall_batch(g.np, (int)g.n, true, false, true, (const TallJob*)J(T.t3), ti, T.n_t_items, st));
+  }
+  if (side) {
+    const size_t used = P.groups.size() < (size_t)kSideStreams ? P.groups.size() : (size_t)kSideStreams;
+    for (size_t i = 0; i < used; ++i) {
+      HIPCHK(hipEventRecord(side->join[i], side->s[i]));
+      HIPCHK(hipStreamWaitEvent(main_st, side->join[i], 0));
+    }
   }
   return RCLUPP_OK;
 }
@@ -959,7 +1015,7 @@ std::vector<PinnedBuf*> g_pinned;
 std::map<uint64_t, GraphEntry> g_graphs;
 std::vector<RetiredExec> g_retired;  // evicted graphs whose last replay may still run
 uint64_t g_tick = 0;
-std::map<uint64_t, int> g_tuned;  // batch shape -> tall tiles per workgroup
+std::map<uint64_t, BatchTune> g_tuned;  // (architecture, batch shape) -> tuned knobs
 std::map<int, hipStream_t> g_capture_stream;
 constexpr size_t kGraphCacheEntries = 16;
 
@@ -1061,24 +1117,97 @@ int batch_run_once(const BatchPlan& P, const rclupp_problem* h, int batch, const
   return rc;
 }
 
+// ---- persistent tuning cache ------------------------------------------------------
+// Tuned knobs are kept in memory and, unless RCLUPP_TUNE_CACHE is "off", in a
+// text file (RCLUPP_TUNE_CACHE, else $HOME/.cache/rclupp_batch_tune.txt) with
+// one "key tall_tpw sk_tpw" line per batch shape; the key hashes the device's
+// architecture name with the shape key (n, s and m in 4096-row buckets per
+// problem, the precisions). The file is read once per process and appended to
+// after each tuning; any I/O failure leaves the in-memory table in charge.
+std::string tune_cache_path() {
+  const char* e = std::getenv("RCLUPP_TUNE_CACHE");
+  if (e && std::strcmp(e, "off") == 0) return std::string();
+  if (e && *e) return std::string(e);
+  const char* home = std::getenv("HOME");
+  if (!home || !*home) return std::string();
+  return std::string(home) + "/.cache/rclupp_batch_tune.txt";
+}
+
+bool g_tune_file_read = false;
+
+void tune_cache_load() {
+  if (g_tune_file_read) return;
+  g_tune_file_read = true;
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return;
+  unsigned long long key = 0;
+  int a = 0, b = 0;
+  auto known = [](int v, const int* c, int nc) {
+    for (int i = 0; i < nc; ++i)
+      if (c[i] == v) return true;
+    return false;
+  };
+  // only candidate values are taken (the workspace size assumes them)
+  while (std::fscanf(f, "%llx %d %d", &key, &a, &b) == 3)
+    if (known(a, kTuneTall, 3) && known(b, kTuneSketch, 3)) g_tuned[(uint64_t)key] = BatchTune{a, b};
+  std::fclose(f);
+}
+
+void tune_cache_store(uint64_t key, BatchTune t) {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos && slash > 0) (void)mkdir(path.substr(0, slash).c_str(), 0755);
+  FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f, "%016llx %d %d\n", (unsigned long long)key, t.tall_tpw, t.sk_tpw);
+  std::fclose(f);
+}
+
+uint64_t arch_key(uint64_t k) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return k;
+  return fnv1a(k, prop.gcnArchName, std::strlen(prop.gcnArchName));
+}
+
+// Times one complete grouped run of `t` on `stream` (waits for it); < 0 if the
+// plan does not fit the workspace.
+int time_candidate(const rclupp_problem* h, int batch, const rclupp_opts* o, char* ws, size_t ws_bytes,
+                   rclupp_info* d_info, hipStream_t stream, BatchTune t, hipEvent_t e0, hipEvent_t e1, float* ms) {
+  BatchPlan P = make_batch_plan(h, batch, o, t);
+  *ms = -1.f;
+  if (P.total > ws_bytes) return RCLUPP_OK;
+  rclupp_info* infos = d_info ? d_info : (rclupp_info*)(ws + P.info_off);
+  if (hipEventRecord(e0, stream) != hipSuccess) return RCLUPP_ERR_HIP;
+  int rc = batch_run_once(P, h, batch, o, ws, infos, stream);
+  if (rc) return rc;
+  if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return RCLUPP_ERR_HIP;
+  (void)hipEventElapsedTime(ms, e0, e1);
+  return RCLUPP_OK;
+}
+
 int batched_grouped(int alg, const rclupp_problem* h, int batch, const rclupp_opts* o, void* ws_v, size_t ws_bytes,
                     rclupp_info* d_info, hipStream_t stream) {
   (void)alg;
   char* ws = (char*)ws_v;
   const int flags = o ? o->batch_flags : 0;
-  int tpw = kDefaultTpw;
+  BatchTune tune = kDefaultTune;
   const uint64_t skey = shape_key(h, batch, o);
   std::lock_guard<std::mutex> lk(g_batch_mu);
   reap_retired();
   if (flags & RCLUPP_BATCH_AUTOTUNE) {
-    auto it = g_tuned.find(skey);
+    tune_cache_load();
+    const uint64_t tkey = arch_key(skey);
+    auto it = g_tuned.find(tkey);
     if (it != g_tuned.end()) {
-      tpw = it->second;
+      tune = it->second;
     } else {
-      // time every candidate once (each run is a complete batch; this waits
-      // for the stream, as the header states) and keep the fastest
-      float best = 0.f;
-      int best_tpw = kDefaultTpw;
+      // coordinate search, one complete batch per candidate (this waits for
+      // the stream, as the header states): the tall passes' tiles per
+      // workgroup with the default sketch, then the sketch's with that choice
       hipEvent_t e0, e1;
       if (hipEventCreate(&e0) != hipSuccess) return RCLUPP_ERR_HIP;
       if (hipEventCreate(&e1) != hipSuccess) {
@@ -1086,30 +1215,36 @@ int batched_grouped(int alg, const rclupp_problem* h, int batch, const rclupp_op
         return RCLUPP_ERR_HIP;
       }
       int rc = RCLUPP_OK;
-      for (int cand : kTuneTpw) {
-        BatchPlan P = make_batch_plan(h, batch, o, cand);
-        if (P.total > ws_bytes) continue;
-        rclupp_info* infos = d_info ? d_info : (rclupp_info*)(ws + P.info_off);
-        if (hipEventRecord(e0, stream) != hipSuccess) rc = RCLUPP_ERR_HIP;
-        if (rc == RCLUPP_OK) rc = batch_run_once(P, h, batch, o, ws, infos, stream);
-        if (rc == RCLUPP_OK && hipEventRecord(e1, stream) != hipSuccess) rc = RCLUPP_ERR_HIP;
-        if (rc == RCLUPP_OK && hipEventSynchronize(e1) != hipSuccess) rc = RCLUPP_ERR_HIP;
-        if (rc) break;
+      float best = -1.f;
+      BatchTune best_t = kDefaultTune;
+      for (int cand : kTuneTall) {
         float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (best == 0.f || ms < best) {
+        const BatchTune t{cand, kDefaultTune.sk_tpw};
+        if ((rc = time_candidate(h, batch, o, ws, ws_bytes, d_info, stream, t, e0, e1, &ms))) break;
+        if (ms >= 0.f && (best < 0.f || ms < best)) {
           best = ms;
-          best_tpw = cand;
+          best_t = t;
+        }
+      }
+      for (int cand : kTuneSketch) {
+        if (rc || cand == best_t.sk_tpw) continue;
+        float ms = 0.f;
+        const BatchTune t{best_t.tall_tpw, cand};
+        if ((rc = time_candidate(h, batch, o, ws, ws_bytes, d_info, stream, t, e0, e1, &ms))) break;
+        if (ms >= 0.f && (best < 0.f || ms < best)) {
+          best = ms;
+          best_t = t;
         }
       }
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
       if (rc) return rc;
-      tpw = best_tpw;
-      g_tuned[skey] = tpw;
+      tune = best_t;
+      g_tuned[tkey] = tune;
+      tune_cache_store(tkey, tune);
     }
   }
-  BatchPlan P = make_batch_plan(h, batch, o, tpw);
+  BatchPlan P = make_batch_plan(h, batch, o, tune);
   if (P.total > ws_bytes) return RCLUPP_ERR_WORKSPACE;
   rclupp_info* infos = d_info ? d_info : (rclupp_info*)(ws + P.info_off);
   if (!(flags & RCLUPP_BATCH_GRAPH)) return batch_run_once(P, h, batch, o, ws, infos, stream);
@@ -1117,7 +1252,7 @@ int batched_grouped(int alg, const rclupp_problem* h, int batch, const rclupp_op
   uint64_t key = fnv1a(skey, h, sizeof(rclupp_problem) * (size_t)batch);
   const void* ptrs[3] = {ws_v, (const void*)d_info, nullptr};
   key = fnv1a(key, ptrs, sizeof(ptrs));
-  key = fnv1a(key, &tpw, sizeof(tpw));
+  key = fnv1a(key, &tune, sizeof(tune));
   auto it = g_graphs.find(key);
   if (it == g_graphs.end()) {
     int dev = 0;
@@ -1206,7 +1341,18 @@ int release_all() {
     for (auto& kv : g_capture_stream)
       if (kv.second && hipStreamDestroy(kv.second) != hipSuccess) rc = RCLUPP_ERR_HIP;
     g_capture_stream.clear();
+    for (auto& kv : g_side) {
+      SideStreams& ss = kv.second;
+      for (int i = 0; i < kSideStreams; ++i) {
+        if (ss.s[i] && hipStreamSynchronize(ss.s[i]) != hipSuccess) rc = RCLUPP_ERR_HIP;
+        if (ss.s[i] && hipStreamDestroy(ss.s[i]) != hipSuccess) rc = RCLUPP_ERR_HIP;
+        if (ss.join[i]) (void)hipEventDestroy(ss.join[i]);
+      }
+      if (ss.fork) (void)hipEventDestroy(ss.fork);
+    }
+    g_side.clear();
     g_tuned.clear();
+    g_tune_file_read = false;
   }
   {
     std::lock_guard<std::mutex> lk(g_trace_mu);
@@ -1249,10 +1395,11 @@ int rclupp_batched_workspace_size(int alg, const rclupp_problem* h_probs, int ba
   }
   if (batch_groupable(alg, h_probs, batch, opts)) {
     // the largest plan among the tuning candidates (fewest rows per workgroup)
-    for (int cand : kTuneTpw) {
-      const size_t t = make_batch_plan(h_probs, batch, opts, cand).total;
-      if (t > mx) mx = t;
-    }
+    for (int ct : kTuneTall)
+      for (int cs : kTuneSketch) {
+        const size_t t = make_batch_plan(h_probs, batch, opts, BatchTune{ct, cs}).total;
+        if (t > mx) mx = t;
+      }
   }
   *bytes = mx > 0 ? mx : kAlign;
   return RCLUPP_OK;

@@ -288,6 +288,55 @@ def test_batched_autotune_parity():
             assert m["orth"] <= TOL_ORTH and m["rel_res"] <= TOL_RES
 
 
+def test_batched_tuning_cache_persists(tmp_path, monkeypatch):
+    # the tuned knobs go to the cache file (one line per batch shape) and are
+    # read back after the in-memory table is dropped: the second run takes the
+    # same plan (equal bits) without tuning again (no second line)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("RCLUPP_TUNE_CACHE", str(cache))
+    # an earlier test may have tuned this batch shape: start from an empty table
+    _nat().release()
+    shapes = [(20000, 16), (15000, 32), (9000, 64), (12000, 128)]
+    xs, _ = _batch_inputs(shapes, seed0=550)
+    Xs = [to_dev(x) for x in xs]
+    b = _lib().Batch(Xs, alg="rclupp", autotune=True)
+    q0, r0, i0 = b.run()
+    torch.cuda.synchronize()
+    lines = cache.read_text().split("\n")
+    lines = [ln for ln in lines if ln.strip()]
+    assert len(lines) == 1
+    key, tall, sk = lines[0].split()
+    assert int(tall) in (4, 8, 16) and int(sk) in (16, 32, 64) and len(key) == 16
+    ref_q = [to_host(q) for q in q0]
+    _nat().release()  # drops the in-memory table (and the cached graphs)
+    q1, r1, i1 = b.run()
+    torch.cuda.synchronize()
+    for k in range(len(xs)):
+        np.testing.assert_array_equal(to_host(q1[k]), ref_q[k])
+    assert len([ln for ln in cache.read_text().split("\n") if ln.strip()]) == 1
+
+
+def test_batched_parity_sample_vs_oracle():
+    # problems drawn from the 512-problem manifest (m cut to a tenth), every
+    # (n, s) group present, each against the oracle at the parity bar
+    from gen import batch_manifest
+    man = [p for p in batch_manifest(0, 512)]
+    picked = []
+    for n in (16, 32, 64, 128):
+        picked += [p for p in man if p["n"] == n][:3]
+    xs = [make_svd(p["m"] // 10, p["n"], p["kappa"], seed=p["input_seed"]) for p in picked]
+    Xs = [to_dev(x) for x in xs]
+    Qs, Rs, info = _lib().qr_batched(Xs, alg="rclupp", seeds=[p["seed"] for p in picked], graph=True)
+    torch.cuda.synchronize()
+    for i, (x, p) in enumerate(zip(xs, picked)):
+        class _R:
+            pass
+        r = _R()
+        r.Q, r.R = Qs[i], Rs[i]
+        r.info_host = lambda i=i: info[i].cpu().tolist()
+        method_parity(x, "rclupp", 2 * p["n"], p["seed"], p["kappa"], r)
+
+
 def test_batched_sequential_fallback_matches_single():
     # a problem beyond the grouped kernels (n = 200) sends the batch down the
     # single-problem pipeline: identical to separate calls
