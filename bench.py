@@ -299,7 +299,7 @@ def bench_mixed(lib, reps=3, x_headline=None):
     return out
 
 
-def bench_c2(lib, steps=10, with_cpu=True):
+def bench_c2(lib, steps=10, with_cpu=True, copy_calibration=False):
     """1,048,576 x 64, s = 2n, kappa = 1e15: FP64 RCLUPP, its roofline, the other
     methods, and the whole result against the oracle."""
     import numpy as np
@@ -313,6 +313,9 @@ def bench_c2(lib, steps=10, with_cpu=True):
     X = torch.empty((n, m), dtype=torch.float64, device="cuda").t()
     X.copy_(torch.from_numpy(x))
     run = Runner(lib, X, "rclupp", s, SEED)
+    if copy_calibration:
+        torch.mul(X, 1.0, out=run.Q)
+        torch.cuda.synchronize()
     ms = run.time(steps, warmup=2)
     stages = run.trace(steps)
     by, fl = tall_bytes(m, n), tall_flops(m, n, s)
@@ -478,7 +481,8 @@ def main():
 
     torch.cuda.set_device(0)
     if args.only:
-        legs = {"mixed": bench_mixed, "c2": lambda l: bench_c2(l, with_cpu=not args.no_cpu),
+        legs = {"mixed": bench_mixed,
+                "c2": lambda l: bench_c2(l, with_cpu=not args.no_cpu, copy_calibration=args.copy_calibration),
                 "batched": bench_batched, "krylov": bench_krylov}
         print(json.dumps({args.only: legs[args.only](lib)}), flush=True)
         return
