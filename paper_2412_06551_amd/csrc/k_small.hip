@@ -4,8 +4,8 @@
 //               R factor of M by Householder reflections (eq. eh, Q_s never
 //               formed), R_1 = D R_0 N with D = sign(diag(R_0 N)) (eq. ey)
 //               (Algorithm 2 steps 2-4; Algorithm 7 steps 3-4 with an external
-//               N; Algorithm 6 step 2 without the LU); several workgroups, one
-//               grid-wide barrier per column step;
+//               N; Algorithm 6 step 2 without the LU); several workgroups,
+//               each step published by its owner and awaited point to point;
 //   k_chol_blk : upper Cholesky of G (+ the shift of Algorithm 4) for n in
 //               (128, 256], blocked on one workgroup with MFMA trailing updates;
 //   k_trmm_pad : the product with an earlier factor (R_3 = R_2 R_1,
@@ -506,39 +506,65 @@ __global__ void k_pad(const double* __restrict__ R, int n, int np, double* __res
 // ---------------------------------------------------------------------------
 // Preconditioner for the shapes the register-resident kernel cannot hold
 // (s > 256 or n > 128), one cooperative launch of G workgroups: column j lives
-// in the LDS of workgroup j % G (cpw columns each). Every column step is one
-// grid-wide barrier: the owner of column k finds the pivot (LU) or forms the
-// reflector (Householder), publishes the multipliers or the reflector in a
-// double-buffered global vector, and after the barrier every workgroup applies
-// the step to its own columns. Rows are swapped physically in every column,
-// so no position bookkeeping is needed. The multipliers are true quotients
-// (so the LU factor equals the oracle's bit for bit, as k_precond_reg's
-// does); dlarfg's beta = -sign(alpha) hypot(alpha, |x|).
-// The barrier waits are bounded: a wait that does not end records
-// INFO_SYNC_TIMEOUT and the kernel exits.
+// in the LDS of workgroup j % G (cpw columns each). The LU steps and then the
+// Householder steps form one sequence; step k is published by the owner of
+// its column: it finds the pivot (LU) or forms the reflector (Householder),
+// writes the pivot or the scale and the multipliers or the reflector into
+// slot k mod CP_RING of a ring in global memory, and raises the step's flag.
+// Every other workgroup waits for that flag alone (no grid-wide barrier) and
+// applies the step to its own columns, in step order. The owner of column
+// k + 1 applies step k to that column first and publishes step k + 1 before
+// updating its other columns (look-ahead), so the next step's search overlaps
+// the other workgroups' updates. Each workgroup counts the steps it has
+// finished; an owner reuses a ring slot only when every workgroup is past the
+// step that used it last. Rows are swapped physically in every column (the
+// finished ones too, as getrf does), so no position bookkeeping is needed. The
+// multipliers are true quotients (so the LU factor equals the oracle's bit for
+// bit, as k_precond_reg's does); dlarfg's beta = -sign(alpha) hypot(alpha, |x|).
+// Every wait is bounded: a wait that does not end records INFO_SYNC_TIMEOUT
+// and the kernel exits. A failing owner (zero pivot or non-finite column)
+// records it, sets the failure word and raises its flag, so every workgroup
+// stops at that step.
 // ---------------------------------------------------------------------------
 constexpr int CP_THREADS = 256;
 constexpr int CP_WAVES = CP_THREADS / 64;
+constexpr int CP_RING = 8;  // ring slots of published steps
 
 struct CoopCtl {
-  unsigned count, gen;  // grid barrier: arrivals, generation
-  int fail;             // a step failed (set by its owner before the barrier)
+  unsigned count, gen;  // grid barrier (start and end of the kernel): arrivals, generation
+  int fail;             // a step failed (set by its owner before its flag)
   int mincol;           // lowest column with a non-finite entry (no LU)
-  int piv[2];           // pivot row of the step, double-buffered
-  double tau[2];        // reflector scale of the step, double-buffered
+  int piv[CP_RING];     // pivot row of the step in each slot
+  double tau[CP_RING];  // reflector scale of the step in each slot
+};
+
+// Global state of the flow: control block, step flags (2n), finished-step
+// counts (G), and the ring of published vectors (CP_RING x s doubles).
+struct CoopState {
+  CoopCtl* ctl;
+  int* flag;
+  int* done;
+  double* ring;
 };
 
 size_t coop_ctl_bytes() { return (sizeof(CoopCtl) + 255) / 256 * 256; }
+size_t coop_state_bytes(int64_t s, int64_t n, int G) {
+  return coop_ctl_bytes() + ((size_t)(2 * n + G) * sizeof(int) + 255) / 256 * 256 +
+         (size_t)CP_RING * s * sizeof(double);
+}
 
-__global__ void k_coop_ctl_init(CoopCtl* c) {
-  if (threadIdx.x == 0) {
+__global__ void k_coop_ctl_init(CoopCtl* c, int* words, int nwords) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     c->count = 0;
     c->gen = 0;
     c->fail = 0;
     c->mincol = INT_MAX;
-    c->piv[0] = c->piv[1] = 0;
-    c->tau[0] = c->tau[1] = 0.0;
+    for (int r = 0; r < CP_RING; ++r) {
+      c->piv[r] = 0;
+      c->tau[r] = 0.0;
+    }
   }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += gridDim.x * blockDim.x) words[i] = 0;
 }
 
 // All G workgroups arrive; false if this workgroup's bounded wait ran out.
@@ -581,6 +607,63 @@ __device__ __forceinline__ double cp_load_d(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Publish step k: every wave's stores of the step are in this CU's L2 after
+// the workgroup barrier; thread 0's agent-scope release writes them back
+// before the flag rises (the same pattern as coop_barrier's arrival).
+__device__ void cp_publish(int* flag, int k) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_store(flag + k, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Wait for step k's flag (thread 0, bounded), then acquire. False on time-out.
+__device__ bool cp_wait_flag(const int* flag, int k) {
+  __shared__ int timed_out;
+  if (threadIdx.x == 0) {
+    timed_out = 0;
+    unsigned spins = 0;
+    while (cp_load_i(flag + k) == 0) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1u << 24)) {
+        timed_out = 1;
+        break;
+      }
+    }
+    __threadfence();
+  }
+  __syncthreads();
+  return timed_out == 0;
+}
+
+// Before an owner overwrites the ring slot of step k: wait until every
+// workgroup has finished step k - CP_RING (wave 0 reads the G counts). False
+// on time-out.
+__device__ bool cp_wait_slot(const int* done, int G, int k) {
+  __shared__ int timed_out;
+  const int need = k - CP_RING + 1;
+  if (need > 0 && threadIdx.x < 64) {
+    unsigned spins = 0;
+    int to = 0;
+    for (;;) {
+      int ok = 1;
+      for (int w = threadIdx.x; w < G; w += 64) ok &= cp_load_i(done + w) >= need;
+      if (__all(ok)) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1u << 24)) {
+        to = 1;
+        break;
+      }
+    }
+    if (threadIdx.x == 0) timed_out = to;
+  } else if (threadIdx.x == 0) {
+    timed_out = 0;
+  }
+  __syncthreads();
+  return timed_out == 0;
+}
+
 // Sum over the workgroup of NV values per thread (each thread gets the sums).
 template <int NV, typename T>
 __device__ void cp_sum(T (&v)[NV], T* sh /* [CP_WAVES][NV] */) {
@@ -607,20 +690,25 @@ template <typename T>
 __global__ __launch_bounds__(CP_THREADS) void k_precond_coop(const double* __restrict__ Y, int s, int n, int lu,
                                                              const double* __restrict__ Nin, int ldn, double* R1pad,
                                                              int np, double* R1out, int32_t* perm_out, double* Mout,
-                                                             double* vbuf, double* Ng, double* R0g, int32_t* permg,
-                                                             CoopCtl* ctl, int cpw, int32_t* info, int32_t stage_qr) {
+                                                             double* Ng, double* R0g, int32_t* permg, CoopState st,
+                                                             int cpw, int32_t* info, int32_t stage_qr) {
   extern __shared__ __align__(16) unsigned char cp_smem[];
   T* cols = (T*)cp_smem;  // local column q (global g + q G) at q*s
   __shared__ T shr[CP_WAVES * CP_MAXC];
   __shared__ double amv[CP_WAVES];
   __shared__ int ami[CP_WAVES], amb[CP_WAVES];
+  __shared__ int my_piv;
+  __shared__ T my_tau;
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const unsigned nb = (unsigned)G;
+  CoopCtl* ctl = st.ctl;
   (void)cpw;  // the LDS holds cpw columns; G = ceil(n / cpw) keeps every workgroup's count within it
   // (no workgroup writes info before the first barrier, so all read the same)
   if (info_failed(info)) return;
   auto col = [&](int q) { return cols + (size_t)q * s; };
+  auto slot = [&](int k) { return st.ring + (size_t)(k % CP_RING) * s; };
   const int nloc = (n - g + G - 1) / G;  // columns of this workgroup
+  const int lusteps = lu ? n : 0;        // QR step k (column k) is step lusteps + k
 #pragma unroll
   for (int q = 0; q < CP_MAXC; ++q) {
     if (q >= nloc) break;
@@ -632,88 +720,141 @@ __global__ __launch_bounds__(CP_THREADS) void k_precond_coop(const double* __res
   if (!coop_barrier(ctl, nb)) goto timeout;
 
   if (lu) {
-    for (int k = 0; k < n; ++k) {
-      const int buf = k & 1, owner = k % G;
-      if (g == owner) {
-        T* c = col(k / G);
-        double best = -1.0;
-        int idx = INT_MAX, bad = 0;
-        for (int i = k + tid; i < s; i += CP_THREADS) {
-          const double a = (double)c[i];
-          if (!is_finite(a)) bad = 1;
-          const double v = fabs(a);
-          if (v > best) {
-            best = v;
-            idx = i;
-          }
-        }
-        // workgroup argmax, first row on ties
-        const int lane = tid & 63, wave = tid >> 6;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          const double ov = __shfl_xor(best, off);
-          const int oi = __shfl_xor(idx, off);
-          const int ob = __shfl_xor(bad, off);
-          if (ov > best || (ov == best && oi < idx)) {
-            best = ov;
-            idx = oi;
-          }
-          bad |= ob;
-        }
-        if (lane == 0) {
-          amv[wave] = best;
-          ami[wave] = idx;
-          amb[wave] = bad;
-        }
-        __syncthreads();
-        best = amv[0];
-        idx = ami[0];
-        bad = amb[0];
-        for (int w = 1; w < CP_WAVES; ++w) {
-          if (amv[w] > best || (amv[w] == best && ami[w] < idx)) {
-            best = amv[w];
-            idx = ami[w];
-          }
-          bad |= amb[w];
-        }
-        if (bad || !(best > 0.0)) {
-          if (tid == 0) {
-            info_set(info, bad ? INFO_NONFINITE : INFO_LU_ZERO_PIVOT, STAGE_LU, k + 1);
-            ctl->fail = 1;
-          }
-        } else {
-          const int p = idx;
-          const T piv = c[p];
-          const T ck = c[k];
-          __syncthreads();
-          if (tid == 0) {
-            c[k] = piv;
-            c[p] = ck;
-            const int32_t t = permg[k];
-            permg[k] = permg[p];
-            permg[p] = t;
-            ctl->piv[buf] = p;
-          }
-          __syncthreads();
-          for (int i = k + 1 + tid; i < s; i += CP_THREADS) {
-            const T l = c[i] / piv;
-            c[i] = l;
-            vbuf[buf * s + i] = (double)l;
-          }
+    // owner of column k: pivot search, swap, multipliers, publish (false: failed
+    // or timed out, and the workgroup stops)
+    auto lu_owner = [&](int k) -> int {
+      T* c = col(k / G);
+      if (!cp_wait_slot(st.done, G, k)) return -1;
+      double best = -1.0;
+      int idx = INT_MAX, bad = 0;
+      for (int i = k + tid; i < s; i += CP_THREADS) {
+        const double a = (double)c[i];
+        if (!is_finite(a)) bad = 1;
+        const double v = fabs(a);
+        if (v > best) {
+          best = v;
+          idx = i;
         }
       }
-      if (!coop_barrier(ctl, nb)) goto timeout;
-      if (cp_load_i(&ctl->fail)) return;
-      const int p = cp_load_i(&ctl->piv[buf]);
-      // read phase: the pivot row's entries (row k after the swap) and row k's
-      // old entries (row p after the swap), in every column but k (the
-      // multipliers of the earlier columns trade rows too, as in getrf)
+      // workgroup argmax, first row on ties
+      const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(best, off);
+        const int oi = __shfl_xor(idx, off);
+        const int ob = __shfl_xor(bad, off);
+        if (ov > best || (ov == best && oi < idx)) {
+          best = ov;
+          idx = oi;
+        }
+        bad |= ob;
+      }
+      if (lane == 0) {
+        amv[wave] = best;
+        ami[wave] = idx;
+        amb[wave] = bad;
+      }
+      __syncthreads();
+      best = amv[0];
+      idx = ami[0];
+      bad = amb[0];
+      for (int w = 1; w < CP_WAVES; ++w) {
+        if (amv[w] > best || (amv[w] == best && ami[w] < idx)) {
+          best = amv[w];
+          idx = ami[w];
+        }
+        bad |= amb[w];
+      }
+      if (bad || !(best > 0.0)) {
+        if (tid == 0) {
+          info_set(info, bad ? INFO_NONFINITE : INFO_LU_ZERO_PIVOT, STAGE_LU, k + 1);
+          __hip_atomic_store(&ctl->fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        cp_publish(st.flag, k);
+        return 0;
+      }
+      const int p = idx;
+      const T piv = c[p];
+      const T ck = c[k];
+      __syncthreads();
+      if (tid == 0) {
+        c[k] = piv;
+        c[p] = ck;
+        const int32_t t = permg[k];
+        permg[k] = permg[p];
+        permg[p] = t;
+        ctl->piv[k % CP_RING] = p;
+        my_piv = p;
+      }
+      __syncthreads();
+      double* v = slot(k);
+      for (int i = k + 1 + tid; i < s; i += CP_THREADS) {
+        const T l = c[i] / piv;
+        c[i] = l;
+        v[i] = (double)l;
+      }
+      cp_publish(st.flag, k);
+      return 1;
+    };
+    // step k (pivot row p, multipliers in its slot) on local column q (j > k)
+    // or, for a finished column (j < k), the row swap alone; the reads of the
+    // two rows happen before the caller's barrier
+    auto lu_apply = [&](int k, int p, int q, T akj, T okk) {
+      const int j = g + q * G;
+      T* c = col(q);
+      if (j < k) {
+        if (tid == 0 && p != k) {
+          c[k] = akj;
+          c[p] = okk;
+        }
+        return;
+      }
+      const double* v = slot(k);
+      for (int i = k + tid; i < s; i += CP_THREADS) {
+        if (i == k) {
+          c[k] = akj;
+        } else {
+          const T l = (T)v[i];
+          const T a = (i == p) ? okk : c[i];
+          c[i] = a - l * akj;
+        }
+      }
+    };
+
+    if (g == 0) {
+      const int r = lu_owner(0);
+      if (r < 0) goto timeout;
+      if (r == 0) return;
+    }
+    for (int k = 0; k < n; ++k) {
+      const int owner = k % G;
+      int p;
+      if (owner == g) {
+        p = my_piv;
+      } else {
+        if (!cp_wait_flag(st.flag, k)) goto timeout;
+        if (cp_load_i(&ctl->fail)) return;
+        p = cp_load_i(&ctl->piv[k % CP_RING]);
+      }
+      // look-ahead: column k + 1 first, then its step
+      const int qa = (k + 1 < n && (k + 1) % G == g) ? (k + 1) / G : -1;
+      if (qa >= 0) {
+        T* c = col(qa);
+        const T akj = c[p], okk = c[k];
+        __syncthreads();
+        lu_apply(k, p, qa, akj, okk);
+        __syncthreads();
+        const int r = lu_owner(k + 1);
+        if (r < 0) goto timeout;
+        if (r == 0) return;
+      }
+      // the other local columns (all but column k itself and the look-ahead one)
       T akj[CP_MAXC], okk[CP_MAXC];
 #pragma unroll
       for (int q = 0; q < CP_MAXC; ++q) {
         if (q >= nloc) break;
         const int j = g + q * G;
-        if (j != k) {
+        if (j != k && q != qa) {
           akj[q] = col(q)[p];
           okk[q] = col(q)[k];
         }
@@ -723,26 +864,11 @@ __global__ __launch_bounds__(CP_THREADS) void k_precond_coop(const double* __res
       for (int q = 0; q < CP_MAXC; ++q) {
         if (q >= nloc) break;
         const int j = g + q * G;
-        if (j == k) continue;
-        T* c = col(q);
-        if (j < k) {  // finished column: the swap only
-          if (tid == 0 && p != k) {
-            c[k] = akj[q];
-            c[p] = okk[q];
-          }
-          continue;
-        }
-        for (int i = k + tid; i < s; i += CP_THREADS) {
-          if (i == k) {
-            c[k] = akj[q];
-          } else {
-            const T l = (T)vbuf[buf * s + i];
-            const T a = (i == p) ? okk[q] : c[i];
-            c[i] = a - l * akj[q];
-          }
-        }
+        if (j == k || q == qa) continue;
+        lu_apply(k, p, q, akj[q], okk[q]);
       }
       __syncthreads();
+      if (tid == 0) __hip_atomic_store(st.done + g, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     // N = the upper n x n part; M = unit lower trapezoid
 #pragma unroll
@@ -757,6 +883,7 @@ __global__ __launch_bounds__(CP_THREADS) void k_precond_coop(const double* __res
       if (Mout)
         for (int i = tid; i < s; i += CP_THREADS) Mout[i + (int64_t)j * s] = (double)c[i];
     }
+    __syncthreads();
   } else {
     // M = Y; N external (upper part) or the identity; non-finite entries of M
     // are reported before the reflections (lowest column)
@@ -779,11 +906,14 @@ __global__ __launch_bounds__(CP_THREADS) void k_precond_coop(const double* __res
     }
   }
 
-  // Householder reflections (LAPACK dlarfg convention)
-  for (int k = 0; k < n; ++k) {
-    const int buf = k & 1, owner = k % G;
-    if (g == owner) {
+  {
+    // Householder reflections (LAPACK dlarfg convention); column k is step
+    // lusteps + k. The owner forms the reflector of its column and publishes
+    // it with tau (tau = 0: the identity).
+    auto qr_owner = [&](int k) -> bool {
+      const int step = lusteps + k;
       T* c = col(k / G);
+      if (!cp_wait_slot(st.done, G, step)) return false;
       T part[1] = {T(0)};
       for (int i = k + 1 + tid; i < s; i += CP_THREADS) part[0] += c[i] * c[i];
       cp_sum<1>(part, shr);
@@ -795,42 +925,73 @@ __global__ __launch_bounds__(CP_THREADS) void k_precond_coop(const double* __res
         tau = (beta - al) / beta;
         scal = T(1) / (al - beta);
       }
+      double* v = slot(step);
       if (tau != T(0)) {
         for (int i = k + 1 + tid; i < s; i += CP_THREADS) {
-          const T v = c[i] * scal;
-          c[i] = v;
-          vbuf[buf * s + i] = (double)v;
+          const T vi = c[i] * scal;
+          c[i] = vi;
+          v[i] = (double)vi;
         }
       }
       __syncthreads();
       if (tid == 0) {
         if (tau != T(0)) c[k] = beta;
-        vbuf[buf * s + k] = 1.0;
-        ctl->tau[buf] = (double)tau;
+        v[k] = 1.0;
+        ctl->tau[step % CP_RING] = (double)tau;
+        my_tau = tau;
       }
-    }
-    if (!coop_barrier(ctl, nb)) goto timeout;
-    const T tau = (T)cp_load_d(&ctl->tau[buf]);
-    if (tau == T(0)) continue;
-    // w_j = v^T M(:, j) for the local columns j > k (one reduction for all), then M(:, j) -= tau w_j v
-    T w[CP_MAXC];
-    for (int q = 0; q < CP_MAXC; ++q) w[q] = T(0);
-    for (int i = k + tid; i < s; i += CP_THREADS) {
-      const T v = (T)vbuf[buf * s + i];
+      cp_publish(st.flag, step);
+      return true;
+    };
+    if (g == 0 && !qr_owner(0)) goto timeout;
+    for (int k = 0; k < n; ++k) {
+      const int step = lusteps + k, owner = k % G;
+      T tau;
+      if (owner == g) {
+        tau = my_tau;
+      } else {
+        if (!cp_wait_flag(st.flag, step)) goto timeout;
+        tau = (T)cp_load_d(&ctl->tau[step % CP_RING]);
+      }
+      const double* v = slot(step);
+      const int qa = (k + 1 < n && (k + 1) % G == g) ? (k + 1) / G : -1;
+      if (qa >= 0) {
+        // look-ahead: column k + 1 takes reflection k, then forms its own
+        if (tau != T(0)) {
+          T* c = col(qa);
+          T w[1] = {T(0)};
+          for (int i = k + tid; i < s; i += CP_THREADS) w[0] += (T)v[i] * c[i];
+          cp_sum<1>(w, shr);
+          const T tw = tau * w[0];
+          for (int i = k + tid; i < s; i += CP_THREADS) c[i] -= tw * (T)v[i];
+          __syncthreads();
+        }
+        if (!qr_owner(k + 1)) goto timeout;
+      }
+      if (tau != T(0)) {
+        // w_j = v^T M(:, j) for the other local columns j > k (one reduction
+        // for all), then M(:, j) -= tau w_j v
+        T w[CP_MAXC];
+        for (int q = 0; q < CP_MAXC; ++q) w[q] = T(0);
+        for (int i = k + tid; i < s; i += CP_THREADS) {
+          const T vi = (T)v[i];
 #pragma unroll
-      for (int q = 0; q < CP_MAXC; ++q)
-        if (q < nloc && g + q * G > k) w[q] += v * col(q)[i];
-    }
-    cp_sum<CP_MAXC>(w, shr);
+          for (int q = 0; q < CP_MAXC; ++q)
+            if (q < nloc && q != qa && g + q * G > k) w[q] += vi * col(q)[i];
+        }
+        cp_sum<CP_MAXC>(w, shr);
 #pragma unroll
-    for (int q = 0; q < CP_MAXC; ++q) {
-      if (q >= nloc) break;
-      if (g + q * G <= k) continue;
-      T* c = col(q);
-      const T tw = tau * w[q];
-      for (int i = k + tid; i < s; i += CP_THREADS) c[i] -= tw * (T)vbuf[buf * s + i];
+        for (int q = 0; q < CP_MAXC; ++q) {
+          if (q >= nloc) break;
+          if (q == qa || g + q * G <= k) continue;
+          T* c = col(q);
+          const T tw = tau * w[q];
+          for (int i = k + tid; i < s; i += CP_THREADS) c[i] -= tw * (T)v[i];
+        }
+        __syncthreads();
+      }
+      if (tid == 0) __hip_atomic_store(st.done + g, step + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();
   }
 
   // R_0 (rows < n, upper), then R_1 = D R_0 N for this workgroup's columns
@@ -897,15 +1058,28 @@ timeout:
 // Launchers. n <= 64 (and s <= 256 for the preconditioner) go to the
 // register-resident kernels of k_dense.hip.
 // ---------------------------------------------------------------------------
+// Workgroups of the multi-workgroup preconditioner: columns per workgroup as
+// many as 60 KB of LDS holds, at most CP_MAXC.
+static int coop_cpw(int64_t s, size_t elt) {
+  int cpw = (int)(61440 / ((size_t)s * elt));
+  return cpw > CP_MAXC ? CP_MAXC : cpw;
+}
+
 size_t precond_scratch_bytes(int64_t s, int64_t n) {
   // generic kernel: A (s*n) + wv (n) + N (n*n) + R (n*n) in doubles, + perm
-  // (s ints), aligned; the multi-workgroup kernel uses 2 s + 2 n^2 doubles, s
-  // ints and its control block of it; the register-resident kernel for
-  // n > 64: its two tables
+  // (s ints), aligned; the multi-workgroup kernel uses 2 n^2 doubles, s ints
+  // and its state (control block, step flags and counts, ring); the
+  // register-resident kernel for n > 64: its two tables
   size_t b = ((size_t)s * n + n + 2 * (size_t)n * n) * sizeof(double);
   b = (b + 255) / 256 * 256;
   b += ((size_t)s * sizeof(int32_t) + 255) / 256 * 256;
-  b += coop_ctl_bytes();
+  const int cpw = coop_cpw(s, sizeof(float));
+  const int gmax = (int)n;  // G <= n for any cpw >= 1
+  (void)cpw;
+  size_t flow = ((size_t)2 * n * n * sizeof(double) + 255) / 256 * 256;
+  flow += ((size_t)s * sizeof(int32_t) + 255) / 256 * 256;
+  flow += coop_state_bytes(s, n, gmax);
+  if (flow > b) b = flow;
   if (n > 64 && precond_reg_fits(s, n) && b < precond_reg_scratch_bytes()) b = precond_reg_scratch_bytes();
   return b;
 }
@@ -915,29 +1089,33 @@ static hipError_t launch_pc_coop(const double* Y, int64_t s, int64_t n, int lu, 
                                  double* R1pad, double* R1out, int32_t* perm, double* Mout, double* scratch,
                                  int32_t* info, int32_t stage_qr, hipStream_t st) {
   const int np = pad_cols(n);
-  // scratch: vbuf (2 s) | N (n n) | R_0 (n n) doubles | perm (s ints) | control block
-  double* vbuf = scratch;
-  double* Ng = vbuf + 2 * s;
-  double* R0g = Ng + (size_t)n * n;
-  size_t off = ((size_t)2 * s + 2 * (size_t)n * n) * sizeof(double);
-  off = (off + 255) / 256 * 256;
-  int32_t* permg = (int32_t*)((char*)scratch + off);
-  off += ((size_t)s * sizeof(int32_t) + 255) / 256 * 256;
-  CoopCtl* ctl = (CoopCtl*)((char*)scratch + off);
-  // columns per workgroup: as many as 60 KB of LDS holds, at most CP_MAXC
-  int cpw = (int)(61440 / ((size_t)s * sizeof(T)));
-  if (cpw > CP_MAXC) cpw = CP_MAXC;
+  const int cpw = coop_cpw(s, sizeof(T));
   if (cpw < 1) return hipErrorInvalidValue;
   const int G = (int)((n + cpw - 1) / cpw);
+  // scratch: N (n n) | R_0 (n n) doubles | perm (s ints) | control block |
+  // step flags (2n ints) and finished-step counts (G ints) | ring (CP_RING s doubles)
+  double* Ng = scratch;
+  double* R0g = Ng + (size_t)n * n;
+  size_t off = ((size_t)2 * n * n * sizeof(double) + 255) / 256 * 256;
+  int32_t* permg = (int32_t*)((char*)scratch + off);
+  off += ((size_t)s * sizeof(int32_t) + 255) / 256 * 256;
+  CoopState cs;
+  cs.ctl = (CoopCtl*)((char*)scratch + off);
+  off += coop_ctl_bytes();
+  cs.flag = (int*)((char*)scratch + off);
+  cs.done = cs.flag + 2 * n;
+  off += ((size_t)(2 * n + G) * sizeof(int) + 255) / 256 * 256;
+  cs.ring = (double*)((char*)scratch + off);
   const size_t lds = (size_t)cpw * s * sizeof(T);
-  hipLaunchKernelGGL(k_coop_ctl_init, dim3(1), dim3(64), 0, st, ctl);
+  const int nwords = (int)(2 * n + G);
+  hipLaunchKernelGGL(k_coop_ctl_init, dim3((nwords + 255) / 256), dim3(256), 0, st, cs.ctl, cs.flag, nwords);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   int si = (int)s, ni = (int)n, ldni = (int)ldn;
   void* args[] = {(void*)&Y, &si, &ni, &lu, (void*)&Nin, &ldni, &R1pad, (void*)&np, &R1out, &perm, &Mout,
-                  &vbuf, &Ng, &R0g, &permg, &ctl, &cpw, &info, &stage_qr};
+                  &Ng, &R0g, &permg, &cs, (void*)&cpw, &info, &stage_qr};
   // a cooperative launch: all G workgroups are resident together (the step
-  // barriers wait for every one of them)
+  // waits depend on every one of them)
   return hipLaunchCooperativeKernel((const void*)k_precond_coop<T>, dim3(G), dim3(CP_THREADS), args, (unsigned)lds, st);
 }
 
