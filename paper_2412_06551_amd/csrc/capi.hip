@@ -703,8 +703,13 @@ struct BatchTune {
   int tall_tpw;
   int sk_tpw;
 };
-constexpr int kTuneTall[] = {4, 8, 16};
-constexpr int kTuneSketch[] = {16, 32, 64};
+// (more tiles per workgroup: fewer per-workgroup partial sums to write and
+// add, each s_pad x n_pad or np x np doubles; fewer: more parallelism for the
+// short problems)
+constexpr int kTuneTall[] = {4, 8, 16, 32, 64};
+constexpr int kTuneSketch[] = {16, 32, 64, 128, 256, 512, 1024};
+constexpr int kNumTuneTall = (int)(sizeof(kTuneTall) / sizeof(kTuneTall[0]));
+constexpr int kNumTuneSketch = (int)(sizeof(kTuneSketch) / sizeof(kTuneSketch[0]));
 constexpr BatchTune kDefaultTune = {8, 32};
 
 struct BatchProbPlan {
@@ -1151,7 +1156,8 @@ void tune_cache_load() {
   };
   // only candidate values are taken (the workspace size assumes them)
   while (std::fscanf(f, "%llx %d %d", &key, &a, &b) == 3)
-    if (known(a, kTuneTall, 3) && known(b, kTuneSketch, 3)) g_tuned[(uint64_t)key] = BatchTune{a, b};
+    if (known(a, kTuneTall, kNumTuneTall) && known(b, kTuneSketch, kNumTuneSketch))
+      g_tuned[(uint64_t)key] = BatchTune{a, b};
   std::fclose(f);
 }
 

@@ -528,18 +528,17 @@ __global__ void k_pad(const double* __restrict__ R, int n, int np, double* __res
 // ---------------------------------------------------------------------------
 constexpr int CP_THREADS = 256;
 constexpr int CP_WAVES = CP_THREADS / 64;
-constexpr int CP_RING = 8;  // ring slots of published steps
+constexpr int CP_RING = 16;  // ring slots of published steps
 
 struct CoopCtl {
   unsigned count, gen;  // grid barrier (start and end of the kernel): arrivals, generation
-  int fail;             // a step failed (set by its owner before its flag)
   int mincol;           // lowest column with a non-finite entry (no LU)
-  int piv[CP_RING];     // pivot row of the step in each slot
-  double tau[CP_RING];  // reflector scale of the step in each slot
 };
 
 // Global state of the flow: control block, step flags (2n), finished-step
-// counts (G), and the ring of published vectors (CP_RING x s doubles).
+// counts (G), and the ring of published vectors (CP_RING slots of s + 1
+// doubles: the multipliers or the reflector, then tau). A step's flag carries
+// its result: LU step, pivot row + 1 (-1: the step failed); Householder step, 1.
 struct CoopState {
   CoopCtl* ctl;
   int* flag;
@@ -550,19 +549,14 @@ struct CoopState {
 size_t coop_ctl_bytes() { return (sizeof(CoopCtl) + 255) / 256 * 256; }
 size_t coop_state_bytes(int64_t s, int64_t n, int G) {
   return coop_ctl_bytes() + ((size_t)(2 * n + G) * sizeof(int) + 255) / 256 * 256 +
-         (size_t)CP_RING * s * sizeof(double);
+         (size_t)CP_RING * (s + 1) * sizeof(double);
 }
 
 __global__ void k_coop_ctl_init(CoopCtl* c, int* words, int nwords) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     c->count = 0;
     c->gen = 0;
-    c->fail = 0;
     c->mincol = INT_MAX;
-    for (int r = 0; r < CP_RING; ++r) {
-      c->piv[r] = 0;
-      c->tau[r] = 0.0;
-    }
   }
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += gridDim.x * blockDim.x) words[i] = 0;
 }
@@ -607,49 +601,57 @@ __device__ __forceinline__ double cp_load_d(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Publish step k: every wave's stores of the step are in this CU's L2 after
-// the workgroup barrier; thread 0's agent-scope release writes them back
-// before the flag rises (the same pattern as coop_barrier's arrival).
-__device__ void cp_publish(int* flag, int k) {
+// Publish step k with its flag value: every wave's stores of the step are in
+// this CU's L2 after the workgroup barrier; thread 0's agent-scope release
+// writes them back before the flag rises (the same pattern as coop_barrier's
+// arrival).
+__device__ void cp_publish(int* flag, int k, int value) {
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
-    __hip_atomic_store(flag + k, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(flag + k, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
-// Wait for step k's flag (thread 0, bounded), then acquire. False on time-out.
-__device__ bool cp_wait_flag(const int* flag, int k) {
-  __shared__ int timed_out;
+// Wait for step k's flag (thread 0, bounded), then acquire; returns the flag
+// value to every thread (0 on time-out).
+__device__ int cp_wait_flag(const int* flag, int k) {
+  __shared__ int value;
   if (threadIdx.x == 0) {
-    timed_out = 0;
     unsigned spins = 0;
-    while (cp_load_i(flag + k) == 0) {
+    int v;
+    while ((v = cp_load_i(flag + k)) == 0) {
       __builtin_amdgcn_s_sleep(1);
-      if (++spins > (1u << 24)) {
-        timed_out = 1;
-        break;
-      }
+      if (++spins > (1u << 24)) break;
     }
     __threadfence();
+    value = v;
   }
   __syncthreads();
-  return timed_out == 0;
+  return value;
 }
 
 // Before an owner overwrites the ring slot of step k: wait until every
-// workgroup has finished step k - CP_RING (wave 0 reads the G counts). False
-// on time-out.
-__device__ bool cp_wait_slot(const int* done, int G, int k) {
+// workgroup has finished step k - CP_RING (wave 0 reads the G counts). The
+// smallest count seen is kept in *seen (LDS), so the counts are read again
+// only when that bound no longer suffices (about once per CP_RING steps).
+// False on time-out.
+__device__ bool cp_wait_slot(const int* done, int G, int k, int* seen) {
   __shared__ int timed_out;
   const int need = k - CP_RING + 1;
-  if (need > 0 && threadIdx.x < 64) {
+  if (need <= *seen) return true;  // (uniform: *seen changes only below, before a barrier)
+  if (threadIdx.x < 64) {
     unsigned spins = 0;
     int to = 0;
     for (;;) {
-      int ok = 1;
-      for (int w = threadIdx.x; w < G; w += 64) ok &= cp_load_i(done + w) >= need;
-      if (__all(ok)) break;
+      int lo = INT_MAX;
+      for (int w = threadIdx.x; w < G; w += 64) lo = min(lo, cp_load_i(done + w));
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) lo = min(lo, __shfl_xor(lo, off));
+      if (lo >= need) {
+        if (threadIdx.x == 0) *seen = lo;
+        break;
+      }
       __builtin_amdgcn_s_sleep(1);
       if (++spins > (1u << 24)) {
         to = 1;
@@ -657,8 +659,6 @@ __device__ bool cp_wait_slot(const int* done, int G, int k) {
       }
     }
     if (threadIdx.x == 0) timed_out = to;
-  } else if (threadIdx.x == 0) {
-    timed_out = 0;
   }
   __syncthreads();
   return timed_out == 0;
@@ -697,7 +697,7 @@ __global__ __launch_bounds__(CP_THREADS) void k_precond_coop(const double* __res
   __shared__ T shr[CP_WAVES * CP_MAXC];
   __shared__ double amv[CP_WAVES];
   __shared__ int ami[CP_WAVES], amb[CP_WAVES];
-  __shared__ int my_piv;
+  __shared__ int my_piv, seen_done;
   __shared__ T my_tau;
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const unsigned nb = (unsigned)G;
@@ -706,7 +706,7 @@ __global__ __launch_bounds__(CP_THREADS) void k_precond_coop(const double* __res
   // (no workgroup writes info before the first barrier, so all read the same)
   if (info_failed(info)) return;
   auto col = [&](int q) { return cols + (size_t)q * s; };
-  auto slot = [&](int k) { return st.ring + (size_t)(k % CP_RING) * s; };
+  auto slot = [&](int k) { return st.ring + (size_t)(k % CP_RING) * (s + 1); };
   const int nloc = (n - g + G - 1) / G;  // columns of this workgroup
   const int lusteps = lu ? n : 0;        // QR step k (column k) is step lusteps + k
 #pragma unroll
@@ -717,6 +717,7 @@ __global__ __launch_bounds__(CP_THREADS) void k_precond_coop(const double* __res
   }
   if (g == 0)
     for (int i = tid; i < s; i += CP_THREADS) permg[i] = i;
+  if (tid == 0) seen_done = 0;
   if (!coop_barrier(ctl, nb)) goto timeout;
 
   if (lu) {
@@ -724,7 +725,7 @@ __global__ __launch_bounds__(CP_THREADS) void k_precond_coop(const double* __res
     // or timed out, and the workgroup stops)
     auto lu_owner = [&](int k) -> int {
       T* c = col(k / G);
-      if (!cp_wait_slot(st.done, G, k)) return -1;
+      if (!cp_wait_slot(st.done, G, k, &seen_done)) return -1;
       double best = -1.0;
       int idx = INT_MAX, bad = 0;
       for (int i = k + tid; i < s; i += CP_THREADS) {
@@ -766,11 +767,8 @@ __global__ __launch_bounds__(CP_THREADS) void k_precond_coop(const double* __res
         bad |= amb[w];
       }
       if (bad || !(best > 0.0)) {
-        if (tid == 0) {
-          info_set(info, bad ? INFO_NONFINITE : INFO_LU_ZERO_PIVOT, STAGE_LU, k + 1);
-          __hip_atomic_store(&ctl->fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        cp_publish(st.flag, k);
+        if (tid == 0) info_set(info, bad ? INFO_NONFINITE : INFO_LU_ZERO_PIVOT, STAGE_LU, k + 1);
+        cp_publish(st.flag, k, -1);
         return 0;
       }
       const int p = idx;
@@ -783,7 +781,6 @@ __global__ __launch_bounds__(CP_THREADS) void k_precond_coop(const double* __res
         const int32_t t = permg[k];
         permg[k] = permg[p];
         permg[p] = t;
-        ctl->piv[k % CP_RING] = p;
         my_piv = p;
       }
       __syncthreads();
@@ -793,7 +790,7 @@ __global__ __launch_bounds__(CP_THREADS) void k_precond_coop(const double* __res
         c[i] = l;
         v[i] = (double)l;
       }
-      cp_publish(st.flag, k);
+      cp_publish(st.flag, k, p + 1);
       return 1;
     };
     // step k (pivot row p, multipliers in its slot) on local column q (j > k)
@@ -832,9 +829,10 @@ __global__ __launch_bounds__(CP_THREADS) void k_precond_coop(const double* __res
       if (owner == g) {
         p = my_piv;
       } else {
-        if (!cp_wait_flag(st.flag, k)) goto timeout;
-        if (cp_load_i(&ctl->fail)) return;
-        p = cp_load_i(&ctl->piv[k % CP_RING]);
+        const int f = cp_wait_flag(st.flag, k);
+        if (f == 0) goto timeout;
+        if (f < 0) return;  // the owner failed and recorded it
+        p = f - 1;
       }
       // look-ahead: column k + 1 first, then its step
       const int qa = (k + 1 < n && (k + 1) % G == g) ? (k + 1) / G : -1;
@@ -913,7 +911,7 @@ __global__ __launch_bounds__(CP_THREADS) void k_precond_coop(const double* __res
     auto qr_owner = [&](int k) -> bool {
       const int step = lusteps + k;
       T* c = col(k / G);
-      if (!cp_wait_slot(st.done, G, step)) return false;
+      if (!cp_wait_slot(st.done, G, step, &seen_done)) return false;
       T part[1] = {T(0)};
       for (int i = k + 1 + tid; i < s; i += CP_THREADS) part[0] += c[i] * c[i];
       cp_sum<1>(part, shr);
@@ -937,10 +935,10 @@ __global__ __launch_bounds__(CP_THREADS) void k_precond_coop(const double* __res
       if (tid == 0) {
         if (tau != T(0)) c[k] = beta;
         v[k] = 1.0;
-        ctl->tau[step % CP_RING] = (double)tau;
+        v[s] = (double)tau;
         my_tau = tau;
       }
-      cp_publish(st.flag, step);
+      cp_publish(st.flag, step, 1);
       return true;
     };
     if (g == 0 && !qr_owner(0)) goto timeout;
@@ -950,8 +948,8 @@ __global__ __launch_bounds__(CP_THREADS) void k_precond_coop(const double* __res
       if (owner == g) {
         tau = my_tau;
       } else {
-        if (!cp_wait_flag(st.flag, step)) goto timeout;
-        tau = (T)cp_load_d(&ctl->tau[step % CP_RING]);
+        if (cp_wait_flag(st.flag, step) == 0) goto timeout;
+        tau = (T)slot(step)[s];
       }
       const double* v = slot(step);
       const int qa = (k + 1 < n && (k + 1) % G == g) ? (k + 1) / G : -1;
@@ -1093,7 +1091,7 @@ static hipError_t launch_pc_coop(const double* Y, int64_t s, int64_t n, int lu, 
   if (cpw < 1) return hipErrorInvalidValue;
   const int G = (int)((n + cpw - 1) / cpw);
   // scratch: N (n n) | R_0 (n n) doubles | perm (s ints) | control block |
-  // step flags (2n ints) and finished-step counts (G ints) | ring (CP_RING s doubles)
+  // step flags (2n ints) and finished-step counts (G ints) | ring (CP_RING (s + 1) doubles)
   double* Ng = scratch;
   double* R0g = Ng + (size_t)n * n;
   size_t off = ((size_t)2 * n * n * sizeof(double) + 255) / 256 * 256;
