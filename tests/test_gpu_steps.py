@@ -119,8 +119,11 @@ def test_sketch_leading_dimension():
 
 
 # ---------------------------------------------------------------- preconditioner
+# (300, 64), (512, 200), (300, 6), (1500, 9), (4096, 40): the multi-workgroup
+# kernel with 8, 25, 1, 2 and 40 workgroups (the last one also wraps the ring
+# of published steps several times)
 @pytest.mark.parametrize("s,n,seed", [(64, 32, 0), (128, 64, 1), (100, 50, 2), (16, 16, 3), (256, 128, 4),
-                                      (300, 64, 5), (512, 200, 6)])
+                                      (300, 64, 5), (512, 200, 6), (300, 6, 7), (1500, 9, 8), (4096, 40, 9)])
 @pytest.mark.parametrize("kappa", [1e2, 1e8])
 def test_precond_lu_householder(s, n, seed, kappa):
     x = make_svd(4 * s, n, kappa, seed=seed)
