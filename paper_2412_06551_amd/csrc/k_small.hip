@@ -715,8 +715,6 @@ __global__ __launch_bounds__(CP_THREADS) void k_precond_coop(const double* __res
     const int j = g + q * G;
     for (int i = tid; i < s; i += CP_THREADS) col(q)[i] = (T)Y[i + (int64_t)j * s];
   }
-  if (g == 0)
-    for (int i = tid; i < s; i += CP_THREADS) permg[i] = i;
   if (tid == 0) seen_done = 0;
   if (!coop_barrier(ctl, nb)) goto timeout;
 
@@ -778,15 +776,28 @@ __global__ __launch_bounds__(CP_THREADS) void k_precond_coop(const double* __res
       if (tid == 0) {
         c[k] = piv;
         c[p] = ck;
-        const int32_t t = permg[k];
-        permg[k] = permg[p];
-        permg[p] = t;
+        permg[k] = p;  // pivot history (the permutation is replayed at the end)
         my_piv = p;
       }
       __syncthreads();
+      // multipliers RN(x / piv): one reciprocal y = RN(1 / piv), then
+      // q0 = RN(x y) and RN(q0 + (x - q0 piv) y), the correctly rounded quotient
+      // by Markstein's theorem when y is normal; a subnormal pivot or one above
+      // 1 / (smallest normal) divides directly (as the register kernel does)
+      const T ap = fabs(piv);
+      const T tiny = sizeof(T) == 8 ? (T)DBL_MIN : (T)FLT_MIN;
+      const bool direct = ap < tiny || ap > T(1) / tiny;
+      const T y = T(1) / piv;
       double* v = slot(k);
       for (int i = k + 1 + tid; i < s; i += CP_THREADS) {
-        const T l = c[i] / piv;
+        const T x = c[i];
+        T l;
+        if (direct) {
+          l = x / piv;
+        } else {
+          const T q0 = x * y;
+          l = fma(fma(-q0, piv, x), y, q0);
+        }
         c[i] = l;
         v[i] = (double)l;
       }
@@ -1044,8 +1055,18 @@ __global__ __launch_bounds__(CP_THREADS) void k_precond_coop(const double* __res
         R1pad[(int64_t)np * np + j] = r;
       }
     }
-    if (lu && perm_out && g == 0)
-      for (int i = tid; i < s; i += CP_THREADS) perm_out[i] = permg[i];
+    if (lu && perm_out && g == 0) {
+      // replay the pivot history: position k takes the row at position permg[k]
+      for (int i = tid; i < s; i += CP_THREADS) perm_out[i] = i;
+      __syncthreads();
+      if (tid == 0)
+        for (int k = 0; k < n; ++k) {
+          const int p = permg[k];
+          const int32_t t = perm_out[k];
+          perm_out[k] = perm_out[p];
+          perm_out[p] = t;
+        }
+    }
   }
   return;
 timeout:
