@@ -105,6 +105,9 @@ def _load(variant: str = ""):
         "orc_rcholqr_f": ([P, I64, I64, I64, I64, U64, P, I64, P, P, P, P, ctypes.c_int], ctypes.c_int),
         "orc_countsketch_hash": ([U64, U64, I64, P, P], None),
         "orc_countsketch": ([P, I64, I64, I64, I64, U64, P], None),
+        "orc_srht_sign": ([U64, U64], ctypes.c_double),
+        "orc_srht_row": ([U64, I64, I64], I64),
+        "orc_srht": ([P, I64, I64, I64, I64, U64, P], None),
         "orc_tslu": ([P, I64, I64, I64, P, P, P, P, I64, P], ctypes.c_int),
         "orc_lc2_f": ([P, I64, I64, I64, P, I64, P, P, P, P, ctypes.c_int], ctypes.c_int),
         "chk_orthogonality": ([P, I64, I64, I64], D),
@@ -197,6 +200,26 @@ def countsketch(x, s: int, seed: int) -> np.ndarray:
     m, n = x.shape
     y = np.zeros((s, n), order="F")
     _load().orc_countsketch(_ptr(x), m, n, _ld(x), s, ctypes.c_uint64(seed), _ptr(y))
+    return y
+
+
+def srht_sign(seed: int, j: int) -> float:
+    """d_j, the random sign of tall row j in the SRHT's D."""
+    return float(_load().orc_srht_sign(ctypes.c_uint64(seed), ctypes.c_uint64(j)))
+
+
+def srht_row(seed: int, m: int, i: int) -> int:
+    """r_i, the row of the order-2^ceil(log2 m) Walsh-Hadamard matrix that row i
+    of the SRHT samples."""
+    return int(_load().orc_srht_row(ctypes.c_uint64(seed), m, i))
+
+
+def srht(x, s: int, seed: int) -> np.ndarray:
+    """Y = S X for the SRHT S = sqrt(m'/s) R H D (s x m)."""
+    x = _f64(x)
+    m, n = x.shape
+    y = np.zeros((s, n), order="F")
+    _load().orc_srht(_ptr(x), m, n, _ld(x), s, ctypes.c_uint64(seed), _ptr(y))
     return y
 
 
@@ -299,7 +322,7 @@ class Result:
 
 
 # method flags: the sketch (Gaussian by default) and the pivoting of the LU of X
-SKETCH_FLAGS = {"gaussian": 0, "count": 1}
+SKETCH_FLAGS = {"gaussian": 0, "count": 1, "srht": 4}
 LU_FLAGS = {"partial": 0, "tournament": 2}
 
 

@@ -248,13 +248,102 @@ void orc_countsketch(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t
   free(part);
 }
 
-/* The sketch of a method: Gaussian (flags without ORC_SKETCH_COUNT) or CountSketch. */
+/* ------------------------------------------------------------------------ */
+/* SRHT, the subsampled randomized Hadamard transform (Section 3 lists it     */
+/* among the common sketches): S = sqrt(m'/s) R H D, with m' = 2^k the       */
+/* smallest power of two >= m (X taken as padded with zero rows), D = diag   */
+/* of random signs d_j, H the Walsh-Hadamard matrix of order m' normalized   */
+/* by 1/sqrt(m') (Sylvester order: H[r][j] = (-1)^popcount(r & j) / sqrt(m')) */
+/* and R the s rows r_0 .. r_{s-1} of a random permutation of [0, m').       */
+/* Entry (i, j) of S is thus (-1)^popcount(r_i & j) d_j / sqrt(s).           */
+/* d_j: Philox4x32-10 with counter (q lo, q hi, 0, 2), q = floor(j/4), key   */
+/* (seed lo, seed hi); word j mod 4, d_j = -1 for odd words.                 */
+/* r_i = pi(i), pi(x) = f3(f2(f1(x))) on k-bit integers: f1(x) = a1 x + b1,  */
+/* f2(x) = x xor (x >> ceil(k/2)), f3(x) = a2 x + b2 (mod 2^k; a1, a2 odd);   */
+/* each step is a bijection of [0, 2^k), so the r_i are distinct. (a1, b1,   */
+/* a2, b2) = the words of Philox4x32-10 at counter (0, 0, 0, 3), a1 and a2    */
+/* with their low bit set.                                                   */
+/* ------------------------------------------------------------------------ */
+static int srht_log2(int64_t m) {
+  int k = 0;
+  while (((int64_t)1 << k) < m) ++k;
+  return k;
+}
+
+double orc_srht_sign(uint64_t seed, uint64_t j) {
+  uint64_t q = j / 4;
+  uint32_t ctr[4] = {(uint32_t)q, (uint32_t)(q >> 32), 0u, 2u};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  orc_philox4x32_10(ctr, key, w);
+  return (w[j % 4] & 1u) ? -1.0 : 1.0;
+}
+
+int64_t orc_srht_row(uint64_t seed, int64_t m, int64_t i) {
+  const int k = srht_log2(m);
+  if (k == 0) return 0;
+  uint32_t ctr[4] = {0u, 0u, 0u, 3u};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  orc_philox4x32_10(ctr, key, w);
+  const uint64_t mask = ((uint64_t)1 << k) - 1;
+  uint64_t x = (uint64_t)i;
+  x = ((uint64_t)(w[0] | 1u) * x + w[1]) & mask;
+  x = x ^ (x >> ((k + 1) / 2));
+  x = ((uint64_t)(w[2] | 1u) * x + w[3]) & mask;
+  return (int64_t)x;
+}
+
+/* Y = S X, summed as the Gaussian sketch (rows in order inside blocks of
+ * ORC_BLOCK rows, the block sums in block order). */
+void orc_srht(const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s, uint64_t seed, double* Y) {
+  int64_t nblk = (m + ORC_BLOCK - 1) / ORC_BLOCK;
+  int64_t batch = 2 * (int64_t)orc_max_threads();
+  size_t psz = (size_t)s * (size_t)n;
+  double* part = (double*)malloc(sizeof(double) * psz * (size_t)batch);
+  int64_t* r = (int64_t*)malloc(sizeof(int64_t) * (size_t)s);
+  const double scale = 1.0 / sqrt((double)s);
+  for (int64_t i = 0; i < s; ++i) r[i] = orc_srht_row(seed, m, i);
+  for (size_t e = 0; e < psz; ++e) Y[e] = 0.0;
+  for (int64_t b0 = 0; b0 < nblk; b0 += batch) {
+    int64_t nb = (nblk - b0 < batch) ? (nblk - b0) : batch;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t bb = 0; bb < nb; ++bb) {
+      double* P = part + (size_t)bb * psz;
+      double* col = (double*)malloc(sizeof(double) * (size_t)s);
+      for (size_t e = 0; e < psz; ++e) P[e] = 0.0;
+      int64_t r0 = (b0 + bb) * ORC_BLOCK;
+      int64_t r1 = r0 + ORC_BLOCK < m ? r0 + ORC_BLOCK : m;
+      for (int64_t j = r0; j < r1; ++j) {
+        const double d = orc_srht_sign(seed, (uint64_t)j) * scale;
+        for (int64_t i = 0; i < s; ++i) col[i] = (__builtin_popcountll((uint64_t)(r[i] & j)) & 1) ? -d : d;
+        for (int64_t k = 0; k < n; ++k) {
+          double xjk = X[j + k * ldx];
+          double* Pk = P + k * s;
+          for (int64_t i = 0; i < s; ++i) Pk[i] += col[i] * xjk;
+        }
+      }
+      free(col);
+    }
+    for (int64_t bb = 0; bb < nb; ++bb) {
+      const double* P = part + (size_t)bb * psz;
+      for (size_t e = 0; e < psz; ++e) Y[e] += P[e];
+    }
+  }
+  free(r);
+  free(part);
+}
+
+/* The sketch of a method: Gaussian (no sketch flag), CountSketch or SRHT. */
 #define ORC_SKETCH_COUNT 1
 #define ORC_LU_TOURNAMENT 2 /* RCLUPPr, LC2: tournament pivoting (orc_tslu) */
+#define ORC_SKETCH_SRHT 4
 static void method_sketch(int flags, const double* X, int64_t m, int64_t n, int64_t ldx, int64_t s, uint64_t seed,
                           double* Y) {
   if (flags & ORC_SKETCH_COUNT)
     orc_countsketch(X, m, n, ldx, s, seed, Y);
+  else if (flags & ORC_SKETCH_SRHT)
+    orc_srht(X, m, n, ldx, s, seed, Y);
   else
     orc_sketch(X, m, n, ldx, s, seed, Y);
 }
