@@ -284,7 +284,8 @@ def bench_mixed(lib, reps=3, x_headline=None):
         row = {}
         r64 = None
         for tag, sk, lu, kind in (("fp64", "fp64", "fp64", "gaussian"), ("fp32", "fp32", "fp32", "gaussian"),
-                                  ("bf16", "bf16", "fp32", "gaussian"), ("count", "fp64", "fp32", "count")):
+                                  ("bf16", "bf16", "fp32", "gaussian"), ("count", "fp64", "fp32", "count"),
+                                  ("srht", "bf16", "fp32", "srht")):
             run = Runner(lib, X, "rclupp", s, SEED, sk, lu, kind)
             ms = run.time(reps)
             stages = run.trace(1)
@@ -297,7 +298,7 @@ def bench_mixed(lib, reps=3, x_headline=None):
             if "sketch" in stages and kind == "gaussian":
                 ent["sketch_roofline"] = rate_entry("sketch", *stages["sketch"], m, n, s, sk)
             elif "sketch" in stages:
-                # CountSketch: one read of X (8mn bytes) against HBM
+                # CountSketch, BF16 SRHT: one read of X (8mn bytes) against HBM
                 t = stages["sketch"][0] / stages["sketch"][1] / 1e3
                 gbs = 8 * m * n / t / 1e9
                 ent["sketch_roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,

@@ -123,7 +123,7 @@ typedef struct {
   int32_t sketch_prec;
   int32_t lu_prec;
   int32_t batch_flags; /* rclupp_qr_batched only: RCLUPP_BATCH_* bits       */
-  int32_t sketch_kind; /* RCLUPP_SKETCH_GAUSSIAN (0) or RCLUPP_SKETCH_COUNT  */
+  int32_t sketch_kind; /* RCLUPP_SKETCH_GAUSSIAN (0), _COUNT (1) or _SRHT (2) */
   int32_t tall_lu;     /* RCLUPP_TALL_LU_PARTIAL (0) or RCLUPP_TALL_LU_TOURNAMENT */
   int32_t reserved[3];
 } rclupp_opts;
@@ -151,9 +151,24 @@ typedef struct {
  *     (seed lo, seed hi); word j mod 4 gives h_j = floor(w s / 2^32) and
  *     sigma_j = -1 for odd w, +1 for even. Y = S X is summed in FP64 (X read
  *     once, no generation cost); requires sketch_prec = FP64 and s <= 1792
- *     (else RCLUPP_ERR_UNSUPPORTED). Batches with it run problem by problem. */
+ *     (else RCLUPP_ERR_UNSUPPORTED). Batches with it run problem by problem.
+ *   RCLUPP_SKETCH_SRHT: the subsampled randomized Hadamard transform (Section
+ *     3 lists it among the common choices), S = sqrt(m'/s) R H D with m' the
+ *     smallest power of two >= m (X taken as padded with zero rows), D the
+ *     diagonal of signs d_j, H the Walsh-Hadamard matrix of order m' in
+ *     Sylvester order normalized by 1/sqrt(m'), R the rows r_0 .. r_{s-1}:
+ *     entry (i, j) of S is (-1)^popcount(r_i & j) d_j / sqrt(s). d_j comes
+ *     from Philox4x32-10 with counter (q lo, q hi, 0, 2), q = floor(j/4), key
+ *     (seed lo, seed hi), word j mod 4, -1 for odd words; r_i = f3(f2(f1(i)))
+ *     on k = log2 m' bits with f1(x) = a1 x + b1, f2(x) = x xor (x >> ceil(k/2)),
+ *     f3(x) = a2 x + b2 (mod 2^k), (a1, b1, a2, b2) the words at counter
+ *     (0, 0, 0, 3) with a1, a2 made odd: a bijection, so the rows are distinct.
+ *     Y = S X is formed as a dense product in the precision of sketch_prec
+ *     (the +-1 entries are exact in all three), with no Gaussian generation.
+ *     Batches with it run problem by problem. */
 #define RCLUPP_SKETCH_GAUSSIAN 0
 #define RCLUPP_SKETCH_COUNT 1
+#define RCLUPP_SKETCH_SRHT 2
 
 /* batch_flags:
  *   RCLUPP_BATCH_GRAPH: capture the batch's launch sequence into a hipGraph
@@ -311,6 +326,12 @@ int rclupp_philox(const uint32_t* ctr, int64_t count, uint32_t k0, uint32_t k1, 
  * per-workgroup partial sums in FP64 in a fixed order. */
 int rclupp_sketch(const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, uint64_t seed, int prec, double* Y,
                   hipStream_t stream);
+
+/* Y = S X (s x n, ld s) for the SRHT S of RCLUPP_SKETCH_SRHT, with `prec` an
+ * rclupp_prec (as rclupp_sketch: FP64, or X rounded to FP32 or BF16); s <= m'
+ * (the order of the Hadamard matrix), m < 2^30. */
+int rclupp_srht(const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, uint64_t seed, int prec, double* Y,
+                hipStream_t stream);
 
 /* Y = S X (s x n, ld s) for the CountSketch S of RCLUPP_SKETCH_COUNT (FP64
  * sums, s <= 1792). */

@@ -10,6 +10,7 @@ from .api import (  # noqa: F401
     chol,
     colmajor,
     countsketch,
+    srht,
     new_colmajor,
     omega,
     philox,
@@ -26,6 +27,6 @@ from .api import (  # noqa: F401
     workspace_size,
 )
 
-__all__ = ["qr", "qr_simple", "qr_noalloc", "qr_batched", "Batch", "workspace_size", "sketch", "countsketch", "omega",
+__all__ = ["qr", "qr_simple", "qr_noalloc", "qr_batched", "Batch", "workspace_size", "sketch", "countsketch", "srht", "omega",
            "philox", "precond", "trsm_gram", "chol", "tall_lu", "tall_lu_tournament", "colmajor", "new_colmajor",
            "QRResult"]

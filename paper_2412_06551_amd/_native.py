@@ -34,7 +34,7 @@ EXPORTS = [
     "rclupp_batched_workspace_size", "rclupp_qr_batched", "rclupp_omega", "rclupp_philox",
     "rclupp_sketch", "rclupp_precond", "rclupp_trsm_gram", "rclupp_chol", "rclupp_tall_lu",
     "rclupp_trace_enable", "rclupp_trace_read", "rclupp_release", "rclupp_qr_noalloc", "rclupp_countsketch",
-    "rclupp_tall_lu_tournament",
+    "rclupp_tall_lu_tournament", "rclupp_srht",
 ]
 
 
@@ -48,7 +48,7 @@ BATCH_AUTOTUNE = 2
 
 
 # sketch kinds (rclupp_opts.sketch_kind)
-SKETCH = {"gaussian": 0, "count": 1}
+SKETCH = {"gaussian": 0, "count": 1, "srht": 2}
 
 
 # pivoting of the LU of X (rclupp_opts.tall_lu)
@@ -98,6 +98,7 @@ def load(path: str = LIB_PATH):
         "rclupp_philox": [P, I64, ctypes.c_uint32, ctypes.c_uint32, P, P],
         "rclupp_sketch": [P, I64, I64, I64, I64, U64, ctypes.c_int, P, P],
         "rclupp_countsketch": [P, I64, I64, I64, I64, U64, P, P],
+        "rclupp_srht": [P, I64, I64, I64, I64, U64, ctypes.c_int, P, P],
         "rclupp_precond": [P, I64, I64, ctypes.c_int, ctypes.c_int, P, P, P, P, P],
         "rclupp_trsm_gram": [P, I64, I64, I64, P, P, I64, P, P],
         "rclupp_chol": [P, I64, I64, ctypes.c_int, P, P, P, I32, P, P],

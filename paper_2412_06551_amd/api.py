@@ -256,6 +256,16 @@ def countsketch(X: torch.Tensor, s: int, seed: int = 0) -> torch.Tensor:
     return Y
 
 
+def srht(X: torch.Tensor, s: int, seed: int = 0, prec: str = "fp64") -> torch.Tensor:
+    """Y = S X for the SRHT S = sqrt(m'/s) R H D (s x n, column-major)."""
+    _require_device()
+    m, n = X.shape
+    Y = new_colmajor(s, n)
+    nat.check(nat.load().rclupp_srht(_ptr(X), m, n, _ld(X), s, ctypes.c_uint64(seed), nat.PREC[prec], _ptr(Y),
+                                     _stream()), "rclupp_srht")
+    return Y
+
+
 def precond(Y: torch.Tensor, lu: bool = True, prec: str = "fp64", want_m: bool = False):
     """R_1 = D R_0 N from the s x n sketch; returns (R1, perm, M, info)."""
     _require_device()

@@ -73,7 +73,8 @@ int validate(int alg, int64_t m, int64_t n, int64_t ld, int64_t s, const rclupp_
   if (m + 3 * ld >= ((int64_t)1 << 29)) return RCLUPP_ERR_UNSUPPORTED;
   if (o) {
     if (o->sketch_prec < 0 || o->sketch_prec > 2 || o->lu_prec < 0 || o->lu_prec > 1) return RCLUPP_ERR_INVALID_ARG;
-    if (o->sketch_kind != RCLUPP_SKETCH_GAUSSIAN && o->sketch_kind != RCLUPP_SKETCH_COUNT)
+    if (o->sketch_kind != RCLUPP_SKETCH_GAUSSIAN && o->sketch_kind != RCLUPP_SKETCH_COUNT &&
+        o->sketch_kind != RCLUPP_SKETCH_SRHT)
       return RCLUPP_ERR_INVALID_ARG;
     if (o->tall_lu != RCLUPP_TALL_LU_PARTIAL && o->tall_lu != RCLUPP_TALL_LU_TOURNAMENT) return RCLUPP_ERR_INVALID_ARG;
     if (o->tall_lu == RCLUPP_TALL_LU_TOURNAMENT && uses_tall_lu(alg) && n > 128) return RCLUPP_ERR_UNSUPPORTED;
@@ -108,6 +109,7 @@ Layout make_layout(int alg, int64_t m, int64_t n, int64_t s, const rclupp_opts* 
     const int grid_hint = sketch_grid > 0 ? sketch_grid : env_int("RCLUPP_SKETCH_GRID", 0);
     L.sk = (o && o->sketch_kind == RCLUPP_SKETCH_COUNT) ? plan_countsketch(m, n, s, grid_hint)
                                                         : plan_sketch(m, n, s, sk_prec, grid_hint);
+    if (o && o->sketch_kind == RCLUPP_SKETCH_SRHT) L.sk.kind = 2;
     L.ypart = take(L.sk.part_bytes);
     L.y = take((size_t)s * n * sizeof(double));
   }
@@ -1446,6 +1448,25 @@ int rclupp_sketch(const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, 
   if (n > RCLUPP_MAX_N || s > 4096) return RCLUPP_ERR_UNSUPPORTED;
   if (prec < RCLUPP_PREC_FP64 || prec > RCLUPP_PREC_BF16) return RCLUPP_ERR_INVALID_ARG;
   const SketchPlan sk = plan_sketch(m, n, s, prec, env_int("RCLUPP_SKETCH_GRID", 0));
+  return with_scratch(sk.part_bytes, stream, [&](char* p) {
+    if (launch_sketch_partials(sk, X, m, n, ld, seed, prec, (double*)p, nullptr, stream) != hipSuccess)
+      return (int)RCLUPP_ERR_HIP;
+    if (launch_sketch_reduce(sk, (double*)p, s, n, 1.0 / std::sqrt((double)s), Y, nullptr, stream) != hipSuccess)
+      return (int)RCLUPP_ERR_HIP;
+    return (int)RCLUPP_OK;
+  });
+}
+
+int rclupp_srht(const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, uint64_t seed, int prec, double* Y,
+                hipStream_t stream) {
+  if (!X || !Y || n < 1 || m < 1 || ld < m || s < 1) return RCLUPP_ERR_INVALID_ARG;
+  if (n > RCLUPP_MAX_N || s > 4096 || m >= ((int64_t)1 << 30)) return RCLUPP_ERR_UNSUPPORTED;
+  if (prec < RCLUPP_PREC_FP64 || prec > RCLUPP_PREC_BF16) return RCLUPP_ERR_INVALID_ARG;
+  int64_t mp = 1;
+  while (mp < m) mp *= 2;
+  if (s > mp) return RCLUPP_ERR_INVALID_ARG;  // s distinct rows of the order-m' Hadamard matrix
+  SketchPlan sk = plan_sketch(m, n, s, prec, env_int("RCLUPP_SKETCH_GRID", 0));
+  sk.kind = 2;
   return with_scratch(sk.part_bytes, stream, [&](char* p) {
     if (launch_sketch_partials(sk, X, m, n, ld, seed, prec, (double*)p, nullptr, stream) != hipSuccess)
       return (int)RCLUPP_ERR_HIP;

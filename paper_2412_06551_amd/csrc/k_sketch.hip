@@ -28,6 +28,18 @@
 // Each workgroup writes its partial sum (fixed order over its tiles); a second
 // kernel adds the partials in chunk order and scales by 1/sqrt(s), so the
 // result is deterministic.
+// KIND = 2: the SRHT (Section 3 lists the subsampled randomized Hadamard
+// transform among the common sketches), S = sqrt(m'/s) R H D with m' the
+// smallest power of two >= m: entry (i, j) is (-1)^popcount(r_i & j) d_j /
+// sqrt(s). The same kernel forms Y = S X as a dense product: the signs d_j
+// are applied to the rows of X as the tile is staged (exact), and the A
+// operand is +-1 from the parity of r_i & j (exact in every precision), so the
+// generation cost is one Philox call per staged row and a popcount per entry.
+// d_j: Philox4x32-10, counter (floor(j/4) lo, hi, 0, 2), word j mod 4, -1 for
+// odd words. r_i = f3(f2(f1(i))) on k = log2 m' bits: f1(x) = a1 x + b1, f2(x)
+// = x xor (x >> ceil(k/2)), f3(x) = a2 x + b2 (mod 2^k, a1 and a2 odd: a
+// bijection, so the sampled rows are distinct), (a1, b1, a2, b2) the words at
+// counter (0, 0, 0, 3).
 #include <type_traits>
 
 #include "device_common.hpp"
@@ -55,7 +67,7 @@ struct SkTile {
   static constexpr int BYTES = (P == 2 ? NN * LD : SK_TK * LD) * ELT;
 };
 
-template <int P, int NN, int NW>
+template <int P, int NN, int NW, int KIND>
 __global__ __launch_bounds__(64 * NW) void k_sketch(const double* __restrict__ X, int64_t m, int n, int64_t ld,
                                                      int64_t ntiles, uint64_t seed, double* __restrict__ Ypart,
                                                      int64_t s_pad, int64_t n_pad, int gy, int xcd_map,
@@ -90,6 +102,21 @@ __global__ __launch_bounds__(64 * NW) void k_sketch(const double* __restrict__ X
   const int lr = tid % TK, lc = tid / TK;  // loader: row, first column
   const int ai = lane & 15, ag = lane >> 4;
   const uint32_t srow = (uint32_t)((sg * NW + wave) * 16 + ai);  // this lane's sketch row (A operand)
+  // SRHT: the Hadamard row this sketch row samples (rows at or past s are
+  // padding and take any row)
+  uint32_t hrow = 0;
+  if constexpr (KIND == 2) {
+    int k = 0;
+    while (((int64_t)1 << k) < m) ++k;
+    if (k > 0) {
+      const philox_out w = philox4x32_10(0u, 0u, 0u, 3u, (uint32_t)seed, (uint32_t)(seed >> 32));
+      const uint32_t mask = (uint32_t)((((uint64_t)1) << k) - 1);
+      uint32_t x = srow & mask;
+      x = ((w.w0 | 1u) * x + w.w1) & mask;
+      x ^= x >> ((k + 1) / 2);
+      hrow = ((w.w2 | 1u) * x + w.w3) & mask;
+    }
+  }
 
   using acc_t = typename std::conditional<P == 0, f64x4, f32x4>::type;
   acc_t acc[NB];
@@ -97,6 +124,7 @@ __global__ __launch_bounds__(64 * NW) void k_sketch(const double* __restrict__ X
   for (int b = 0; b < NB; ++b) acc[b] = acc_t{0, 0, 0, 0};
 
   double pre[CPT];
+  double dpre = 1.0;  // SRHT: the sign d_j of the prefetched row (applied when it is staged)
   auto load_tile = [&](int64_t t) {
     const int64_t row = t * TK + lr;
 #pragma unroll
@@ -104,18 +132,26 @@ __global__ __launch_bounds__(64 * NW) void k_sketch(const double* __restrict__ X
       const int col = lc + CG * c;
       pre[c] = (row < m && col < n) ? X[row + (int64_t)col * ld] : 0.0;
     }
+    if constexpr (KIND == 2) {
+      // (the loads stay in flight: the sign multiplies them only in store_tile)
+      const uint64_t q = (uint64_t)row >> 2;
+      const philox_out w = philox4x32_10((uint32_t)q, (uint32_t)(q >> 32), 0u, 2u, (uint32_t)seed, (uint32_t)(seed >> 32));
+      const uint32_t wt = (row & 2) ? ((row & 1) ? w.w3 : w.w2) : ((row & 1) ? w.w1 : w.w0);
+      dpre = (wt & 1u) ? -1.0 : 1.0;
+    }
   };
   auto store_tile = [&](int buf) {
     unsigned char* base = lds + buf * T::BYTES;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       const int col = lc + CG * c;
+      const double v = KIND == 2 ? dpre * pre[c] : pre[c];  // (a sign change: exact)
       if constexpr (P == 0) {
-        ((double*)base)[lr * LD + col] = pre[c];
+        ((double*)base)[lr * LD + col] = v;
       } else if constexpr (P == 1) {
-        ((float*)base)[lr * LD + col] = (float)pre[c];
+        ((float*)base)[lr * LD + col] = (float)v;
       } else {
-        ((unsigned short*)base)[col * LD + lr] = (unsigned short)f32_to_bf16_rne((float)pre[c]);
+        ((unsigned short*)base)[col * LD + lr] = (unsigned short)f32_to_bf16_rne((float)v);
       }
     }
   };
@@ -126,8 +162,8 @@ __global__ __launch_bounds__(64 * NW) void k_sketch(const double* __restrict__ X
     load_tile(t);
     store_tile(0);
   }
-  f32x4 zc[TK / 16];  // normals of the current tile (FP64 and FP32 forms)
-  if constexpr (P != 2) {
+  f32x4 zc[TK / 16];  // normals of the current tile (FP64 and FP32 Gaussian forms)
+  if constexpr (P != 2 && KIND == 0) {
 #pragma unroll
     for (int ss = 0; ss < TK / 16; ++ss) zc[ss] = normals4(seed, (uint64_t)(t * TK + 16 * ss) / 4 + ag, srow);
   }
@@ -139,12 +175,26 @@ __global__ __launch_bounds__(64 * NW) void k_sketch(const double* __restrict__ X
     if constexpr (P == 2) {
       const unsigned short* xs = (const unsigned short*)base;
       // one K-step of 32 rows: lane group g holds rows 8g .. 8g+7
-      const uint64_t q0 = (uint64_t)(t * TK) / 4 + 2 * ag;
-      const f32x4 z0 = normals4(seed, q0, srow), z1 = normals4(seed, q0 + 1, srow);
-      const uint4 a4 = {f32_to_bf16_rne(z0[0]) | (f32_to_bf16_rne(z0[1]) << 16),
-                        f32_to_bf16_rne(z0[2]) | (f32_to_bf16_rne(z0[3]) << 16),
-                        f32_to_bf16_rne(z1[0]) | (f32_to_bf16_rne(z1[1]) << 16),
-                        f32_to_bf16_rne(z1[2]) | (f32_to_bf16_rne(z1[3]) << 16)};
+      uint4 a4;
+      if constexpr (KIND == 2) {
+        // +-1 in BF16 (0x3F80 / 0xBF80) from the parity of r_i & j
+        uint32_t hv[4];
+        const uint32_t j0 = (uint32_t)(t * TK) + 8 * ag;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t lo = 0x3F80u | ((__builtin_popcount(hrow & (j0 + 2 * e)) & 1u) << 15);
+          const uint32_t hi = 0x3F80u | ((__builtin_popcount(hrow & (j0 + 2 * e + 1)) & 1u) << 15);
+          hv[e] = lo | (hi << 16);
+        }
+        a4 = uint4{hv[0], hv[1], hv[2], hv[3]};
+      } else {
+        const uint64_t q0 = (uint64_t)(t * TK) / 4 + 2 * ag;
+        const f32x4 z0 = normals4(seed, q0, srow), z1 = normals4(seed, q0 + 1, srow);
+        a4 = uint4{f32_to_bf16_rne(z0[0]) | (f32_to_bf16_rne(z0[1]) << 16),
+                   f32_to_bf16_rne(z0[2]) | (f32_to_bf16_rne(z0[3]) << 16),
+                   f32_to_bf16_rne(z1[0]) | (f32_to_bf16_rne(z1[1]) << 16),
+                   f32_to_bf16_rne(z1[2]) | (f32_to_bf16_rne(z1[3]) << 16)};
+      }
       const bf16x8 A = __builtin_bit_cast(bf16x8, a4);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
@@ -156,12 +206,21 @@ __global__ __launch_bounds__(64 * NW) void k_sketch(const double* __restrict__ X
       // (their vector-ALU work overlaps the matrix instructions; for tn past
       // the end they are computed and not used)
       f32x4 zn[TK / 16];
+      if constexpr (KIND == 0) {
 #pragma unroll
-      for (int ss = 0; ss < TK / 16; ++ss) zn[ss] = normals4(seed, (uint64_t)(tn * TK + 16 * ss) / 4 + ag, srow);
+        for (int ss = 0; ss < TK / 16; ++ss) zn[ss] = normals4(seed, (uint64_t)(tn * TK + 16 * ss) / 4 + ag, srow);
+      }
 #pragma unroll
       for (int ss = 0; ss < TK / 16; ++ss) {
         // super-step of 16 rows: K-step ks takes row 16 ss + 4g + ks in lane group g
-        const f32x4 z = zc[ss];
+        f32x4 z;
+        if constexpr (KIND == 2) {
+          const uint32_t j0 = (uint32_t)(t * TK + 16 * ss) + 4 * ag;
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) z[ks] = (__builtin_popcount(hrow & (j0 + ks)) & 1) ? -1.0f : 1.0f;
+        } else {
+          z = zc[ss];
+        }
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
           const int r = 16 * ss + 4 * ag + ks;
@@ -177,7 +236,7 @@ __global__ __launch_bounds__(64 * NW) void k_sketch(const double* __restrict__ X
           }
         }
       }
-      if constexpr (P == 1) {
+      if constexpr (P == 1 && KIND == 0) {
         // FP32: interleave explicitly, one product, its B read and two
         // vector-ALU instructions at a time (measured: 9 % faster; the FP64
         // form is fastest as the compiler schedules it)
@@ -188,8 +247,10 @@ __global__ __launch_bounds__(64 * NW) void k_sketch(const double* __restrict__ X
           __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
         }
       }
+      if constexpr (KIND == 0) {
 #pragma unroll
-      for (int ss = 0; ss < TK / 16; ++ss) zc[ss] = zn[ss];
+        for (int ss = 0; ss < TK / 16; ++ss) zc[ss] = zn[ss];
+      }
     }
     if (tn < ntiles) store_tile(buf ^ 1);
     __syncthreads();
@@ -440,7 +501,7 @@ SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int gx_hint) {
   return p;
 }
 
-template <int P, int NN, int NW>
+template <int P, int NN, int NW, int KIND>
 static hipError_t launch_sk3(const SketchPlan& p, const double* X, int64_t m, int64_t n, int64_t ld, uint64_t seed,
                              double* Ypart, const int32_t* info, const SketchJob* jobs, const BatchItem* items,
                              int nitems, hipStream_t st) {
@@ -452,7 +513,7 @@ static hipError_t launch_sk3(const SketchPlan& p, const double* X, int64_t m, in
     grid = dim3((unsigned)(p.gx * p.gy));
     xcd = (p.gx % 8 == 0) ? 1 : 0;
   }
-  hipLaunchKernelGGL((k_sketch<P, NN, NW>), grid, block, 0, st, X, m, (int)n, ld, p.ntiles, seed, Ypart, p.s_pad,
+  hipLaunchKernelGGL((k_sketch<P, NN, NW, KIND>), grid, block, 0, st, X, m, (int)n, ld, p.ntiles, seed, Ypart, p.s_pad,
                      p.n_pad, p.gy, xcd, info, jobs, items);
   return hipGetLastError();
 }
@@ -461,15 +522,20 @@ template <int NN, int NW>
 static hipError_t launch_sk2(const SketchPlan& p, const double* X, int64_t m, int64_t n, int64_t ld, uint64_t seed,
                              int prec, double* Ypart, const int32_t* info, const SketchJob* jobs,
                              const BatchItem* items, int nitems, hipStream_t st) {
-  if (prec == 0) return launch_sk3<0, NN, NW>(p, X, m, n, ld, seed, Ypart, info, jobs, items, nitems, st);
-  if (prec == 1) return launch_sk3<1, NN, NW>(p, X, m, n, ld, seed, Ypart, info, jobs, items, nitems, st);
-  return launch_sk3<2, NN, NW>(p, X, m, n, ld, seed, Ypart, info, jobs, items, nitems, st);
+  if (p.kind == 2) {
+    if (prec == 0) return launch_sk3<0, NN, NW, 2>(p, X, m, n, ld, seed, Ypart, info, jobs, items, nitems, st);
+    if (prec == 1) return launch_sk3<1, NN, NW, 2>(p, X, m, n, ld, seed, Ypart, info, jobs, items, nitems, st);
+    return launch_sk3<2, NN, NW, 2>(p, X, m, n, ld, seed, Ypart, info, jobs, items, nitems, st);
+  }
+  if (prec == 0) return launch_sk3<0, NN, NW, 0>(p, X, m, n, ld, seed, Ypart, info, jobs, items, nitems, st);
+  if (prec == 1) return launch_sk3<1, NN, NW, 0>(p, X, m, n, ld, seed, Ypart, info, jobs, items, nitems, st);
+  return launch_sk3<2, NN, NW, 0>(p, X, m, n, ld, seed, Ypart, info, jobs, items, nitems, st);
 }
 
 static hipError_t sketch_dispatch(const SketchPlan& p, const double* X, int64_t m, int64_t n, int64_t ld,
                                   uint64_t seed, int prec, double* Ypart, const int32_t* info, const SketchJob* jobs,
                                   const BatchItem* items, int nitems, hipStream_t st) {
-  if (prec < 0 || prec > 2 || p.gz != 1 || n > p.nn) return hipErrorInvalidValue;
+  if (prec < 0 || prec > 2 || p.gz != 1 || n > p.nn || (p.kind != 0 && p.kind != 2)) return hipErrorInvalidValue;
 #define SK_CASE(NNV, NWV)           \
   if (p.nn == NNV && p.nw == NWV) \
     return launch_sk2<NNV, NWV>(p, X, m, n, ld, seed, prec, Ypart, info, jobs, items, nitems, st);

@@ -78,7 +78,7 @@ struct SketchPlan {
   int64_t n_pad;   // padded columns (nn)
   int64_t ntiles;  // 32-row tiles of the tall operand (CountSketch: 4096 / nn rows)
   size_t part_bytes;  // bytes of the per-chunk partial sums and their level-1 sums
-  int kind;        // 0 Gaussian, 1 CountSketch (nn = column slice, gz slices; nn = 0: unsupported)
+  int kind;        // 0 Gaussian, 1 CountSketch (nn = column slice, gz slices; nn = 0: unsupported), 2 SRHT
 };
 SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int gx_hint);
 SketchPlan plan_countsketch(int64_t m, int64_t n, int64_t s, int gx_hint);

@@ -450,6 +450,26 @@ def test_countsketch_rejects_reduced_precision_sums():
     assert getattr(e.value, "status", None) == _nat().ERR_UNSUPPORTED
 
 
+# ------------------------------------------------------------------ SRHT
+# The SRHT in place of the Gaussian sketch, FP64 or BF16 products with an FP64
+# or FP32 preconditioner: the same bar against the oracle run with the same
+# (FP64) sketch.
+@pytest.mark.parametrize("method", ["rclupp", "rcluppr", "rcholqr"])
+@pytest.mark.parametrize("kappa,sk,lu", [(1e4, "fp64", "fp64"), (1e12, "fp64", "fp64"), (1e15, "fp64", "fp64"),
+                                         (1e8, "bf16", "fp32"), (1e14, "bf16", "fp32")])
+def test_srht_methods(method, kappa, sk, lu):
+    if method == "rcholqr" and sk == "bf16":
+        # Algorithm 6 has one CholeskyQR after the preconditioner: a sketch of X
+        # rounded to BF16 (relative error 2^-8) leaves kappa(Q_1) near
+        # 4e-3 kappa(X), beyond one CholeskyQR's reach already at kappa(X) = 1e8
+        pytest.skip("randomized CholeskyQR with a BF16 sketch is limited to small kappa(X)")
+    m, n, s = 30000 + 7, 64, 128
+    x = make_svd(m, n, kappa, seed=44)
+    orc = oracle.run(method, x, s=s, seed=6, sketch="srht")
+    res = _lib().qr(to_dev(x), alg=method, s=s, seed=6, sketch="srht", sketch_prec=sk, lu_prec=lu)
+    method_parity(x, method, s, 6, kappa, res, orc=orc)
+
+
 # ------------------------------------------------------------------ tournament pivoting
 @pytest.mark.parametrize("method", ["rcluppr", "lc2"])
 @pytest.mark.parametrize("kappa", [1e4, 1e12, 1e15])

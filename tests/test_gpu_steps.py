@@ -111,6 +111,44 @@ def test_countsketch_matches_oracle(m, n, s, seed):
     assert np.max(np.abs(y - want)) <= 1e-12 * np.max(colsum)
 
 
+@pytest.mark.parametrize("m,n,s,seed", [(4096, 32, 64, 0), (5000 + 37, 64, 128, 3), (64, 16, 64, 1),
+                                        (3000, 100, 200, 2), (40000 + 3, 256, 1024, 8), (1, 1, 1, 5)])
+def test_srht_matches_oracle(m, n, s, seed):
+    # a power of two, ragged sizes (X padded to m' rows), all rows of the
+    # order-64 Hadamard matrix (s = m = 64) and the 1 x 1 case; the +-1 / sqrt(s)
+    # entries are exact on both sides, so only the association of the sums differs
+    x = make_svd(m, n, 1e6, seed=seed) if m >= n and m > 1 else np.ones((m, n), order="F")
+    y = to_host(_lib().srht(to_dev(x), s, seed))
+    want = oracle.srht(x, s, seed)
+    colsum = np.sum(np.abs(x), axis=0) / np.sqrt(s)  # = |S| |X| (every |S_ij| = 1 / sqrt(s))
+    assert np.all(np.abs(y - want) <= (4 * m + 8) * oracle.U * colsum[None, :])
+    # a wrong row sample or sign would be O(|x|): the typical error is at rounding level
+    assert np.max(np.abs(y - want)) <= 1e-12 * max(np.max(colsum), 1.0)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("m,n,s,seed", [(2048, 32, 64, 0), (5000 + 37, 64, 128, 3), (4099, 256, 512, 5)])
+def test_srht_low_precision(prec, m, n, s, seed):
+    # X rounded to the working precision (S is exact), products exact in FP32, at
+    # most m terms added in FP32 per accumulator, then FP64
+    x = make_svd(m, n, 1e6, seed=seed)
+    y = to_host(_lib().srht(to_dev(x), s, seed, prec=prec))
+    want = oracle.srht(x, s, seed)
+    ab = np.broadcast_to(np.sum(np.abs(x), axis=0) / np.sqrt(s), want.shape)
+    uin = 2.0**-24 if prec == "fp32" else 2.0**-8
+    assert np.all(np.abs(y - want) <= (uin + (m + 8) * 2.0**-24) * ab)
+    rel = np.abs(y - want) / ab
+    assert np.median(rel) <= 4 * uin + 4 * np.sqrt(m) * 2.0**-24
+
+
+def test_srht_rejects_more_rows_than_the_hadamard_order():
+    x = make_svd(100, 4, 1e2, seed=1)
+    with pytest.raises(Exception) as e:
+        _lib().srht(to_dev(x), 129, 0)  # m' = 128
+    from paper_2412_06551_amd import _native
+    assert getattr(e.value, "status", None) == _native.ERR_INVALID_ARG
+
+
 def test_sketch_leading_dimension():
     x = make_svd(3000, 24, 1e3, seed=5)
     a = to_host(_lib().sketch(to_dev(x, ld=3072), 48, 9))
