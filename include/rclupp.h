@@ -323,13 +323,15 @@ int rclupp_philox(const uint32_t* ctr, int64_t count, uint32_t k0, uint32_t k1, 
  * FP64: exact products of the FP32 normals with X, FP64 sums. FP32: X rounded
  * to FP32, FP32 products and sums within a wave. BF16: G and X (through FP32)
  * rounded to BF16, FP32 sums within a wave. All forms add the per-wave and
- * per-workgroup partial sums in FP64 in a fixed order. */
+ * per-workgroup partial sums in FP64 in a fixed order. FP32 and BF16 require
+ * m + 16 ld < 2^32 (else RCLUPP_ERR_UNSUPPORTED). */
 int rclupp_sketch(const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, uint64_t seed, int prec, double* Y,
                   hipStream_t stream);
 
 /* Y = S X (s x n, ld s) for the SRHT S of RCLUPP_SKETCH_SRHT, with `prec` an
  * rclupp_prec (as rclupp_sketch: FP64, or X rounded to FP32 or BF16); s <= m'
- * (the order of the Hadamard matrix), m < 2^30. */
+ * (the order of the Hadamard matrix), m < 2^30; FP32 and BF16 require
+ * m + 16 ld < 2^32. */
 int rclupp_srht(const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, uint64_t seed, int prec, double* Y,
                 hipStream_t stream);
 

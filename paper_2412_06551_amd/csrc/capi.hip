@@ -1447,6 +1447,8 @@ int rclupp_sketch(const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, 
   if (!X || !Y || n < 1 || m < 1 || ld < m || s < 1) return RCLUPP_ERR_INVALID_ARG;
   if (n > RCLUPP_MAX_N || s > 4096) return RCLUPP_ERR_UNSUPPORTED;
   if (prec < RCLUPP_PREC_FP64 || prec > RCLUPP_PREC_BF16) return RCLUPP_ERR_INVALID_ARG;
+  // the reduced-precision loaders address a tile row with 32-bit element offsets
+  if (prec != RCLUPP_PREC_FP64 && m + 16 * ld >= ((int64_t)1 << 32)) return RCLUPP_ERR_UNSUPPORTED;
   const SketchPlan sk = plan_sketch(m, n, s, prec, env_int("RCLUPP_SKETCH_GRID", 0));
   return with_scratch(sk.part_bytes, stream, [&](char* p) {
     if (launch_sketch_partials(sk, X, m, n, ld, seed, prec, (double*)p, nullptr, stream) != hipSuccess)
@@ -1462,6 +1464,7 @@ int rclupp_srht(const double* X, int64_t m, int64_t n, int64_t ld, int64_t s, ui
   if (!X || !Y || n < 1 || m < 1 || ld < m || s < 1) return RCLUPP_ERR_INVALID_ARG;
   if (n > RCLUPP_MAX_N || s > 4096 || m >= ((int64_t)1 << 30)) return RCLUPP_ERR_UNSUPPORTED;
   if (prec < RCLUPP_PREC_FP64 || prec > RCLUPP_PREC_BF16) return RCLUPP_ERR_INVALID_ARG;
+  if (prec != RCLUPP_PREC_FP64 && m + 16 * ld >= ((int64_t)1 << 32)) return RCLUPP_ERR_UNSUPPORTED;
   int64_t mp = 1;
   while (mp < m) mp *= 2;
   if (s > mp) return RCLUPP_ERR_INVALID_ARG;  // s distinct rows of the order-m' Hadamard matrix
