@@ -28,8 +28,8 @@
 
 namespace rclupp {
 
-constexpr int TS_THREADS = 1024;
-constexpr int TS_LEAF = 256;  // rows of a node's block (16 A with A = 16)
+constexpr int TS_ROWS = 256;  // rows of a node's block
+constexpr int TS_CPW = 8;     // columns of the block held by one wave
 
 __device__ __forceinline__ void ts_info_set(int32_t* info, int32_t code, int32_t stage, int32_t index) {
   // many nodes may fail at once: the first failure wins the code word
@@ -40,177 +40,297 @@ __device__ __forceinline__ void ts_info_set(int32_t* info, int32_t code, int32_t
   }
 }
 
-// DPP helpers for 16-lane rows (as in the small dense kernels).
-template <int CTRL>
-__device__ __forceinline__ int ts_dpp_b32(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+// A DPP move within each 16-lane row (quad permutations, mirrors) or a row
+// broadcast (row_bcast:15 = 0x142 into rows 1 and 3, row_bcast:31 = 0x143
+// into rows 2 and 3); lanes of the rows outside ROWS keep their own value.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int ts_dpp(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, ROWS, 0xF, false);
 }
-template <int CTRL>
+template <int CTRL, int ROWS>
 __device__ __forceinline__ double ts_dpp(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = ts_dpp_b32<CTRL>((int)b), hi = ts_dpp_b32<CTRL>((int)(b >> 32));
+  const int lo = ts_dpp<CTRL, ROWS>((int)b), hi = ts_dpp<CTRL, ROWS>((int)(b >> 32));
   return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
 }
-__device__ __forceinline__ void ts_take(double& v, int& key, double ov, int okey) {
-  const double a = fabs(v), b = fabs(ov);
-  const bool take = (b > a) | ((b == a) & (okey < key));
-  v = take ? ov : v;
-  key = take ? okey : key;
+// lane `ln` (wave-uniform) of a double held in VGPRs
+__device__ __forceinline__ double ts_readlane(double v, int ln) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, ln), hi = __builtin_amdgcn_readlane((int)(b >> 32), ln);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
 }
-template <int CTRL>
-__device__ __forceinline__ void ts_step(double& v, int& key) {
-  const double ov = ts_dpp<CTRL>(v);
-  const int ok = ts_dpp_b32<CTRL>(key);
-  ts_take(v, key, ov, ok);
+// Wave maximum of v (butterflies within each 16-lane row, then the row
+// broadcasts into the last row): the result is read from lane 63.
+__device__ __forceinline__ double ts_wave_max(double v) {
+  v = fmax(v, ts_dpp<0xB1, 0xF>(v));
+  v = fmax(v, ts_dpp<0x4E, 0xF>(v));
+  v = fmax(v, ts_dpp<0x141, 0xF>(v));
+  v = fmax(v, ts_dpp<0x140, 0xF>(v));
+  v = fmax(v, ts_dpp<0x142, 0xA>(v));
+  v = fmax(v, ts_dpp<0x143, 0xC>(v));
+  return ts_readlane(v, 63);
+}
+__device__ __forceinline__ int ts_wave_min(int v) {
+  v = min(v, ts_dpp<0xB1, 0xF>(v));
+  v = min(v, ts_dpp<0x4E, 0xF>(v));
+  v = min(v, ts_dpp<0x141, 0xF>(v));
+  v = min(v, ts_dpp<0x140, 0xF>(v));
+  v = min(v, ts_dpp<0x142, 0xA>(v));
+  v = min(v, ts_dpp<0x143, 0xC>(v));
+  return __builtin_amdgcn_readlane(v, 63);
+}
+// Shared state of one node.
+struct TsShared {
+  double l[2][TS_CPW][TS_ROWS];  // multipliers of the steps of a panel, by local row (two panels in flight)
+  int key[2][TS_CPW];            // pivots of those steps: (position << 8) | row
+  int posl[TS_ROWS];             // position of each local row
+  int fail;                      // set when a pivot fails (or the stage had failed before)
+};
+
+// x[c] -= l u_c for the register columns c in [C0, 8), u_c being column c of
+// the pivot row of the step (row = key & 255: lane row % 64, register row
+// row / 64, both wave-uniform; one branch on the register row).
+template <int C0>
+__device__ __forceinline__ void ts_apply(double (&x)[TS_CPW][4], const double (&l)[4], int key) {
+  if constexpr (C0 < TS_CPW) {
+    const int prow = key & 255, pa = prow >> 6, pl = prow & 63;
+    double u[TS_CPW];
+#define TS_READ_ROW(A) \
+  _Pragma("unroll") for (int c = C0; c < TS_CPW; ++c) u[c] = ts_readlane(x[c][A], pl);
+    switch (pa) {
+      case 0: TS_READ_ROW(0) break;
+      case 1: TS_READ_ROW(1) break;
+      case 2: TS_READ_ROW(2) break;
+      default: TS_READ_ROW(3) break;
+    }
+#undef TS_READ_ROW
+#pragma unroll
+    for (int c = C0; c < TS_CPW; ++c)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) x[c][a] = __builtin_fma(-l[a], u[c], x[c][a]);
+  }
 }
 
-// One node: Gaussian elimination with partial pivoting of r <= 256 rows, n <= 64 CS
-// columns, in registers: thread (wave w, lane l) holds columns 4w + l/16 + 64c
-// and rows l%16 + 16a (a < 16). Rows never move; positions trade (LDS tables).
+// The pivot of step k on register column C (pos: the positions of the lane's
+// rows after step k - 1): the largest |x| over the rows at positions >= k,
+// ties to the smaller position (a wave maximum of |x|, then a wave minimum of
+// the keys of the rows that attain it), and the multipliers RN(x / p) of the
+// other live rows into l (zero for rows that are not eliminated). Publishes
+// the multipliers (ls), the key (ks) and the position swap; pos becomes the
+// positions after step k. Returns the key, or -1 (with zero multipliers, and
+// the failure flag set) if the column is not finite or, at the root, zero.
+template <int C>
+__device__ __forceinline__ int ts_pivot(double (&x)[TS_CPW][4], int (&pos)[4], double (&l)[4], double* ls, int* ks,
+                                        TsShared& sh, int k, int r, int lane, bool root, int32_t* info) {
+  double mag[4];
+  bool live[4], bad = false;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    live[a] = (lane + 64 * a < r) & (pos[a] >= k);
+    mag[a] = live[a] ? fabs(x[C][a]) : -1.0;
+    bad |= live[a] & !is_finite(x[C][a]);
+  }
+  const double best = ts_wave_max(fmax(fmax(mag[0], mag[1]), fmax(mag[2], mag[3])));
+  // RN(1 / |p|), formed while the keys are reduced (RN(1 / -b) = -RN(1 / b))
+  const double yb = 1.0 / best;
+  int kc[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) kc[a] = (mag[a] == best) ? ((pos[a] << 8) | (lane + 64 * a)) : INT_MAX;
+  const int key = ts_wave_min(min(min(kc[0], kc[1]), min(kc[2], kc[3])));
+  __asm__ volatile("" ::"v"(yb));  // keep the reciprocal ahead of the branch below
+  const bool anybad = __ballot(bad) != 0;
+  const bool zero = !(best > 0.0);
+  if (anybad || (zero && root)) {
+    if (lane == 0) {
+      ts_info_set(info, anybad ? INFO_NONFINITE : INFO_LU_ZERO_PIVOT, STAGE_LU, k + 1);
+      sh.fail = 1;
+      *ks = -1;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) l[a] = 0.0;
+    return -1;
+  }
+  const int prow = key & 255, ppos = key >> 8, pa = prow >> 6, pl = prow & 63;
+  // the pivot's sign, and the row now at position k, from wave ballots
+  unsigned long long neg = 0, atk = 0;
+  int qa = 0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const unsigned long long bn = __ballot(x[C][a] < 0.0), bk = __ballot(pos[a] == k);
+    neg = (a == pa) ? bn : neg;
+    if (bk != 0) {
+      atk = bk;
+      qa = a;
+    }
+  }
+  const bool pneg = (neg >> pl) & 1;
+  const int q = 64 * qa + __builtin_ctzll(atk);
+  const double p = pneg ? -best : best;
+  if (lane == 0) *ks = key;
+  // multipliers RN(x / p): Markstein's corrected quotient from one reciprocal
+  // y = RN(1 / p), q0 = RN(x y), RN(q0 + (x - q0 p) y), the correctly rounded
+  // quotient when y is normal (|x / p| <= 1); subnormal pivots and pivots
+  // above 1 / (smallest normal) divide directly. A zero pivot column (a
+  // singular block below the root) eliminates nothing.
+  double qv[4];
+  if (zero) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) qv[a] = 0.0;
+  } else if (best < 0x1p-1022 || best > 0x1p1022) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) qv[a] = x[C][a] / p;
+  } else {
+    const double y = pneg ? -yb : yb;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const double q0 = x[C][a] * y;
+      qv[a] = __builtin_fma(__builtin_fma(-q0, p, x[C][a]), y, q0);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int row = lane + 64 * a;
+    const bool elim = live[a] & (row != prow) & !zero;
+    l[a] = elim ? qv[a] : 0.0;
+    x[C][a] = elim ? qv[a] : x[C][a];
+    ls[row] = l[a];
+  }
+  // positions after step k: the pivot row moves to k, the row at k to its place
+  if (lane == 0) {
+    sh.posl[q] = ppos;
+    sh.posl[prow] = k;
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) pos[a] = (lane + 64 * a == prow) ? k : (pos[a] == k ? ppos : pos[a]);
+  return key;
+}
+
+// Steps 8w .. 8w+7 (those below n) on the wave that holds their columns: the
+// unblocked elimination of its 8 columns (each pivot, then that step applied
+// to the wave's columns after it), published into panel buffer w % 2.
+// Returns false if a pivot failed.
+__device__ __forceinline__ void ts_panel(double (&x)[TS_CPW][4], int (&pos)[4], TsShared& sh, int w, int n, int r,
+                                         int lane, bool root, int32_t* info) {
+  const int b = w & 1;
+  double l[4];
+  // A failed pivot sets the node's failure flag and the node stops at the
+  // next barrier; the rest of the panel still runs (on meaningless values,
+  // with every index in range: a key of -1 names row 255), which keeps one
+  // path through the registers.
+#define TS_PANEL_STEP(C)                                                                                    \
+  if (TS_CPW * w + C < n) {                                                                                 \
+    const int key = ts_pivot<C>(x, pos, l, sh.l[b][C], &sh.key[b][C], sh, TS_CPW * w + C, r, lane, root, info); \
+    ts_apply<C + 1>(x, l, key);                                                                             \
+  }
+  TS_PANEL_STEP(0)
+  TS_PANEL_STEP(1)
+  TS_PANEL_STEP(2)
+  TS_PANEL_STEP(3)
+  TS_PANEL_STEP(4)
+  TS_PANEL_STEP(5)
+  TS_PANEL_STEP(6)
+  TS_PANEL_STEP(7)
+#undef TS_PANEL_STEP
+}
+
+// One node: Gaussian elimination with partial pivoting of r <= 256 rows and
+// n <= 8 NWV columns, in registers: wave w holds columns 8w .. 8w+7, lane l
+// the rows l, l+64, l+128, l+192. Rows never move; positions trade (an LDS
+// table, and registers in the wave that chooses the pivots). Blocked by
+// panels of 8 columns: the wave that holds a panel eliminates it on its own
+// and publishes its 8 steps; after one barrier the waves that hold later
+// columns apply them, and the wave of the next panel then eliminates that
+// one. Every element receives the updates of the steps in step order, each
+// as one fused multiply-add, as in the unblocked elimination.
 //   leaf level (prev == nullptr): node g factors rows floor(g m / L) .. of X;
 //   upper levels: node g stacks the sets g F .. of prev (n indices each; the
 //     last node may have fewer), nsets sets in all.
 // Writes the original indices of its first n pivot rows to sel[g n ..]; the
 // root (one node) also writes N and L_11 (n x n, ld n).
-template <int CS>
-__global__ __launch_bounds__(TS_THREADS) void k_tslu_node(const double* __restrict__ X, int64_t ldx, int64_t m, int n,
-                                                          int64_t leaves, const int32_t* __restrict__ prev,
-                                                          int64_t nsets, int F, int32_t* __restrict__ sel,
-                                                          double* __restrict__ Nout, double* __restrict__ Lout,
-                                                          int32_t* info) {
-  constexpr int A = 16, SR = 16 * A;
-  __shared__ double vb[2][SR];       // multipliers of the step, by (row % 16) * A + row / 16
-  __shared__ int posl[SR], rowl[SR];  // position of each local row, row at each position
-  __shared__ int64_t orig[SR];        // original row index of each local row
-  __shared__ int bc_key[2];
-  if (info_failed(info)) return;
+template <int NWV>
+__global__ __launch_bounds__(64 * NWV, NWV == 1 ? 2 : 4) void k_tslu_node(
+    const double* __restrict__ X, int64_t ldx, int64_t m, int n, int64_t leaves, const int32_t* __restrict__ prev,
+    int64_t nsets, int F, int32_t* __restrict__ sel, double* __restrict__ Nout, double* __restrict__ Lout,
+    int32_t* info) {
+  __shared__ TsShared sh;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) sh.fail = info_failed(info) ? 1 : 0;
+  for (int i = tid; i < TS_ROWS; i += 64 * NWV) sh.posl[i] = i;
+  __syncthreads();
+  if (sh.fail) return;
   const int64_t g = blockIdx.x;
   const bool root = gridDim.x == 1;
+  // local row i is X's row r0 + i (leaves) or prev[s0 n + i] (upper levels)
   int r;
+  int64_t r0 = 0, s0 = 0;
   if (!prev) {
-    const int64_t r0 = g * m / leaves, r1 = (g + 1) * m / leaves;
-    r = (int)(r1 - r0);
-    for (int i = threadIdx.x; i < r; i += TS_THREADS) orig[i] = r0 + i;
+    r0 = g * m / leaves;
+    r = (int)((g + 1) * m / leaves - r0);
   } else {
-    const int64_t s0 = g * F, s1 = (s0 + F < nsets) ? s0 + F : nsets;
+    s0 = g * F;
+    const int64_t s1 = (s0 + F < nsets) ? s0 + F : nsets;
     r = (int)((s1 - s0) * n);
-    for (int i = threadIdx.x; i < r; i += TS_THREADS) orig[i] = prev[s0 * n + i];
   }
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tr = lane & 15, col0 = 4 * wave + (lane >> 4);
-  for (int i = tid; i < SR; i += TS_THREADS) {
-    posl[(i & 15) * A + (i >> 4)] = i;
-    rowl[i] = i;
+  auto orig = [&](int row) -> int64_t { return prev ? (int64_t)prev[s0 * n + row] : r0 + row; };
+  double x[TS_CPW][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int row = lane + 64 * a;
+    const int64_t xr = row < r ? orig(row) : 0;
+#pragma unroll
+    for (int c = 0; c < TS_CPW; ++c) {
+      const int col = TS_CPW * wave + c;
+      x[c][a] = (row < r && col < n) ? X[xr + (int64_t)col * ldx] : 0.0;
+    }
+  }
+  int pos[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) pos[a] = lane + 64 * a;
+  const int np = (n + TS_CPW - 1) / TS_CPW;  // panels
+  if (wave == 0) ts_panel(x, pos, sh, 0, n, r, lane, root, info);
+  for (int j = 0; j < np; ++j) {
+    __syncthreads();  // panel j published
+    if (sh.fail) return;
+    if (wave > j && TS_CPW * wave < n) {
+      // the steps of panel j on this wave's columns, in step order
+      const int b = j & 1;
+#pragma unroll 1
+      for (int c = 0; c < TS_CPW; ++c) {
+        if (TS_CPW * j + c >= n) break;
+        const int key = __builtin_amdgcn_readfirstlane(sh.key[b][c]);
+        double l[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) l[a] = sh.l[b][c][lane + 64 * a];
+        ts_apply<0>(x, l, key);
+      }
+      if (wave == j + 1) {
+        // the next panel: its wave takes the positions from the table
+#pragma unroll
+        for (int a = 0; a < 4; ++a) pos[a] = sh.posl[lane + 64 * a];
+        ts_panel(x, pos, sh, wave, n, r, lane, root, info);
+      }
+    }
   }
   __syncthreads();
-  double x[CS][A];
+  if (sh.fail) return;
+  if (wave == 0) {
 #pragma unroll
-  for (int c = 0; c < CS; ++c)
-#pragma unroll
-    for (int a = 0; a < A; ++a) {
-      const int row = tr + 16 * a, col = col0 + 64 * c;
-      x[c][a] = (row < r && col < n) ? X[orig[row] + (int64_t)col * ldx] : 0.0;
+    for (int a = 0; a < 4; ++a) {
+      const int row = lane + 64 * a;
+      const int p = sh.posl[row];
+      if (row < r && p < n) sel[g * n + p] = (int32_t)orig(row);
     }
-
-#pragma unroll
-  for (int kc = 0; kc < CS; ++kc) {
-    for (int kk = 0; kk < 64; ++kk) {
-      const int k = 64 * kc + kk;
-      if (k >= n) break;
-      const int buf = k & 1;
-      if (wave == (kk >> 2)) {
-        // pivot candidates (rows at positions >= k), scanned in register order
-        double best = 0.0;
-        int key = INT_MAX, bad = 0;
-#pragma unroll
-        for (int a = 0; a < A; ++a) {
-          const int row = tr + 16 * a, pa = posl[tr * A + a];
-          const bool live = (row < r) & (pa >= k);
-          bad |= live & !is_finite(x[kc][a]);
-          ts_take(best, key, live ? x[kc][a] : 0.0, live ? ((pa << 12) | row) : INT_MAX);
-        }
-        ts_step<0xB1>(best, key);
-        ts_step<0x4E>(best, key);
-        ts_step<0x141>(best, key);
-        ts_step<0x140>(best, key);
-        const bool own = (col0 == kk);
-        const bool anybad = __ballot(own && bad) != 0;
-        if (own) {
-          const int prow = key & 4095, ppos = key >> 12;
-          const bool zero = !(fabs(best) > 0.0);
-          if (anybad || (zero && root)) {
-            if (tr == 0) {
-              ts_info_set(info, anybad ? INFO_NONFINITE : INFO_LU_ZERO_PIVOT, STAGE_LU, k + 1);
-              bc_key[buf] = -1;
-            }
-          } else {
-            // multipliers RN(x / p): Markstein's corrected quotient from one
-            // reciprocal y = RN(1 / p), q0 = RN(x y), RN(q0 + (x - q0 p) y), which
-            // is the correctly rounded quotient when y is normal (|x / p| <= 1);
-            // subnormal pivots and pivots above 1 / (smallest normal) divide
-            // directly. A zero pivot column (a singular block below the root)
-            // eliminates nothing.
-            const double ap = fabs(best);
-            const bool direct = ap < 0x1p-1022 || ap > 0x1p1022;
-            const double y = zero ? 0.0 : 1.0 / best;
-#pragma unroll
-            for (int a = 0; a < A; ++a) {
-              const int row = tr + 16 * a;
-              const bool live = (row < r) & (posl[tr * A + a] >= k) & (row != prow) & !zero;
-              double qv;
-              if (direct) {
-                qv = zero ? 0.0 : x[kc][a] / best;
-              } else {
-                const double q0 = x[kc][a] * y;
-                qv = __builtin_fma(__builtin_fma(-q0, best, x[kc][a]), y, q0);
-              }
-              const double l = live ? qv : 0.0;
-              x[kc][a] = live ? l : x[kc][a];
-              vb[buf][tr * A + a] = l;
-            }
-            if (tr == 0) {
-              const int q = rowl[k];
-              rowl[k] = prow;
-              rowl[ppos] = q;
-              posl[(prow & 15) * A + (prow >> 4)] = k;
-              posl[(q & 15) * A + (q >> 4)] = ppos;
-              bc_key[buf] = key;
-            }
-          }
-        }
-      }
-      __syncthreads();
-      const int pkey = __builtin_amdgcn_readfirstlane(bc_key[buf]);
-      if (pkey < 0) return;
-      const int prow = pkey & 4095;
-      const int ap = prow >> 4, src = (lane & 48) | (prow & 15);
-#pragma unroll
-      for (int c = kc; c < CS; ++c) {
-        if (4 * wave + 3 + 64 * c > k) {
-          double u = x[c][0];
-#pragma unroll
-          for (int a = 1; a < A; ++a)
-            if (a == ap) u = x[c][a];
-          u = __shfl(u, src);
-          if (col0 + 64 * c <= k) u = 0.0;  // columns <= k are final
-#pragma unroll
-          for (int a = 0; a < A; ++a) x[c][a] = __builtin_fma(-vb[buf][tr * A + a], u, x[c][a]);
-        }
-      }
-    }
-    __syncthreads();
   }
-
-  for (int p = tid; p < n; p += TS_THREADS) sel[g * n + p] = (int32_t)orig[rowl[p]];
   if (root) {
 #pragma unroll
-    for (int c = 0; c < CS; ++c) {
-      const int col = col0 + 64 * c;
+    for (int c = 0; c < TS_CPW; ++c) {
+      const int col = TS_CPW * wave + c;
       if (col >= n) continue;
 #pragma unroll
-      for (int a = 0; a < A; ++a) {
-        const int p = posl[tr * A + a];
-        if (tr + 16 * a < r && p < n) {
+      for (int a = 0; a < 4; ++a) {
+        const int row = lane + 64 * a;
+        const int p = sh.posl[row];
+        if (row < r && p < n) {
           Nout[p + (int64_t)col * n] = (col >= p) ? x[c][a] : 0.0;
           Lout[p + (int64_t)col * n] = (col < p) ? x[c][a] : (col == p ? 1.0 : 0.0);
         }
@@ -229,7 +349,7 @@ __global__ void k_tslu_scatter(double* W, int64_t ldw, int n, const int32_t* __r
   W[(int64_t)sel[k] + (int64_t)j * ldw] = L[k + (int64_t)j * n];
 }
 
-int64_t tslu_leaves(int64_t m) { return (m + TS_LEAF - 1) / TS_LEAF; }
+int64_t tslu_leaves(int64_t m) { return (m + TS_ROWS - 1) / TS_ROWS; }
 
 size_t tslu_scratch_bytes(int64_t m, int64_t n) {
   // candidate sets of two consecutive levels, N and L_11, the padded N
@@ -241,21 +361,31 @@ size_t tslu_scratch_bytes(int64_t m, int64_t n) {
 
 hipError_t launch_tslu(const double* X, int64_t m, int64_t n, int64_t ldx, double* W, int64_t ldw, int32_t* sel,
                        double* Nout, double* scratch, int32_t* info, hipStream_t st) {
-  if (n < 1 || n > 128 || m < n) return hipErrorInvalidValue;
+  if (n < 1 || n > TS_CPW * 16 || m < n) return hipErrorInvalidValue;
   const int64_t leaves = tslu_leaves(m);
   const size_t sets = ((size_t)leaves * n * sizeof(int32_t) + 255) / 256 * 256;
   int32_t* lv[2] = {(int32_t*)scratch, (int32_t*)((char*)scratch + sets)};
   double* Lt = (double*)((char*)scratch + 2 * sets);
   double* Nt = Nout ? Nout : (double*)((char*)Lt + ((size_t)n * n * 8 + 255) / 256 * 256);
   double* Npad = (double*)((char*)Lt + 2 * (((size_t)n * n * 8 + 255) / 256 * 256));
-  const int F = TS_LEAF / (int)n;
+  const int F = TS_ROWS / (int)n;
+  // waves per node: one per 8 columns, rounded up to a power of two
+  const int64_t wv = (n + TS_CPW - 1) / TS_CPW;
   auto node = [&](int64_t nodes, const int32_t* prev, int64_t nsets, int32_t* out) {
-    if (n <= 64)
-      hipLaunchKernelGGL(k_tslu_node<1>, dim3((unsigned)nodes), dim3(TS_THREADS), 0, st, X, ldx, m, (int)n, leaves,
-                         prev, nsets, F, out, Nt, Lt, info);
+#define TS_LAUNCH(NWV)                                                                                           \
+  hipLaunchKernelGGL(k_tslu_node<NWV>, dim3((unsigned)nodes), dim3(64 * NWV), 0, st, X, ldx, m, (int)n, leaves, \
+                     prev, nsets, F, out, Nt, Lt, info)
+    if (wv <= 1)
+      TS_LAUNCH(1);
+    else if (wv <= 2)
+      TS_LAUNCH(2);
+    else if (wv <= 4)
+      TS_LAUNCH(4);
+    else if (wv <= 8)
+      TS_LAUNCH(8);
     else
-      hipLaunchKernelGGL(k_tslu_node<2>, dim3((unsigned)nodes), dim3(TS_THREADS), 0, st, X, ldx, m, (int)n, leaves,
-                         prev, nsets, F, out, Nt, Lt, info);
+      TS_LAUNCH(16);
+#undef TS_LAUNCH
     return hipGetLastError();
   };
   // leaves, then levels of F-way merges until one set is left (the root

@@ -461,7 +461,8 @@ def test_tall_lu_matches_oracle(m, n):
 
 # ---------------------------------------------------------------- tournament pivoting
 @pytest.mark.parametrize("m,n,kappa", [(5000, 16, 1e6), (9001, 40, 1e10), (3000, 64, 1e4), (2600, 100, 1e8),
-                                       (70000 + 3, 8, 1e3), (300, 128, 1e2), (256, 30, 1e5), (40000 + 7, 128, 1e12)])
+                                       (70000 + 3, 8, 1e3), (300, 128, 1e2), (256, 30, 1e5), (40000 + 7, 128, 1e12),
+                                       (1000, 1, 1.0), (128, 128, 1e3), (4099, 9, 1e7), (20000, 65, 1e9)])
 def test_tournament_lu_matches_oracle(m, n, kappa):
     # the selection is integer work: pivot rows identical; the tree's
     # eliminations use the same operations, so N and L_11 equal the oracle's bit
