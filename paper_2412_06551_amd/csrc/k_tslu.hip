@@ -83,6 +83,7 @@ __device__ __forceinline__ int ts_wave_min(int v) {
 struct TsShared {
   double l[2][TS_CPW][TS_ROWS];  // multipliers of the steps of a panel, by local row (two panels in flight)
   int key[2][TS_CPW];            // pivots of those steps: (position << 8) | row
+  int flag[2][TS_CPW];           // p + 1 once step c of panel p is published
   int posl[TS_ROWS];             // position of each local row
   int fail;                      // set when a pivot fails (or the stage had failed before)
 };
@@ -133,10 +134,18 @@ __device__ __forceinline__ int ts_pivot(double (&x)[TS_CPW][4], int (&pos)[4], d
   const double best = ts_wave_max(fmax(fmax(mag[0], mag[1]), fmax(mag[2], mag[3])));
   // RN(1 / |p|), formed while the keys are reduced (RN(1 / -b) = -RN(1 / b))
   const double yb = 1.0 / best;
-  int kc[4];
+  // the rows attaining it: usually one (its key read from its lane), else
+  // the wave minimum of their keys
+  int kc[4], nbest = 0, lbest = 0;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) kc[a] = (mag[a] == best) ? ((pos[a] << 8) | (lane + 64 * a)) : INT_MAX;
-  const int key = ts_wave_min(min(min(kc[0], kc[1]), min(kc[2], kc[3])));
+  for (int a = 0; a < 4; ++a) {
+    const unsigned long long at = __ballot(mag[a] == best);
+    nbest += __builtin_popcountll(at);
+    if (at != 0) lbest = __builtin_ctzll(at);
+    kc[a] = (mag[a] == best) ? ((pos[a] << 8) | (lane + 64 * a)) : INT_MAX;
+  }
+  const int kl = min(min(kc[0], kc[1]), min(kc[2], kc[3]));
+  const int key = nbest == 1 ? __builtin_amdgcn_readlane(kl, lbest) : ts_wave_min(kl);
   __asm__ volatile("" ::"v"(yb));  // keep the reciprocal ahead of the branch below
   const bool anybad = __ballot(bad) != 0;
   const bool zero = !(best > 0.0);
@@ -207,7 +216,10 @@ __device__ __forceinline__ int ts_pivot(double (&x)[TS_CPW][4], int (&pos)[4], d
 
 // Steps 8w .. 8w+7 (those below n) on the wave that holds their columns: the
 // unblocked elimination of its 8 columns (each pivot, then that step applied
-// to the wave's columns after it), published into panel buffer w % 2.
+// to the wave's columns after it), published step by step into panel buffer
+// w % 2 (multipliers, key, then the step's flag: the LDS executes one wave's
+// accesses in issue order, so a wave that reads the flag and then the step
+// sees the step; no wait for the writes is needed before the flag).
 // Returns false if a pivot failed.
 __device__ __forceinline__ void ts_panel(double (&x)[TS_CPW][4], int (&pos)[4], TsShared& sh, int w, int n, int r,
                                          int lane, bool root, int32_t* info) {
@@ -221,7 +233,10 @@ __device__ __forceinline__ void ts_panel(double (&x)[TS_CPW][4], int (&pos)[4], 
   if (TS_CPW * w + C < n) {                                                                                 \
     const int key = ts_pivot<C>(x, pos, l, sh.l[b][C], &sh.key[b][C], sh, TS_CPW * w + C, r, lane, root, info); \
     ts_apply<C + 1>(x, l, key);                                                                             \
+    if (lane == 0) __hip_atomic_store(&sh.flag[b][C], w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); \
   }
+  // the panel is the node's critical path: its wave issues first
+  __builtin_amdgcn_s_setprio(3);
   TS_PANEL_STEP(0)
   TS_PANEL_STEP(1)
   TS_PANEL_STEP(2)
@@ -231,6 +246,17 @@ __device__ __forceinline__ void ts_panel(double (&x)[TS_CPW][4], int (&pos)[4], 
   TS_PANEL_STEP(6)
   TS_PANEL_STEP(7)
 #undef TS_PANEL_STEP
+  __builtin_amdgcn_s_setprio(0);
+}
+
+// Step c of panel p (published) on a wave's own columns.
+__device__ __forceinline__ void ts_follow(double (&x)[TS_CPW][4], const TsShared& sh, int p, int c, int lane) {
+  const int b = p & 1;
+  const int key = __builtin_amdgcn_readfirstlane(sh.key[b][c]);
+  double l[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) l[a] = sh.l[b][c][lane + 64 * a];
+  ts_apply<0>(x, l, key);
 }
 
 // One node: Gaussian elimination with partial pivoting of r <= 256 rows and
@@ -256,6 +282,7 @@ __global__ __launch_bounds__(64 * NWV, NWV == 1 ? 2 : 4) void k_tslu_node(
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) sh.fail = info_failed(info) ? 1 : 0;
   for (int i = tid; i < TS_ROWS; i += 64 * NWV) sh.posl[i] = i;
+  for (int i = tid; i < 2 * TS_CPW; i += 64 * NWV) sh.flag[i / TS_CPW][i % TS_CPW] = 0;
   __syncthreads();
   if (sh.fail) return;
   const int64_t g = blockIdx.x;
@@ -292,22 +319,37 @@ __global__ __launch_bounds__(64 * NWV, NWV == 1 ? 2 : 4) void k_tslu_node(
     __syncthreads();  // panel j published
     if (sh.fail) return;
     if (wave > j && TS_CPW * wave < n) {
-      // the steps of panel j on this wave's columns, in step order
-      const int b = j & 1;
+      // the steps of panel j on this wave's columns, in step order (the wave
+      // of panel j + 1 applied them while they were published, from j = 1)
+      if (wave != j + 1 || j == 0) {
 #pragma unroll 1
-      for (int c = 0; c < TS_CPW; ++c) {
-        if (TS_CPW * j + c >= n) break;
-        const int key = __builtin_amdgcn_readfirstlane(sh.key[b][c]);
-        double l[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) l[a] = sh.l[b][c][lane + 64 * a];
-        ts_apply<0>(x, l, key);
+        for (int c = 0; c < TS_CPW && TS_CPW * j + c < n; ++c) ts_follow(x, sh, j, c, lane);
       }
       if (wave == j + 1) {
         // the next panel: its wave takes the positions from the table
 #pragma unroll
         for (int a = 0; a < 4; ++a) pos[a] = sh.posl[lane + 64 * a];
         ts_panel(x, pos, sh, wave, n, r, lane, root, info);
+      } else if (wave == j + 2) {
+        // the wave of panel j + 2 applies the steps of panel j + 1 as they
+        // are published, so that it can start its own panel at the barrier
+        // (a bounded wait: on time-out the node fails)
+#pragma unroll 1
+        for (int c = 0; c < TS_CPW && TS_CPW * (j + 1) + c < n; ++c) {
+          unsigned spins = 0;
+          while (__hip_atomic_load(&sh.flag[(j + 1) & 1][c], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != j + 2) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > (1u << 22)) break;
+          }
+          if (spins > (1u << 22)) {
+            if (lane == 0) {
+              ts_info_set(info, INFO_SYNC_TIMEOUT, STAGE_LU, TS_CPW * (j + 1) + c + 1);
+              sh.fail = 1;
+            }
+            break;
+          }
+          ts_follow(x, sh, j + 1, c, lane);
+        }
       }
     }
   }
