@@ -40,45 +40,45 @@ __device__ __forceinline__ void ts_info_set(int32_t* info, int32_t code, int32_t
   }
 }
 
-// A DPP move within each 16-lane row (quad permutations, mirrors) or a row
-// broadcast (row_bcast:15 = 0x142 into rows 1 and 3, row_bcast:31 = 0x143
-// into rows 2 and 3); lanes of the rows outside ROWS keep their own value.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ int ts_dpp(int v) {
-  return __builtin_amdgcn_update_dpp(v, v, CTRL, ROWS, 0xF, false);
-}
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double ts_dpp(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = ts_dpp<CTRL, ROWS>((int)b), hi = ts_dpp<CTRL, ROWS>((int)(b >> 32));
-  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
-}
 // lane `ln` (wave-uniform) of a double held in VGPRs
 __device__ __forceinline__ double ts_readlane(double v, int ln) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)b, ln), hi = __builtin_amdgcn_readlane((int)(b >> 32), ln);
   return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
 }
-// Wave maximum of v (butterflies within each 16-lane row, then the row
-// broadcasts into the last row): the result is read from lane 63.
-__device__ __forceinline__ double ts_wave_max(double v) {
-  v = fmax(v, ts_dpp<0xB1, 0xF>(v));
-  v = fmax(v, ts_dpp<0x4E, 0xF>(v));
-  v = fmax(v, ts_dpp<0x141, 0xF>(v));
-  v = fmax(v, ts_dpp<0x140, 0xF>(v));
-  v = fmax(v, ts_dpp<0x142, 0xA>(v));
-  v = fmax(v, ts_dpp<0x143, 0xC>(v));
-  return ts_readlane(v, 63);
+// Wave maximum / minimum by DPP: butterflies within each 16-lane row (quad
+// permutations, half-row and row mirrors), then the row broadcasts
+// (row_bcast:15 = 0x142 into rows 1 and 3, row_bcast:31 = 0x143 into rows 2
+// and 3) carry the result into the last row; it is read from lane 63. The
+// moved operand of a lane without a source is the operation's identity,
+// which lets the compiler fold each move into the max or min instruction.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned ts_dpp_umax(unsigned v) {
+  return max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, false));
+}
+__device__ __forceinline__ unsigned ts_wave_umax(unsigned v) {
+  v = ts_dpp_umax<0xB1, 0xF>(v);
+  v = ts_dpp_umax<0x4E, 0xF>(v);
+  v = ts_dpp_umax<0x141, 0xF>(v);
+  v = ts_dpp_umax<0x140, 0xF>(v);
+  v = ts_dpp_umax<0x142, 0xA>(v);
+  v = ts_dpp_umax<0x143, 0xC>(v);
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int ts_dpp_min(int v) {
+  return min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, CTRL, ROWS, 0xF, false));
 }
 __device__ __forceinline__ int ts_wave_min(int v) {
-  v = min(v, ts_dpp<0xB1, 0xF>(v));
-  v = min(v, ts_dpp<0x4E, 0xF>(v));
-  v = min(v, ts_dpp<0x141, 0xF>(v));
-  v = min(v, ts_dpp<0x140, 0xF>(v));
-  v = min(v, ts_dpp<0x142, 0xA>(v));
-  v = min(v, ts_dpp<0x143, 0xC>(v));
+  v = ts_dpp_min<0xB1, 0xF>(v);
+  v = ts_dpp_min<0x4E, 0xF>(v);
+  v = ts_dpp_min<0x141, 0xF>(v);
+  v = ts_dpp_min<0x140, 0xF>(v);
+  v = ts_dpp_min<0x142, 0xA>(v);
+  v = ts_dpp_min<0x143, 0xC>(v);
   return __builtin_amdgcn_readlane(v, 63);
 }
+
 // Shared state of one node.
 struct TsShared {
   double l[2][TS_CPW][TS_ROWS];  // multipliers of the steps of a panel, by local row (two panels in flight)
@@ -90,7 +90,8 @@ struct TsShared {
 
 // x[c] -= l u_c for the register columns c in [C0, 8), u_c being column c of
 // the pivot row of the step (row = key & 255: lane row % 64, register row
-// row / 64, both wave-uniform; one branch on the register row).
+// row / 64, both wave-uniform; one branch on the register row: reading all
+// four register rows and selecting measured slower).
 template <int C0>
 __device__ __forceinline__ void ts_apply(double (&x)[TS_CPW][4], const double (&l)[4], int key) {
   if constexpr (C0 < TS_CPW) {
@@ -114,38 +115,68 @@ __device__ __forceinline__ void ts_apply(double (&x)[TS_CPW][4], const double (&
 
 // The pivot of step k on register column C (pos: the positions of the lane's
 // rows after step k - 1): the largest |x| over the rows at positions >= k,
-// ties to the smaller position (a wave maximum of |x|, then a wave minimum of
-// the keys of the rows that attain it), and the multipliers RN(x / p) of the
-// other live rows into l (zero for rows that are not eliminated). Publishes
-// the multipliers (ls), the key (ks) and the position swap; pos becomes the
-// positions after step k. Returns the key, or -1 (with zero multipliers, and
-// the failure flag set) if the column is not finite or, at the root, zero.
+// ties to the smaller position (a wave maximum over the bit patterns of |x|,
+// then the key of the row that attains it, or the wave minimum of the keys
+// when several do), and the multipliers RN(x / p) of the other live rows into
+// l (zero for rows that are not eliminated). Publishes the multipliers (ls),
+// the key (ks), the position swap and then the step's flag (fs = fv); pos
+// becomes the positions after step k. Returns the key, or -1 (with zero
+// multipliers, and the failure flag set) if the column is not finite or, at
+// the root, zero.
 template <int C>
 __device__ __forceinline__ int ts_pivot(double (&x)[TS_CPW][4], int (&pos)[4], double (&l)[4], double* ls, int* ks,
-                                        TsShared& sh, int k, int r, int lane, bool root, int32_t* info) {
-  double mag[4];
+                                        int* fs, int fv, TsShared& sh, int k, int r, int lane, bool root,
+                                        int32_t* info) {
+  // |x| compared through its bit pattern (the order of non-negative
+  // doubles): first the high words (a live row's plus one, zero for the
+  // others), then, only when several rows share the largest, the low words
+  unsigned hv[4], lo[4];
   bool live[4], bad = false;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     live[a] = (lane + 64 * a < r) & (pos[a] >= k);
-    mag[a] = live[a] ? fabs(x[C][a]) : -1.0;
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(x[C][a]));
+    hv[a] = live[a] ? (unsigned)(bits >> 32) + 1u : 0u;
+    lo[a] = (unsigned)bits;
     bad |= live[a] & !is_finite(x[C][a]);
   }
-  const double best = ts_wave_max(fmax(fmax(mag[0], mag[1]), fmax(mag[2], mag[3])));
-  // RN(1 / |p|), formed while the keys are reduced (RN(1 / -b) = -RN(1 / b))
-  const double yb = 1.0 / best;
-  // the rows attaining it: usually one (its key read from its lane), else
-  // the wave minimum of their keys
-  int kc[4], nbest = 0, lbest = 0;
+  const unsigned hm = ts_wave_umax(max(max(hv[0], hv[1]), max(hv[2], hv[3])));
+  bool cand[4];
+  int nc = 0, lw = 0;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    const unsigned long long at = __ballot(mag[a] == best);
-    nbest += __builtin_popcountll(at);
-    if (at != 0) lbest = __builtin_ctzll(at);
-    kc[a] = (mag[a] == best) ? ((pos[a] << 8) | (lane + 64 * a)) : INT_MAX;
+    cand[a] = hv[a] == hm;
+    const unsigned long long at = __ballot(cand[a]);
+    nc += __builtin_popcountll(at);
+    if (at != 0) lw = __builtin_ctzll(at);
   }
+  // common case first, without a taken branch (a taken branch costs a wave
+  // about as much as a dozen dependent instructions): one row has the
+  // largest high word; otherwise the low words of those rows decide
+  unsigned lm = (unsigned)__builtin_amdgcn_readlane((int)(cand[0] ? lo[0] : cand[1] ? lo[1] : cand[2] ? lo[2] : lo[3]), lw);
+  if (nc != 1) {
+    lm = ts_wave_umax(max(max(cand[0] ? lo[0] : 0u, cand[1] ? lo[1] : 0u),
+                          max(cand[2] ? lo[2] : 0u, cand[3] ? lo[3] : 0u)));
+    nc = 0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      cand[a] = cand[a] & (lo[a] == lm);
+      const unsigned long long at = __ballot(cand[a]);
+      nc += __builtin_popcountll(at);
+      if (at != 0) lw = __builtin_ctzll(at);
+    }
+  }
+  const double best = __longlong_as_double((long long)(((unsigned long long)(hm - 1u) << 32) | lm));
+  // RN(1 / |p|), formed while the keys are reduced (RN(1 / -b) = -RN(1 / b))
+  const double yb = 1.0 / best;
+  // the key of the row attaining it (read from its lane), or the wave
+  // minimum of the keys when several do
+  int kc[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) kc[a] = cand[a] ? ((pos[a] << 8) | (lane + 64 * a)) : INT_MAX;
   const int kl = min(min(kc[0], kc[1]), min(kc[2], kc[3]));
-  const int key = nbest == 1 ? __builtin_amdgcn_readlane(kl, lbest) : ts_wave_min(kl);
+  int key = __builtin_amdgcn_readlane(kl, lw);
+  if (nc != 1) key = ts_wave_min(kl);
   __asm__ volatile("" ::"v"(yb));  // keep the reciprocal ahead of the branch below
   const bool anybad = __ballot(bad) != 0;
   const bool zero = !(best > 0.0);
@@ -154,6 +185,7 @@ __device__ __forceinline__ int ts_pivot(double (&x)[TS_CPW][4], int (&pos)[4], d
       ts_info_set(info, anybad ? INFO_NONFINITE : INFO_LU_ZERO_PIVOT, STAGE_LU, k + 1);
       sh.fail = 1;
       *ks = -1;
+      *fs = fv;
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a) l[a] = 0.0;
@@ -175,26 +207,22 @@ __device__ __forceinline__ int ts_pivot(double (&x)[TS_CPW][4], int (&pos)[4], d
   const bool pneg = (neg >> pl) & 1;
   const int q = 64 * qa + __builtin_ctzll(atk);
   const double p = pneg ? -best : best;
-  if (lane == 0) *ks = key;
   // multipliers RN(x / p): Markstein's corrected quotient from one reciprocal
   // y = RN(1 / p), q0 = RN(x y), RN(q0 + (x - q0 p) y), the correctly rounded
   // quotient when y is normal (|x / p| <= 1); subnormal pivots and pivots
-  // above 1 / (smallest normal) divide directly. A zero pivot column (a
-  // singular block below the root) eliminates nothing.
+  // above 1 / (smallest normal) divide directly (rare: formed after the
+  // common case). A zero pivot column (a singular block below the root)
+  // eliminates nothing.
+  const double y = pneg ? -yb : yb;
   double qv[4];
-  if (zero) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a) qv[a] = 0.0;
-  } else if (best < 0x1p-1022 || best > 0x1p1022) {
+  for (int a = 0; a < 4; ++a) {
+    const double q0 = x[C][a] * y;
+    qv[a] = __builtin_fma(__builtin_fma(-q0, p, x[C][a]), y, q0);
+  }
+  if (zero || best < 0x1p-1022 || best > 0x1p1022) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a) qv[a] = x[C][a] / p;
-  } else {
-    const double y = pneg ? -yb : yb;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const double q0 = x[C][a] * y;
-      qv[a] = __builtin_fma(__builtin_fma(-q0, p, x[C][a]), y, q0);
-    }
+    for (int a = 0; a < 4; ++a) qv[a] = zero ? 0.0 : x[C][a] / p;
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
@@ -204,10 +232,13 @@ __device__ __forceinline__ int ts_pivot(double (&x)[TS_CPW][4], int (&pos)[4], d
     x[C][a] = elim ? qv[a] : x[C][a];
     ls[row] = l[a];
   }
-  // positions after step k: the pivot row moves to k, the row at k to its place
+  // one lane publishes the key, the position swap (the pivot row moves to k,
+  // the row at k to its place) and then the step's flag
   if (lane == 0) {
+    *ks = key;
     sh.posl[q] = ppos;
     sh.posl[prow] = k;
+    __hip_atomic_store(fs, fv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a) pos[a] = (lane + 64 * a == prow) ? k : (pos[a] == k ? ppos : pos[a]);
@@ -231,9 +262,9 @@ __device__ __forceinline__ void ts_panel(double (&x)[TS_CPW][4], int (&pos)[4], 
   // path through the registers.
 #define TS_PANEL_STEP(C)                                                                                    \
   if (TS_CPW * w + C < n) {                                                                                 \
-    const int key = ts_pivot<C>(x, pos, l, sh.l[b][C], &sh.key[b][C], sh, TS_CPW * w + C, r, lane, root, info); \
+    const int key = ts_pivot<C>(x, pos, l, sh.l[b][C], &sh.key[b][C], &sh.flag[b][C], w + 1, sh, TS_CPW * w + C, r, \
+                                lane, root, info);                                                          \
     ts_apply<C + 1>(x, l, key);                                                                             \
-    if (lane == 0) __hip_atomic_store(&sh.flag[b][C], w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); \
   }
   // the panel is the node's critical path: its wave issues first
   __builtin_amdgcn_s_setprio(3);
@@ -274,7 +305,7 @@ __device__ __forceinline__ void ts_follow(double (&x)[TS_CPW][4], const TsShared
 // Writes the original indices of its first n pivot rows to sel[g n ..]; the
 // root (one node) also writes N and L_11 (n x n, ld n).
 template <int NWV>
-__global__ __launch_bounds__(64 * NWV, NWV == 1 ? 2 : 4) void k_tslu_node(
+__global__ __launch_bounds__(64 * NWV, NWV >= 4 ? 4 : NWV) void k_tslu_node(
     const double* __restrict__ X, int64_t ldx, int64_t m, int n, int64_t leaves, const int32_t* __restrict__ prev,
     int64_t nsets, int F, int32_t* __restrict__ sel, double* __restrict__ Nout, double* __restrict__ Lout,
     int32_t* info) {
@@ -314,14 +345,17 @@ __global__ __launch_bounds__(64 * NWV, NWV == 1 ? 2 : 4) void k_tslu_node(
 #pragma unroll
   for (int a = 0; a < 4; ++a) pos[a] = lane + 64 * a;
   const int np = (n + TS_CPW - 1) / TS_CPW;  // panels
-  if (wave == 0) ts_panel(x, pos, sh, 0, n, r, lane, root, info);
-  for (int j = 0; j < np; ++j) {
-    __syncthreads();  // panel j published
-    if (sh.fail) return;
+  // j = -1: wave 0 eliminates panel 0 (one copy of the panel code for all
+  // panels keeps the kernel's instructions few)
+  for (int j = -1; j < np; ++j) {
+    if (j >= 0) {
+      __syncthreads();  // panel j published
+      if (sh.fail) return;
+    }
     if (wave > j && TS_CPW * wave < n) {
       // the steps of panel j on this wave's columns, in step order (the wave
-      // of panel j + 1 applied them while they were published, from j = 1)
-      if (wave != j + 1 || j == 0) {
+      // of panel j + 1 applied them while they were published)
+      if (j >= 0 && wave != j + 1) {
 #pragma unroll 1
         for (int c = 0; c < TS_CPW && TS_CPW * j + c < n; ++c) ts_follow(x, sh, j, c, lane);
       }

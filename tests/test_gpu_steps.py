@@ -480,6 +480,23 @@ def test_tournament_lu_matches_oracle(m, n, kappa):
     assert np.all(np.abs(m_h @ N_o - x) <= bound + 1e-300)
 
 
+@pytest.mark.parametrize("kind", ["integers", "shared_high_word"])
+def test_tournament_lu_ties(kind):
+    # equal magnitudes decide by position: small integers tie exactly; entries
+    # 1 + e 2^-40 share the high word of their bit pattern and differ below it
+    rng = np.random.default_rng(11)
+    m, n = 3000 + 5, 24
+    e = rng.integers(-40, 41, size=(m, n)).astype(np.float64)
+    x = np.asfortranarray(e if kind == "integers" else 1.0 + e * 2.0**-40)
+    M, sel, N, info = _lib().tall_lu_tournament(to_dev(x))
+    sel_o, N_o, L_o, _, info_o = oracle.tslu(x)
+    assert info.cpu().tolist()[0] == 0 and info_o[0] == 0
+    sel_h = sel.cpu().numpy()
+    np.testing.assert_array_equal(sel_h, sel_o)
+    np.testing.assert_array_equal(to_host(N), N_o)
+    np.testing.assert_array_equal(to_host(M)[sel_h], L_o)
+
+
 def test_tournament_lu_singular_leaf_and_zero_column():
     m, n = 2048, 12
     x = make_svd(m, n, 1e3, seed=7)
