@@ -220,21 +220,23 @@ def gpu_accuracy(X, Q, R):
 class Runner:
     """Q, R, outcome record and workspace for repeated calls on one input."""
 
-    def __init__(self, lib, X, alg, s, seed, sketch_prec="fp64", lu_prec="fp64", sketch="gaussian"):
+    def __init__(self, lib, X, alg, s, seed, sketch_prec="fp64", lu_prec="fp64", sketch="gaussian",
+                 tall_lu="partial"):
         import torch
         m, n = X.shape
         self.lib, self.X, self.alg, self.s, self.seed = lib, X, alg, s, seed
-        self.sp, self.lp, self.kind = sketch_prec, lu_prec, sketch
+        self.sp, self.lp, self.kind, self.tl = sketch_prec, lu_prec, sketch, tall_lu
         self.stream = torch.cuda.current_stream()
         self.Q = torch.empty((n, m), dtype=torch.float64, device=X.device).t()
         self.R = torch.empty((n, n), dtype=torch.float64, device=X.device).t()
         self.info = torch.zeros(4, dtype=torch.int32, device=X.device)
-        self.ws = torch.empty(max(lib.workspace_size(alg, m, n, s, sketch_prec, lu_prec, sketch), 256),
+        self.ws = torch.empty(max(lib.workspace_size(alg, m, n, s, sketch_prec, lu_prec, sketch, tall_lu=tall_lu), 256),
                               dtype=torch.uint8, device=X.device)
 
     def __call__(self):
         self.lib.qr(self.X, alg=self.alg, s=self.s, seed=self.seed, sketch_prec=self.sp, lu_prec=self.lp, Q=self.Q,
-                    R=self.R, workspace=self.ws, info=self.info, stream=self.stream, sketch=self.kind)
+                    R=self.R, workspace=self.ws, info=self.info, stream=self.stream, sketch=self.kind,
+                    tall_lu=self.tl)
 
     def time(self, reps, warmup=1):
         import torch
@@ -348,10 +350,11 @@ def bench_c2(lib, steps=10, with_cpu=True, copy_calibration=False):
            "stages_ms_per_step": {k: round(v[0] / steps, 5) for k, v in stages.items()},
            "roofline": roofline_entry(stages, m, n, s, workload="c2"), "stage_rates": stage_rates(stages, m, n, s)}
     other = {}
-    for alg in ("rcluppr", "cholqr2", "scholqr3", "lc2", "rcholqr"):
-        o = Runner(lib, X, alg, s, SEED)
+    for alg, tl in (("rcluppr", "partial"), ("cholqr2", "partial"), ("scholqr3", "partial"), ("lc2", "partial"),
+                    ("rcholqr", "partial"), ("rcluppr", "tournament"), ("lc2", "tournament")):
+        o = Runner(lib, X, alg, s, SEED, tall_lu=tl)
         t = o.time(max(2, steps // 4))
-        other[alg] = {"ms": round(t, 4), "info": o.info_host()}
+        other[alg if tl == "partial" else alg + "_tournament"] = {"ms": round(t, 4), "info": o.info_host()}
         del o
     out["other_methods_ms"] = other
     if with_cpu:
@@ -442,6 +445,15 @@ def bench_krylov(lib):
     ms2 = run.time(1)
     orth2, res2 = gpu_accuracy(X, run.Q, run.R)
     out["mixed_bf16_sketch_fp32_lu"] = {"ms": round(ms2, 3), "info": run.info_host(), "orth": orth2, "rel_res": res2}
+    del run
+    torch.cuda.empty_cache()
+    # tournament pivoting for the LU of X (TSLU tree, then M = X N^{-1})
+    run = Runner(lib, X, "rcluppr", s, SEED, tall_lu="tournament")
+    ms3 = run.time(1)
+    st3 = run.trace(1)
+    orth3, res3 = gpu_accuracy(X, run.Q, run.R)
+    out["tournament_lu"] = {"ms": round(ms3, 3), "info": run.info_host(), "orth": orth3, "rel_res": res3,
+                            "tall_lu_ms": round(st3["tall_lu"][0], 3) if "tall_lu" in st3 else None}
     return out
 
 
