@@ -508,3 +508,30 @@ def test_full_size_rclupp(kappa):
         torch.cuda.synchronize()
         method_parity(x, method, s, 0, kappa, res)
         del res
+
+
+@pytest.mark.parametrize("method,kappa,lu", [("cholqr2", 1e6, "partial"), ("scholqr3", 1e12, "partial"),
+                                             ("lc2", 1e15, "partial"), ("rcholqr", 1e15, "partial"),
+                                             ("lc2", 1e15, "tournament"), ("rcluppr", 1e15, "tournament")])
+def test_full_size_other_methods(method, kappa, lu):
+    # the baselines and the tournament-pivoting forms on the 1,048,576 x 64
+    # workload (s = 128, seed 0), each inside its range, against the oracle
+    m, n, s = 1 << 20, 64, 128
+    x = make_svd(m, n, kappa, seed=0)
+    sk = s if method in ("rcluppr", "rcholqr") else None
+    res = _lib().qr(to_dev(x), alg=method, s=sk, seed=0, tall_lu=lu)
+    torch.cuda.synchronize()
+    method_parity(x, method, sk, 0, kappa, res, orc=oracle.run(method, x, s=sk, seed=0, lu=lu))
+
+
+@pytest.mark.parametrize("method", ["cholqr2", "scholqr3"])
+def test_full_size_breakdown_like_oracle(method):
+    # at kappa = 1e15 both Cholesky-based baselines leave their range; the
+    # device reports the breakdown as the oracle does (code and stage)
+    m, n = 1 << 20, 64
+    x = make_svd(m, n, 1e15, seed=0)
+    orc = oracle.run(method, x)
+    info = _lib().qr(to_dev(x), alg=method).info_host()
+    assert not orc.ok
+    assert info[0] == orc.info[0] == oracle.CHOL_BREAKDOWN and info[1] == orc.info[1]
+
