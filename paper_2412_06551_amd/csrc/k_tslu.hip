@@ -468,14 +468,24 @@ static size_t tslu_al(size_t b) { return (b + 255) / 256 * 256; }
 
 static bool tslu_forward(int64_t n) { return n > 64; }
 
+// The sizes of the forwarded rows of the first and second merge levels (the
+// leaves do not forward: the first merge level gathers 2n rows from two
+// neighbouring 256-row blocks of X, nearly as fast as the leaves read theirs,
+// and writing the leaves' candidates cost more than it saved).
+static size_t tslu_fwd_bytes(int64_t m, int64_t n, int level) {
+  if (!tslu_forward(n)) return 0;
+  const int64_t F = TS_ROWS / n;
+  int64_t nodes = tslu_leaves(m);
+  for (int l = 0; l < level; ++l) nodes = (nodes + F - 1) / F;
+  return (size_t)nodes * n * n * sizeof(double);
+}
+
 size_t tslu_scratch_bytes(int64_t m, int64_t n) {
-  // candidate sets of two consecutive levels (indices, and for n > 64 their
-  // rows of X: the leaves' output and the first merge level's), N and L_11,
-  // the padded N
-  const int64_t leaves = tslu_leaves(m), F = TS_ROWS / n;
+  // candidate sets of two consecutive levels (indices, and for n > 64 the
+  // rows of X of the merge levels' candidates), N and L_11, the padded N
+  const int64_t leaves = tslu_leaves(m);
   const size_t sets = (size_t)leaves * n * sizeof(int32_t);
-  const size_t c0 = tslu_forward(n) ? (size_t)leaves * n * n * sizeof(double) : 0;
-  const size_t c1 = tslu_forward(n) ? (size_t)((leaves + F - 1) / F) * n * n * sizeof(double) : 0;
+  const size_t c0 = tslu_fwd_bytes(m, n, 1), c1 = tslu_fwd_bytes(m, n, 2);
   const int np = pad_cols(n);
   return 2 * tslu_al(sets) + tslu_al(c0) + tslu_al(c1) + 2 * tslu_al((size_t)n * n * 8) +
          tslu_al(padded_r_doubles(np) * 8);
@@ -488,8 +498,7 @@ hipError_t launch_tslu(const double* X, int64_t m, int64_t n, int64_t ldx, doubl
   const int F = TS_ROWS / (int)n;
   const size_t sets = tslu_al((size_t)leaves * n * sizeof(int32_t));
   const bool fwd = tslu_forward(n);
-  const size_t c0 = fwd ? tslu_al((size_t)leaves * n * n * sizeof(double)) : 0;
-  const size_t c1 = fwd ? tslu_al((size_t)((leaves + F - 1) / F) * n * n * sizeof(double)) : 0;
+  const size_t c0 = tslu_al(tslu_fwd_bytes(m, n, 1)), c1 = tslu_al(tslu_fwd_bytes(m, n, 2));
   char* sp = (char*)scratch;
   int32_t* lv[2] = {(int32_t*)sp, (int32_t*)(sp + sets)};
   double* cv[2] = {(double*)(sp + 2 * sets), (double*)(sp + 2 * sets + c0)};
@@ -517,19 +526,23 @@ hipError_t launch_tslu(const double* X, int64_t m, int64_t n, int64_t ldx, doubl
   };
   // leaves, then levels of F-way merges until one set is left (the root
   // writes N and L_11; the final candidates go to `sel`)
-  // (the candidates' rows of X: the leaves' in cv[0], then alternately in
-  // cv[1] and cv[0], each level's output smaller than its buffer)
+  // (the merge levels' candidates' rows of X: the first level's in cv[0],
+  // then alternately in cv[1] and cv[0], each level's output no larger than
+  // its buffer; the first merge level gathers from X)
   int cur = 0;
-  hipError_t e = node(leaves, nullptr, 0, leaves == 1 ? sel : lv[cur], nullptr, leaves == 1 || !fwd ? nullptr : cv[0]);
+  hipError_t e = node(leaves, nullptr, 0, leaves == 1 ? sel : lv[cur], nullptr, nullptr);
   if (e != hipSuccess) return e;
   int64_t nsets = leaves;
+  int level = 1;
   while (nsets > 1) {
     const int64_t nodes = (nsets + F - 1) / F;
-    e = node(nodes, lv[cur], nsets, nodes == 1 ? sel : lv[cur ^ 1], fwd ? cv[cur] : nullptr,
-             nodes == 1 || !fwd ? nullptr : cv[cur ^ 1]);
+    const double* cin = (fwd && level >= 2) ? cv[level & 1] : nullptr;
+    double* cout = (fwd && nodes > 1) ? cv[(level + 1) & 1] : nullptr;
+    e = node(nodes, lv[cur], nsets, nodes == 1 ? sel : lv[cur ^ 1], cin, cout);
     if (e != hipSuccess) return e;
     cur ^= 1;
     nsets = nodes;
+    ++level;
   }
   // W = X N^{-1} (row-wise substitution on the tall kernels), then the pivot rows
   e = launch_pad(Nt, n, Npad, st);
