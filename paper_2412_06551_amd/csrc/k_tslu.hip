@@ -86,7 +86,9 @@ struct TsShared {
   int flag[2][TS_CPW];           // p + 1 once step c of panel p is published
   int posl[TS_ROWS];             // position of each local row
   int rowat[TS_ROWS];            // local row at each of the first n positions (at the end)
-  int fail;                      // set when a pivot fails (or the stage had failed before)
+  int fail[2];                   // failure seen after the barrier that publishes panel p, in slot p % 2
+                                 // (set during the window before it, read after it: no wave reads a
+                                 // slot while another may still set it)
 };
 
 // x[c] -= l u_c for the register columns c in [C0, 8), u_c being column c of
@@ -184,7 +186,7 @@ __device__ __forceinline__ int ts_pivot(double (&x)[TS_CPW][4], int (&pos)[4], d
   if (anybad || (zero && root)) {
     if (lane == 0) {
       ts_info_set(info, anybad ? INFO_NONFINITE : INFO_LU_ZERO_PIVOT, STAGE_LU, k + 1);
-      sh.fail = 1;
+      sh.fail[(k / TS_CPW) & 1] = 1;
       *ks = -1;
       *fs = fv;
     }
@@ -252,7 +254,6 @@ __device__ __forceinline__ int ts_pivot(double (&x)[TS_CPW][4], int (&pos)[4], d
 // w % 2 (multipliers, key, then the step's flag: the LDS executes one wave's
 // accesses in issue order, so a wave that reads the flag and then the step
 // sees the step; no wait for the writes is needed before the flag).
-// Returns false if a pivot failed.
 __device__ __forceinline__ void ts_panel(double (&x)[TS_CPW][4], int (&pos)[4], TsShared& sh, int w, int n, int r,
                                          int lane, bool root, int32_t* info) {
   const int b = w & 1;
@@ -317,11 +318,11 @@ __global__ __launch_bounds__(64 * NWV, NWV >= 4 ? 4 : NWV) void k_tslu_node(
     double* __restrict__ Nout, double* __restrict__ Lout, int32_t* info) {
   __shared__ TsShared sh;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid == 0) sh.fail = info_failed(info) ? 1 : 0;
+  if (tid == 0) sh.fail[0] = sh.fail[1] = info_failed(info) ? 1 : 0;
   for (int i = tid; i < TS_ROWS; i += 64 * NWV) sh.posl[i] = i;
   for (int i = tid; i < 2 * TS_CPW; i += 64 * NWV) sh.flag[i / TS_CPW][i % TS_CPW] = 0;
   __syncthreads();
-  if (sh.fail) return;
+  if (sh.fail[0]) return;
   const int64_t g = blockIdx.x;
   const bool root = gridDim.x == 1;
   // local row i is X's row r0 + i (leaves) or prev[s0 n + i] (upper levels)
@@ -364,7 +365,7 @@ __global__ __launch_bounds__(64 * NWV, NWV >= 4 ? 4 : NWV) void k_tslu_node(
   for (int j = -1; j < np; ++j) {
     if (j >= 0) {
       __syncthreads();  // panel j published
-      if (sh.fail) return;
+      if (sh.fail[j & 1]) return;
     }
     if (wave > j && TS_CPW * wave < n) {
       // the steps of panel j on this wave's columns, in step order (the wave
@@ -392,7 +393,7 @@ __global__ __launch_bounds__(64 * NWV, NWV >= 4 ? 4 : NWV) void k_tslu_node(
           if (spins > (1u << 22)) {
             if (lane == 0) {
               ts_info_set(info, INFO_SYNC_TIMEOUT, STAGE_LU, TS_CPW * (j + 1) + c + 1);
-              sh.fail = 1;
+              sh.fail[(j + 1) & 1] = 1;
             }
             break;
           }
@@ -402,7 +403,7 @@ __global__ __launch_bounds__(64 * NWV, NWV >= 4 ? 4 : NWV) void k_tslu_node(
     }
   }
   __syncthreads();
-  if (sh.fail) return;
+  if (sh.fail[0] | sh.fail[1]) return;
   if (wave == 0) {
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
