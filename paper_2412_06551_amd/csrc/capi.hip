@@ -1530,8 +1530,8 @@ int rclupp_trsm_gram(const double* X, int64_t m, int64_t n, int64_t ldx, const d
     double* gpart = (double*)(p + rb);
     double* gfull = (double*)(p + rb + align_up(tp.part_bytes));
     if (R && launch_pad(R, n, rpad, stream) != hipSuccess) return (int)RCLUPP_ERR_HIP;
-    // the n <= 64 substitution kernel always forms the Gram partials as well
-    if (launch_tall_pass(tp, X, ldx, m, n, R ? rpad : nullptr, W, W ? ldw : ldx, (G || R) ? gpart : nullptr, nullptr,
+    // (the Gram partials only when G is asked for: a solve alone skips the Gram)
+    if (launch_tall_pass(tp, X, ldx, m, n, R ? rpad : nullptr, W, W ? ldw : ldx, G ? gpart : nullptr, nullptr,
                          stream) != hipSuccess)
       return (int)RCLUPP_ERR_HIP;
     if (G) {

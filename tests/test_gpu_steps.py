@@ -358,6 +358,17 @@ def test_trsm_in_place_and_ld():
     _check_trsm(to_host(X), wo, x, R)
 
 
+@pytest.mark.parametrize("n", [16, 100, 256])
+def test_trsm_without_gram(n):
+    # the solve alone (no Gram asked for) on each kernel family
+    m = 3000 + 7
+    x = np.asfortranarray(np.random.default_rng(n).standard_normal((m, n)))
+    R = _upper(n, 3)
+    W, G = _lib().trsm_gram(to_dev(x), to_dev(R), gram=False)
+    assert G is None
+    _check_trsm(to_host(W), oracle.trsm(x, R), x, R)
+
+
 @pytest.mark.parametrize("n", [32, 64, 128, 200])
 @pytest.mark.parametrize("layout", ["ld16", "ld_odd", "base_off"])
 def test_trsm_gram_layouts(n, layout):
