@@ -77,9 +77,10 @@ typedef enum {
   RCLUPP_INFO_CHOL_BREAKDOWN = 2, /* a Cholesky pivot was not > 0                          */
   RCLUPP_INFO_NONFINITE = 3,      /* the input of a small factorization held NaN or Inf    */
   RCLUPP_INFO_SINGULAR = 4,       /* the preconditioner R_1 has an exactly zero diagonal   */
-  RCLUPP_INFO_SYNC_TIMEOUT = 5    /* a grid-wide step barrier of the multi-workgroup small
-                                     factorization did not complete within its bounded wait
-                                     (should not happen; the kernel exits rather than hang) */
+  RCLUPP_INFO_SYNC_TIMEOUT = 5    /* a bounded wait did not complete: a step of the
+                                     multi-workgroup small factorization, or a panel inside
+                                     a tournament-pivoting node (should not happen; the
+                                     kernel exits rather than hang) */
 } rclupp_info_code;
 
 /* Stage = the role of the failing small factorization in the pipeline. */
@@ -138,7 +139,12 @@ typedef struct {
  *     first n pivot rows; floor(256 / n) sets merge per node); N and the unit
  *     lower L_11 come from the root; M = P X N^{-1} is one substitution pass
  *     and is kept in X's row order (RCLUPPr's sketch then sees M through a
- *     column permutation of S, a Gaussian matrix of the same distribution). */
+ *     column permutation of S, a Gaussian matrix of the same distribution).
+ *     Its workspace (rclupp_workspace_size) holds, for n > 64, the candidate
+ *     rows of the first two merge levels: about (1 + 1/F) (m / 256) n^2 / F
+ *     doubles with F = floor(256 / n), 6.4 GB at m = 16,777,216, n = 128.
+ *     A node that waits longer than its bounded wait for the previous panel
+ *     reports RCLUPP_INFO_SYNC_TIMEOUT (stage LU) rather than hang. */
 #define RCLUPP_TALL_LU_PARTIAL 0
 #define RCLUPP_TALL_LU_TOURNAMENT 1
 
