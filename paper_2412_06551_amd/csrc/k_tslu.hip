@@ -82,7 +82,7 @@ __device__ __forceinline__ int ts_wave_min(int v) {
 // Shared state of one node.
 struct TsShared {
   double l[2][TS_CPW][TS_ROWS];  // multipliers of the steps of a panel, by local row (two panels in flight)
-  int key[2][TS_CPW];            // pivots of those steps: (position << 8) | row
+  int key[2][TS_CPW];            // pivots of those steps: (position << 9) | (sign << 8) | row
   int flag[2][TS_CPW];           // p + 1 once step c of panel p is published
   int posl[TS_ROWS];             // position of each local row
   int rowat[TS_ROWS];            // local row at each of the first n positions (at the end)
@@ -143,6 +143,20 @@ __device__ __forceinline__ int ts_pivot(double (&x)[TS_CPW][4], int (&pos)[4], d
     lo[a] = (unsigned)bits;
     bad |= live[a] & !is_finite(x[C][a]);
   }
+  // independent of the pivot, so formed beside the reductions below: the
+  // row now at position k, and whether any live entry is not finite
+  unsigned long long atk = 0;
+  int qa = 0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const unsigned long long bk = __ballot(pos[a] == k);
+    if (bk != 0) {
+      atk = bk;
+      qa = a;
+    }
+  }
+  const int q = 64 * qa + __builtin_ctzll(atk);
+  const bool anybad = __ballot(bad) != 0;
   const unsigned hm = ts_wave_umax(max(max(hv[0], hv[1]), max(hv[2], hv[3])));
   bool cand[4];
   int nc = 0, lw = 0;
@@ -157,7 +171,7 @@ __device__ __forceinline__ int ts_pivot(double (&x)[TS_CPW][4], int (&pos)[4], d
   // about as much as a dozen dependent instructions): one row has the
   // largest high word; otherwise the low words of those rows decide
   unsigned lm = (unsigned)__builtin_amdgcn_readlane((int)(cand[0] ? lo[0] : cand[1] ? lo[1] : cand[2] ? lo[2] : lo[3]), lw);
-  if (nc != 1) {
+  if (__builtin_expect(nc != 1, 0)) {
     lm = ts_wave_umax(max(max(cand[0] ? lo[0] : 0u, cand[1] ? lo[1] : 0u),
                           max(cand[2] ? lo[2] : 0u, cand[3] ? lo[3] : 0u)));
     nc = 0;
@@ -173,17 +187,18 @@ __device__ __forceinline__ int ts_pivot(double (&x)[TS_CPW][4], int (&pos)[4], d
   // RN(1 / |p|), formed while the keys are reduced (RN(1 / -b) = -RN(1 / b))
   const double yb = 1.0 / best;
   // the key of the row attaining it (read from its lane), or the wave
-  // minimum of the keys when several do
+  // minimum of the keys when several do; the key carries the entry's sign
+  // below the position, which decides nothing (positions are distinct)
   int kc[4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a) kc[a] = cand[a] ? ((pos[a] << 8) | (lane + 64 * a)) : INT_MAX;
+  for (int a = 0; a < 4; ++a)
+    kc[a] = cand[a] ? ((pos[a] << 9) | ((x[C][a] < 0.0) << 8) | (lane + 64 * a)) : INT_MAX;
   const int kl = min(min(kc[0], kc[1]), min(kc[2], kc[3]));
   int key = __builtin_amdgcn_readlane(kl, lw);
-  if (nc != 1) key = ts_wave_min(kl);
+  if (__builtin_expect(nc != 1, 0)) key = ts_wave_min(kl);
   __asm__ volatile("" ::"v"(yb));  // keep the reciprocal ahead of the branch below
-  const bool anybad = __ballot(bad) != 0;
   const bool zero = !(best > 0.0);
-  if (anybad || (zero && root)) {
+  if (__builtin_expect(anybad || (zero && root), 0)) {
     if (lane == 0) {
       ts_info_set(info, anybad ? INFO_NONFINITE : INFO_LU_ZERO_PIVOT, STAGE_LU, k + 1);
       sh.fail[(k / TS_CPW) & 1] = 1;
@@ -194,21 +209,8 @@ __device__ __forceinline__ int ts_pivot(double (&x)[TS_CPW][4], int (&pos)[4], d
     for (int a = 0; a < 4; ++a) l[a] = 0.0;
     return -1;
   }
-  const int prow = key & 255, ppos = key >> 8, pa = prow >> 6, pl = prow & 63;
-  // the pivot's sign, and the row now at position k, from wave ballots
-  unsigned long long neg = 0, atk = 0;
-  int qa = 0;
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const unsigned long long bn = __ballot(x[C][a] < 0.0), bk = __ballot(pos[a] == k);
-    neg = (a == pa) ? bn : neg;
-    if (bk != 0) {
-      atk = bk;
-      qa = a;
-    }
-  }
-  const bool pneg = (neg >> pl) & 1;
-  const int q = 64 * qa + __builtin_ctzll(atk);
+  const int prow = key & 255, ppos = key >> 9;
+  const bool pneg = (key >> 8) & 1;
   const double p = pneg ? -best : best;
   // multipliers RN(x / p): Markstein's corrected quotient from one reciprocal
   // y = RN(1 / p), q0 = RN(x y), RN(q0 + (x - q0 p) y), the correctly rounded
@@ -223,7 +225,7 @@ __device__ __forceinline__ int ts_pivot(double (&x)[TS_CPW][4], int (&pos)[4], d
     const double q0 = x[C][a] * y;
     qv[a] = __builtin_fma(__builtin_fma(-q0, p, x[C][a]), y, q0);
   }
-  if (zero || best < 0x1p-1022 || best > 0x1p1022) {
+  if (__builtin_expect(zero || best < 0x1p-1022 || best > 0x1p1022, 0)) {
 #pragma unroll
     for (int a = 0; a < 4; ++a) qv[a] = zero ? 0.0 : x[C][a] / p;
   }
