@@ -158,15 +158,19 @@ __device__ __forceinline__ int ts_pivot(double (&x)[TS_CPW][4], int (&pos)[4], d
   const int q = 64 * qa + __builtin_ctzll(atk);
   const bool anybad = __ballot(bad) != 0;
   const unsigned hm = ts_wave_umax(max(max(hv[0], hv[1]), max(hv[2], hv[3])));
+  // nc rows attain it; lw is the lane of one of them (of the only one when
+  // nc = 1)
   bool cand[4];
-  int nc = 0, lw = 0;
+  int nc = 0;
+  unsigned long long anyc = 0;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     cand[a] = hv[a] == hm;
     const unsigned long long at = __ballot(cand[a]);
     nc += __builtin_popcountll(at);
-    if (at != 0) lw = __builtin_ctzll(at);
+    anyc |= at;
   }
+  int lw = __builtin_ctzll(anyc);
   // common case first, without a taken branch (a taken branch costs a wave
   // about as much as a dozen dependent instructions): one row has the
   // largest high word; otherwise the low words of those rows decide
@@ -175,13 +179,15 @@ __device__ __forceinline__ int ts_pivot(double (&x)[TS_CPW][4], int (&pos)[4], d
     lm = ts_wave_umax(max(max(cand[0] ? lo[0] : 0u, cand[1] ? lo[1] : 0u),
                           max(cand[2] ? lo[2] : 0u, cand[3] ? lo[3] : 0u)));
     nc = 0;
+    anyc = 0;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       cand[a] = cand[a] & (lo[a] == lm);
       const unsigned long long at = __ballot(cand[a]);
       nc += __builtin_popcountll(at);
-      if (at != 0) lw = __builtin_ctzll(at);
+      anyc |= at;
     }
+    lw = __builtin_ctzll(anyc);
   }
   const double best = __longlong_as_double((long long)(((unsigned long long)(hm - 1u) << 32) | lm));
   // RN(1 / |p|), formed while the keys are reduced (RN(1 / -b) = -RN(1 / b))
@@ -195,10 +201,17 @@ __device__ __forceinline__ int ts_pivot(double (&x)[TS_CPW][4], int (&pos)[4], d
     kc[a] = cand[a] ? ((pos[a] << 9) | ((x[C][a] < 0.0) << 8) | (lane + 64 * a)) : INT_MAX;
   const int kl = min(min(kc[0], kc[1]), min(kc[2], kc[3]));
   int key = __builtin_amdgcn_readlane(kl, lw);
-  if (__builtin_expect(nc != 1, 0)) key = ts_wave_min(kl);
-  __asm__ volatile("" ::"v"(yb));  // keep the reciprocal ahead of the branch below
+  // the tests of the rare cases below (a failure; a pivot the corrected
+  // quotient does not cover)
   const bool zero = !(best > 0.0);
-  if (__builtin_expect(anybad || (zero && root), 0)) {
+  const bool failed = anybad || (zero && root);
+  const bool odd = zero || best < 0x1p-1022 || best > 0x1p1022;
+  // the reciprocal, the key and those tests are independent chains: keep
+  // them in one block, ahead of the branches below, so that their latencies
+  // overlap
+  __asm__ volatile("" ::"v"(yb), "s"((int)failed | ((int)odd << 1)));
+  if (__builtin_expect(nc != 1, 0)) key = ts_wave_min(kl);
+  if (__builtin_expect(failed, 0)) {
     if (lane == 0) {
       ts_info_set(info, anybad ? INFO_NONFINITE : INFO_LU_ZERO_PIVOT, STAGE_LU, k + 1);
       sh.fail[(k / TS_CPW) & 1] = 1;
@@ -225,7 +238,7 @@ __device__ __forceinline__ int ts_pivot(double (&x)[TS_CPW][4], int (&pos)[4], d
     const double q0 = x[C][a] * y;
     qv[a] = __builtin_fma(__builtin_fma(-q0, p, x[C][a]), y, q0);
   }
-  if (__builtin_expect(zero || best < 0x1p-1022 || best > 0x1p1022, 0)) {
+  if (__builtin_expect(odd, 0)) {
 #pragma unroll
     for (int a = 0; a < 4; ++a) qv[a] = zero ? 0.0 : x[C][a] / p;
   }
