@@ -171,9 +171,9 @@ __device__ __forceinline__ int ts_pivot(double (&x)[TS_CPW][4], int (&pos)[4], d
     anyc |= at;
   }
   int lw = __builtin_ctzll(anyc);
-  // common case first, without a taken branch (a taken branch costs a wave
-  // about as much as a dozen dependent instructions): one row has the
-  // largest high word; otherwise the low words of those rows decide
+  // common case first: one row has the largest high word; otherwise the low
+  // words of those rows decide, behind a branch laid out of line (a taken
+  // branch costs a wave about as much as a dozen dependent instructions)
   unsigned lm = (unsigned)__builtin_amdgcn_readlane((int)(cand[0] ? lo[0] : cand[1] ? lo[1] : cand[2] ? lo[2] : lo[3]), lw);
   if (__builtin_expect(nc != 1, 0)) {
     lm = ts_wave_umax(max(max(cand[0] ? lo[0] : 0u, cand[1] ? lo[1] : 0u),
