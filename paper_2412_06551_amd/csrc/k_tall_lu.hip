@@ -84,9 +84,19 @@ __global__ __launch_bounds__(LU_THREADS) void k_lu_init(const double* __restrict
   double best = -1.0;
   int idx = INT_MAX, bad = 0;
   for (int64_t i = (int64_t)blockIdx.x * LU_THREADS + threadIdx.x; i < m; i += (int64_t)gridDim.x * LU_THREADS) {
-    for (int j = 0; j < n; ++j) M[i + j * ldm] = X[i + j * ldx];
+    // eight columns at a time, so that eight loads are in flight per thread
+    const double x0 = X[i];
+    int j = 0;
+    for (; j + 8 <= n; j += 8) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = X[i + (int64_t)(j + q) * ldx];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) M[i + (int64_t)(j + q) * ldm] = v[q];
+    }
+    for (; j < n; ++j) M[i + (int64_t)j * ldm] = X[i + (int64_t)j * ldx];
     perm[i] = (int32_t)i;
-    track(M[i], i, best, idx, bad);
+    track(x0, i, best, idx, bad);
   }
   wg_argmax_write(best, idx, bad, part + blockIdx.x);
 }
@@ -180,12 +190,20 @@ __global__ __launch_bounds__(LU_THREADS) void k_lu_panel(double* __restrict__ M,
   int idx = INT_MAX, bad = 0;
   for (int64_t i = (int64_t)k + 1 + (int64_t)blockIdx.x * LU_THREADS + threadIdx.x; i < m;
        i += (int64_t)gridDim.x * LU_THREADS) {
-    const double l = M[i + (int64_t)k * ldm] / piv;
+    // the row's columns k .. c1 - 1 of the panel (at most LU_NB) are read
+    // before any is written, so that their loads are in flight together
+    double v[LU_NB];
+#pragma unroll
+    for (int q = 0; q < LU_NB; ++q) v[q] = (k + q < c1) ? M[i + (int64_t)(k + q) * ldm] : 0.0;
+    const double l = v[0] / piv;
     M[i + (int64_t)k * ldm] = l;
-    for (int j = k + 1; j < c1; ++j) {
-      const double a = M[i + (int64_t)j * ldm] - l * prow[j];
-      M[i + (int64_t)j * ldm] = a;
-      if (j == k + 1) track(a, i, best, idx, bad);
+#pragma unroll
+    for (int q = 1; q < LU_NB; ++q) {
+      if (k + q < c1) {
+        const double a = v[q] - l * prow[k + q];
+        M[i + (int64_t)(k + q) * ldm] = a;
+        if (q == 1) track(a, i, best, idx, bad);
+      }
     }
   }
   if (want_next) wg_argmax_write(best, idx, bad, part + blockIdx.x);
@@ -223,8 +241,8 @@ __global__ __launch_bounds__(LU_THREADS) void k_lu_trailing(double* __restrict__
     double l[LU_NB];
 #pragma unroll
     for (int t = 0; t < LU_NB; ++t) l[t] = (t < nb) ? M[i + (int64_t)(c0 + t) * ldm] : 0.0;
-    // column 0 first (its argmax partial), then four columns at a time so that
-    // four loads are in flight per thread
+    // column 0 first (its argmax partial), then eight (then four) columns
+    // at a time so that eight loads are in flight per thread
     {
       double a = M[i + (int64_t)c1 * ldm];
 #pragma unroll
@@ -234,6 +252,18 @@ __global__ __launch_bounds__(LU_THREADS) void k_lu_trailing(double* __restrict__
       track(a, i, best, idx, bad);
     }
     int j = 1;
+    for (; j + 7 < nt; j += 8) {
+      double a[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] = __builtin_nontemporal_load(M + i + (int64_t)(c1 + j + q) * ldm);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+#pragma unroll
+        for (int t = 0; t < LU_NB; ++t)
+          if (t < nb) a[q] -= l[t] * u[t + (j + q) * nb];
+        __builtin_nontemporal_store(a[q], M + i + (int64_t)(c1 + j + q) * ldm);
+      }
+    }
     for (; j + 3 < nt; j += 4) {
       double a[4];
 #pragma unroll
