@@ -8,8 +8,15 @@
 //   per panel: U12 = L11^{-1} A12 (one workgroup), then the trailing update
 //     A22 -= L21 U12 streams every row once and records the argmax partial of
 //     the next panel's first column.
-// The per-step update order equals that of the unblocked algorithm (the
-// trailing columns receive the panel's rank-1 updates in column order).
+// Two levels of panels: the 8-column panels update only the columns of their
+// LU_OB-column block; at the end of a block one wide update (U12 of the
+// block's LU_OB rows, then A22 -= L21 U12 with the block's LU_OB columns of L)
+// brings the columns after it up to date, so those columns are streamed once
+// per block instead of once per 8-column panel. Row swaps act on all n columns
+// at once (a row's multipliers and its not yet updated entries move together).
+// The per-element update order equals that of the unblocked algorithm: every
+// element receives the rank-1 updates of the steps in step order, each one
+// fused multiply-add (the wide update applies the block's steps in order).
 // M is stored with its rows in pivoted order (position p holds original row
 // perm[p]); the upper n x n part holds N as in LAPACK getrf.
 #include <limits.h>
@@ -21,6 +28,7 @@ namespace rclupp {
 
 constexpr int LU_THREADS = 256;
 constexpr int LU_NB = 8;
+constexpr int LU_OB = 32;
 constexpr int LU_GRID = 1024;
 
 struct LuPartial {
@@ -210,44 +218,102 @@ __global__ __launch_bounds__(LU_THREADS) void k_lu_panel(double* __restrict__ M,
 }
 
 // U12 = L11^{-1} A12 in place: rows c0..c1-1, columns c1..n-1 (unit lower L11).
-__global__ __launch_bounds__(LU_THREADS) void k_lu_trsm12(double* __restrict__ M, int64_t ldm, int c0, int c1, int n,
-                                                          const int32_t* info) {
+// U12 = L11^{-1} A12 for the rows c0 .. c1 - 1 (c1 - c0 <= NB) and the columns
+// cs .. ce - 1 (at most LU_THREADS of them): forward substitution with the unit lower L11 (in LDS), each
+// column in a thread's registers, every entry taking its terms in step order.
+template <int NB>
+__global__ __launch_bounds__(LU_THREADS) void k_lu_trsm12(double* __restrict__ M, int64_t ldm, int c0, int c1, int cs,
+                                                          int ce, const int32_t* info) {
   if (info_failed(info)) return;
-  for (int j = c1 + threadIdx.x; j < n; j += LU_THREADS) {
-    for (int r = c0 + 1; r < c1; ++r) {
-      double a = M[r + (int64_t)j * ldm];
-      for (int t = c0; t < r; ++t) a -= M[r + (int64_t)t * ldm] * M[t + (int64_t)j * ldm];
-      M[r + (int64_t)j * ldm] = a;
+  __shared__ double L11[NB * NB];  // (r, t) at r + t NB, zero outside the block
+  const int nb = c1 - c0;
+  for (int e = threadIdx.x; e < NB * NB; e += LU_THREADS) {
+    const int r = e % NB, q = e / NB;
+    L11[e] = (r < nb && q < nb) ? M[(c0 + r) + (int64_t)(c0 + q) * ldm] : 0.0;
+  }
+  __syncthreads();
+  // one column per thread (ce - cs <= n - 1 < LU_THREADS)
+  const int j = cs + (int)threadIdx.x;
+  if (j < ce) {
+    // rows beyond the block read its last row instead (in range; those
+    // entries meet only zero entries of L11 and are not written back)
+    const double* col = M + (int64_t)j * ldm;
+    double a[NB];
+#pragma unroll
+    for (int r = 0; r < NB; ++r) a[r] = col[c0 + (r < nb ? r : nb - 1)];
+    // step q (in order) updates the rows after it
+#pragma unroll
+    for (int q = 0; q + 1 < NB; ++q) {
+#pragma unroll
+      for (int r = q + 1; r < NB; ++r) a[r] -= L11[r + q * NB] * a[q];
     }
+    double* out = M + (int64_t)j * ldm + c0;
+#pragma unroll
+    for (int r = 1; r < NB; ++r)
+      if (r < nb) out[r] = a[r];
   }
 }
 
 // Trailing update rows i >= c1: M[i][j] -= sum_t M[i][t] U12[t][j] (t in panel,
 // ascending); argmax partial of column c1.
-__global__ __launch_bounds__(LU_THREADS) void k_lu_trailing(double* __restrict__ M, int64_t ldm, int64_t m, int c0,
-                                                            int c1, int n, LuPartial* part, const int32_t* info) {
+// The same for a block of more rows (c1 - c0 <= NB, NB > LU_NB): each
+// thread's column lives in LDS instead of registers (128 threads, columns
+// taken in turn), with the same order of terms.
+constexpr int LU_TRSM_LDS_THREADS = 128;
+template <int NB>
+__global__ __launch_bounds__(LU_TRSM_LDS_THREADS) void k_lu_trsm12_lds(double* __restrict__ M, int64_t ldm, int c0,
+                                                                        int c1, int cs, int ce, const int32_t* info) {
   if (info_failed(info)) return;
-  __shared__ double u[LU_NB * RCLUPP_SMALL_MAXN];
-  const int nb = c1 - c0, nt = n - c1;
-  for (int e = threadIdx.x; e < nb * nt; e += LU_THREADS) {
-    const int t = e % nb, j = e / nb;
-    u[e] = M[(c0 + t) + (int64_t)(c1 + j) * ldm];
+  __shared__ double L11[NB * NB];                   // (r, q) at r + q NB
+  __shared__ double A[NB * LU_TRSM_LDS_THREADS];   // thread's row r at r * threads + thread
+  const int nb = c1 - c0;
+  for (int e = threadIdx.x; e < nb * nb; e += LU_TRSM_LDS_THREADS) {
+    const int r = e % nb, q = e / nb;
+    L11[r + q * NB] = M[(c0 + r) + (int64_t)(c0 + q) * ldm];
+  }
+  __syncthreads();
+  double* a = A + threadIdx.x;
+  for (int j = cs + (int)threadIdx.x; j < ce; j += LU_TRSM_LDS_THREADS) {
+    const double* col = M + (int64_t)j * ldm + c0;
+    for (int r = 0; r < nb; ++r) a[r * LU_TRSM_LDS_THREADS] = col[r];
+    for (int q = 0; q + 1 < nb; ++q) {
+      const double aq = a[q * LU_TRSM_LDS_THREADS];
+      for (int r = q + 1; r < nb; ++r) a[r * LU_TRSM_LDS_THREADS] -= L11[r + q * NB] * aq;
+    }
+    double* out = M + (int64_t)j * ldm + c0;
+    for (int r = 1; r < nb; ++r) out[r] = a[r * LU_TRSM_LDS_THREADS];
+  }
+}
+
+// A22 -= L21 U12 for the rows c1 .. m - 1 and the columns c1 .. ce - 1, with
+// the L columns c0 .. c1 - 1 (c1 - c0 <= NB); records the argmax partial of
+// column c1. U12 (nb x nt) is staged in dynamic LDS. Steps beyond nb carry a
+// zero multiplier and a zero U12 entry, which leave every element unchanged
+// (fma(-0, 0, a) = a, signed zeros included).
+template <int NB>
+__global__ __launch_bounds__(LU_THREADS) void k_lu_trailing(double* __restrict__ M, int64_t ldm, int64_t m, int c0,
+                                                            int c1, int ce, LuPartial* part, const int32_t* info) {
+  if (info_failed(info)) return;
+  extern __shared__ double u[];  // (t, j) at t + j NB
+  const int nb = c1 - c0, nt = ce - c1;
+  for (int e = threadIdx.x; e < NB * nt; e += LU_THREADS) {
+    const int q = e % NB, j = e / NB;
+    u[e] = (q < nb) ? M[(c0 + q) + (int64_t)(c1 + j) * ldm] : 0.0;
   }
   __syncthreads();
   double best = -1.0;
   int idx = INT_MAX, bad = 0;
   for (int64_t i = (int64_t)c1 + (int64_t)blockIdx.x * LU_THREADS + threadIdx.x; i < m;
        i += (int64_t)gridDim.x * LU_THREADS) {
-    double l[LU_NB];
+    double l[NB];
 #pragma unroll
-    for (int t = 0; t < LU_NB; ++t) l[t] = (t < nb) ? M[i + (int64_t)(c0 + t) * ldm] : 0.0;
-    // column 0 first (its argmax partial), then eight (then four) columns
+    for (int q = 0; q < NB; ++q) l[q] = (q < nb) ? M[i + (int64_t)(c0 + q) * ldm] : 0.0;
+    // column c1 first (its argmax partial), then eight (then four) columns
     // at a time so that eight loads are in flight per thread
     {
       double a = M[i + (int64_t)c1 * ldm];
 #pragma unroll
-      for (int t = 0; t < LU_NB; ++t)
-        if (t < nb) a -= l[t] * u[t];
+      for (int q = 0; q < NB; ++q) a -= l[q] * u[q];
       M[i + (int64_t)c1 * ldm] = a;
       track(a, i, best, idx, bad);
     }
@@ -255,32 +321,18 @@ __global__ __launch_bounds__(LU_THREADS) void k_lu_trailing(double* __restrict__
     for (; j + 7 < nt; j += 8) {
       double a[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) a[q] = __builtin_nontemporal_load(M + i + (int64_t)(c1 + j + q) * ldm);
+      for (int w = 0; w < 8; ++w) a[w] = __builtin_nontemporal_load(M + i + (int64_t)(c1 + j + w) * ldm);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
+      for (int w = 0; w < 8; ++w) {
 #pragma unroll
-        for (int t = 0; t < LU_NB; ++t)
-          if (t < nb) a[q] -= l[t] * u[t + (j + q) * nb];
-        __builtin_nontemporal_store(a[q], M + i + (int64_t)(c1 + j + q) * ldm);
-      }
-    }
-    for (; j + 3 < nt; j += 4) {
-      double a[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) a[q] = __builtin_nontemporal_load(M + i + (int64_t)(c1 + j + q) * ldm);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-#pragma unroll
-        for (int t = 0; t < LU_NB; ++t)
-          if (t < nb) a[q] -= l[t] * u[t + (j + q) * nb];
-        __builtin_nontemporal_store(a[q], M + i + (int64_t)(c1 + j + q) * ldm);
+        for (int q = 0; q < NB; ++q) a[w] -= l[q] * u[q + (j + w) * NB];
+        __builtin_nontemporal_store(a[w], M + i + (int64_t)(c1 + j + w) * ldm);
       }
     }
     for (; j < nt; ++j) {
       double a = M[i + (int64_t)(c1 + j) * ldm];
 #pragma unroll
-      for (int t = 0; t < LU_NB; ++t)
-        if (t < nb) a -= l[t] * u[t + j * nb];
+      for (int q = 0; q < NB; ++q) a -= l[q] * u[q + j * NB];
       M[i + (int64_t)(c1 + j) * ldm] = a;
     }
   }
@@ -324,16 +376,29 @@ hipError_t launch_tall_lu(const double* X, int64_t m, int64_t n, int64_t ldx, do
   hipLaunchKernelGGL(k_lu_init, dim3(g), dim3(LU_THREADS), 0, st, X, ldx, m, (int)n, M, ldm, perm, part, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  for (int c0 = 0; c0 < n; c0 += LU_NB) {
-    const int c1 = (int)((c0 + LU_NB < n) ? c0 + LU_NB : n);
-    for (int k = c0; k < c1; ++k) {
-      hipLaunchKernelGGL(k_lu_pivot, dim3(1), dim3(LU_THREADS), 0, st, M, ldm, (int)n, k, perm, part, g, prow, info);
-      const int want_next = (k + 1 < c1) ? 1 : 0;
-      hipLaunchKernelGGL(k_lu_panel, dim3(g), dim3(LU_THREADS), 0, st, M, ldm, m, k, c1, prow, part, want_next, info);
+  for (int b0 = 0; b0 < n; b0 += LU_OB) {
+    const int b1 = (int)((b0 + LU_OB < n) ? b0 + LU_OB : n);
+    for (int c0 = b0; c0 < b1; c0 += LU_NB) {
+      const int c1 = (c0 + LU_NB < b1) ? c0 + LU_NB : b1;
+      for (int k = c0; k < c1; ++k) {
+        hipLaunchKernelGGL(k_lu_pivot, dim3(1), dim3(LU_THREADS), 0, st, M, ldm, (int)n, k, perm, part, g, prow, info);
+        const int want_next = (k + 1 < c1) ? 1 : 0;
+        hipLaunchKernelGGL(k_lu_panel, dim3(g), dim3(LU_THREADS), 0, st, M, ldm, m, k, c1, prow, part, want_next,
+                           info);
+      }
+      if (c1 < b1) {
+        // the panel's update of the rest of its block
+        hipLaunchKernelGGL(k_lu_trsm12<LU_NB>, dim3(1), dim3(LU_THREADS), 0, st, M, ldm, c0, c1, c1, b1, info);
+        hipLaunchKernelGGL(k_lu_trailing<LU_NB>, dim3(g), dim3(LU_THREADS), (size_t)LU_NB * (b1 - c1) * sizeof(double),
+                           st, M, ldm, m, c0, c1, b1, part, info);
+      }
     }
-    if (c1 < n) {
-      hipLaunchKernelGGL(k_lu_trsm12, dim3(1), dim3(LU_THREADS), 0, st, M, ldm, c0, c1, (int)n, info);
-      hipLaunchKernelGGL(k_lu_trailing, dim3(g), dim3(LU_THREADS), 0, st, M, ldm, m, c0, c1, (int)n, part, info);
+    if (b1 < n) {
+      // the block's update of the columns after it
+      hipLaunchKernelGGL(k_lu_trsm12_lds<LU_OB>, dim3(1), dim3(LU_TRSM_LDS_THREADS), 0, st, M, ldm, b0, b1, b1,
+                         (int)n, info);
+      hipLaunchKernelGGL(k_lu_trailing<LU_OB>, dim3(g), dim3(LU_THREADS), (size_t)LU_OB * (n - b1) * sizeof(double),
+                         st, M, ldm, m, b0, b1, (int)n, part, info);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
