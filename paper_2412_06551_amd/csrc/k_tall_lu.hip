@@ -1,5 +1,5 @@
 // LU with partial pivoting of the tall X (m x n), P X = M N (Algorithm 7 step
-// 1, Algorithm 5 step 1), blocked right-looking with LU_NB-column panels:
+// 1, Algorithm 5 step 1), blocked right-looking:
 //   per column k of a panel: one workgroup reduces the per-workgroup argmax
 //     partials of |column k| (first row wins ties, LAPACK idamax), swaps rows
 //     k and p across all n columns and keeps the pivot row; then every
@@ -8,15 +8,16 @@
 //   per panel: U12 = L11^{-1} A12 (one workgroup), then the trailing update
 //     A22 -= L21 U12 streams every row once and records the argmax partial of
 //     the next panel's first column.
-// Two levels of panels: the 8-column panels update only the columns of their
-// LU_OB-column block; at the end of a block one wide update (U12 of the
-// block's LU_OB rows, then A22 -= L21 U12 with the block's LU_OB columns of L)
-// brings the columns after it up to date, so those columns are streamed once
-// per block instead of once per 8-column panel. Row swaps act on all n columns
-// at once (a row's multipliers and its not yet updated entries move together).
-// The per-element update order equals that of the unblocked algorithm: every
-// element receives the rank-1 updates of the steps in step order, each one
-// fused multiply-add (the wide update applies the block's steps in order).
+// Three levels of panels: a 4-column panel updates only the rest of its
+// 16-column block, a 16-column block only the rest of its 32-column block,
+// and a 32-column block the rest of the matrix (each update: U12 of the
+// block's rows, then A22 -= L21 U12 with the block's columns of L), so a
+// column is streamed once per block of each level that precedes it instead of
+// once per panel. Row swaps act on all n columns at once (a row's multipliers
+// and its not yet updated entries move together). The per-element update
+// order equals that of the unblocked algorithm: every element receives the
+// rank-1 updates of the steps in step order, each one fused multiply-add (an
+// update applies its block's steps in order).
 // M is stored with its rows in pivoted order (position p holds original row
 // perm[p]); the upper n x n part holds N as in LAPACK getrf.
 #include <limits.h>
@@ -27,8 +28,11 @@
 namespace rclupp {
 
 constexpr int LU_THREADS = 256;
+// panel widths of the three levels (a panel of LU_W0 columns is factored
+// column by column; LU_NB bounds the columns one column step reads per row)
+constexpr int LU_W0 = 4, LU_W1 = 16, LU_W2 = 32;
 constexpr int LU_NB = 8;
-constexpr int LU_OB = 32;
+static_assert(LU_W0 <= LU_NB, "a column step reads at most LU_NB columns");
 constexpr int LU_GRID = 1024;
 
 struct LuPartial {
@@ -256,7 +260,7 @@ __global__ __launch_bounds__(LU_THREADS) void k_lu_trsm12(double* __restrict__ M
 
 // Trailing update rows i >= c1: M[i][j] -= sum_t M[i][t] U12[t][j] (t in panel,
 // ascending); argmax partial of column c1.
-// The same for a block of more rows (c1 - c0 <= NB, NB > LU_NB): each
+// The same for a block of more rows (c1 - c0 <= NB): each
 // thread's column lives in LDS instead of registers (128 threads, columns
 // taken in turn), with the same order of terms.
 constexpr int LU_TRSM_LDS_THREADS = 128;
@@ -376,30 +380,47 @@ hipError_t launch_tall_lu(const double* X, int64_t m, int64_t n, int64_t ldx, do
   hipLaunchKernelGGL(k_lu_init, dim3(g), dim3(LU_THREADS), 0, st, X, ldx, m, (int)n, M, ldm, perm, part, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  for (int b0 = 0; b0 < n; b0 += LU_OB) {
-    const int b1 = (int)((b0 + LU_OB < n) ? b0 + LU_OB : n);
-    for (int c0 = b0; c0 < b1; c0 += LU_NB) {
-      const int c1 = (c0 + LU_NB < b1) ? c0 + LU_NB : b1;
-      for (int k = c0; k < c1; ++k) {
-        hipLaunchKernelGGL(k_lu_pivot, dim3(1), dim3(LU_THREADS), 0, st, M, ldm, (int)n, k, perm, part, g, prow, info);
-        const int want_next = (k + 1 < c1) ? 1 : 0;
-        hipLaunchKernelGGL(k_lu_panel, dim3(g), dim3(LU_THREADS), 0, st, M, ldm, m, k, c1, prow, part, want_next,
-                           info);
-      }
-      if (c1 < b1) {
-        // the panel's update of the rest of its block
-        hipLaunchKernelGGL(k_lu_trsm12<LU_NB>, dim3(1), dim3(LU_THREADS), 0, st, M, ldm, c0, c1, c1, b1, info);
-        hipLaunchKernelGGL(k_lu_trailing<LU_NB>, dim3(g), dim3(LU_THREADS), (size_t)LU_NB * (b1 - c1) * sizeof(double),
-                           st, M, ldm, m, c0, c1, b1, part, info);
-      }
+  // the update of the columns c1 .. ce - 1 by the steps c0 .. c1 - 1 (U12,
+  // then A22 -= L21 U12), which also records the argmax partial of column c1
+  auto update = [&](int c0, int c1, int ce) {
+    const size_t lds = (size_t)(ce - c1) * sizeof(double);
+    if (c1 - c0 <= LU_W0) {
+      hipLaunchKernelGGL(k_lu_trsm12<LU_W0>, dim3(1), dim3(LU_THREADS), 0, st, M, ldm, c0, c1, c1, ce, info);
+      hipLaunchKernelGGL(k_lu_trailing<LU_W0>, dim3(g), dim3(LU_THREADS), LU_W0 * lds, st, M, ldm, m, c0, c1, ce, part,
+                         info);
+    } else if (c1 - c0 <= LU_W1) {
+      hipLaunchKernelGGL(k_lu_trsm12_lds<LU_W1>, dim3(1), dim3(LU_TRSM_LDS_THREADS), 0, st, M, ldm, c0, c1, c1, ce,
+                         info);
+      hipLaunchKernelGGL(k_lu_trailing<LU_W1>, dim3(g), dim3(LU_THREADS), LU_W1 * lds, st, M, ldm, m, c0, c1, ce, part,
+                         info);
+    } else {
+      hipLaunchKernelGGL(k_lu_trsm12_lds<LU_W2>, dim3(1), dim3(LU_TRSM_LDS_THREADS), 0, st, M, ldm, c0, c1, c1, ce,
+                         info);
+      hipLaunchKernelGGL(k_lu_trailing<LU_W2>, dim3(g), dim3(LU_THREADS), LU_W2 * lds, st, M, ldm, m, c0, c1, ce, part,
+                         info);
     }
-    if (b1 < n) {
-      // the block's update of the columns after it
-      hipLaunchKernelGGL(k_lu_trsm12_lds<LU_OB>, dim3(1), dim3(LU_TRSM_LDS_THREADS), 0, st, M, ldm, b0, b1, b1,
-                         (int)n, info);
-      hipLaunchKernelGGL(k_lu_trailing<LU_OB>, dim3(g), dim3(LU_THREADS), (size_t)LU_OB * (n - b1) * sizeof(double),
-                         st, M, ldm, m, b0, b1, (int)n, part, info);
+  };
+  // blocks of LU_W2 columns, made of blocks of LU_W1 columns, made of panels
+  // of LU_W0 columns; each (sub-)block, once factored, updates the rest of
+  // the block that holds it (the outermost: the rest of the matrix)
+  for (int b0 = 0; b0 < n; b0 += LU_W2) {
+    const int b1 = (int)((b0 + LU_W2 < n) ? b0 + LU_W2 : n);
+    for (int s0 = b0; s0 < b1; s0 += LU_W1) {
+      const int s1 = (s0 + LU_W1 < b1) ? s0 + LU_W1 : b1;
+      for (int c0 = s0; c0 < s1; c0 += LU_W0) {
+        const int c1 = (c0 + LU_W0 < s1) ? c0 + LU_W0 : s1;
+        for (int k = c0; k < c1; ++k) {
+          hipLaunchKernelGGL(k_lu_pivot, dim3(1), dim3(LU_THREADS), 0, st, M, ldm, (int)n, k, perm, part, g, prow,
+                             info);
+          const int want_next = (k + 1 < c1) ? 1 : 0;
+          hipLaunchKernelGGL(k_lu_panel, dim3(g), dim3(LU_THREADS), 0, st, M, ldm, m, k, c1, prow, part, want_next,
+                             info);
+        }
+        if (c1 < s1) update(c0, c1, s1);
+      }
+      if (s1 < b1) update(s0, s1, b1);
     }
+    if (b1 < n) update(b0, b1, (int)n);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
