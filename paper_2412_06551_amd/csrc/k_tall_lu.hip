@@ -221,15 +221,15 @@ __global__ __launch_bounds__(LU_THREADS) void k_lu_panel(double* __restrict__ M,
   if (want_next) wg_argmax_write(best, idx, bad, part + blockIdx.x);
 }
 
-// U12 = L11^{-1} A12 in place: rows c0..c1-1, columns c1..n-1 (unit lower L11).
-// U12 = L11^{-1} A12 for the rows c0 .. c1 - 1 (c1 - c0 <= NB) and the columns
-// cs .. ce - 1 (at most LU_THREADS of them): forward substitution with the unit lower L11 (in LDS), each
-// column in a thread's registers, every entry taking its terms in step order.
+// U12 = L11^{-1} A12 in place for the rows c0 .. c1 - 1 (c1 - c0 <= NB) and
+// the columns cs .. ce - 1 (at most LU_THREADS of them): forward substitution
+// with the unit lower L11 (in LDS), each column in a thread's registers, every
+// entry taking its terms in step order.
 template <int NB>
 __global__ __launch_bounds__(LU_THREADS) void k_lu_trsm12(double* __restrict__ M, int64_t ldm, int c0, int c1, int cs,
                                                           int ce, const int32_t* info) {
   if (info_failed(info)) return;
-  __shared__ double L11[NB * NB];  // (r, t) at r + t NB, zero outside the block
+  __shared__ double L11[NB * NB];  // (r, q) at r + q NB, zero outside the block
   const int nb = c1 - c0;
   for (int e = threadIdx.x; e < NB * NB; e += LU_THREADS) {
     const int r = e % NB, q = e / NB;
@@ -258,11 +258,9 @@ __global__ __launch_bounds__(LU_THREADS) void k_lu_trsm12(double* __restrict__ M
   }
 }
 
-// Trailing update rows i >= c1: M[i][j] -= sum_t M[i][t] U12[t][j] (t in panel,
-// ascending); argmax partial of column c1.
-// The same for a block of more rows (c1 - c0 <= NB): each
-// thread's column lives in LDS instead of registers (128 threads, columns
-// taken in turn), with the same order of terms.
+// The same for the wider blocks (c1 - c0 <= NB): each thread's column lives in
+// LDS instead of registers (128 threads, columns taken in turn), with the same
+// order of terms.
 constexpr int LU_TRSM_LDS_THREADS = 128;
 template <int NB>
 __global__ __launch_bounds__(LU_TRSM_LDS_THREADS) void k_lu_trsm12_lds(double* __restrict__ M, int64_t ldm, int c0,
