@@ -91,3 +91,24 @@ def test_more_than_one_gpu_is_refused():
     p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert p.returncode == 2 and "one GPU" in p.stderr
+
+
+def test_tall_lu_moved_bytes(bench):
+    """The blocked LU's byte count: closed forms for one level of panels and
+    for the three levels at n = 128, and the widths the library launches."""
+    import re
+    m = 1000
+    # one level of w-column panels: copy n, column steps n (w + 1) / 2, and
+    # after each panel but the last its L (w / 2) and the later columns
+    n, w = 64, 8
+    later = sum(n - c1 for c1 in range(w, n, w))
+    one = n + n * (w + 1) / 2 + (n // w - 1) * w / 2 + later
+    assert bench.tall_lu_moved_bytes(m, n, widths=(w, w, n)) == int(one * 16 * m)
+    # three levels at n = 128: 128 + 320 + 240 + 96 + 240 passes
+    assert bench.tall_lu_moved_bytes(m, 128) == 1024 * 16 * m
+    # a single column: the copy and its step
+    assert bench.tall_lu_moved_bytes(m, 1) == 2 * 16 * m
+    # the default widths are the ones the library uses
+    src = open(os.path.join(ROOT, "paper_2412_06551_amd", "csrc", "k_tall_lu.hip")).read()
+    got = re.search(r"LU_W0 = (\d+), LU_W1 = (\d+), LU_W2 = (\d+);", src)
+    assert got and tuple(int(x) for x in got.groups()) == (4, 16, 32)
