@@ -458,16 +458,21 @@ def test_chol_blocked_shift_breakdown_nonfinite(n):
 
 
 # ---------------------------------------------------------------- tall LU
-@pytest.mark.parametrize("m,n", [(1000, 8), (5000 + 13, 32), (20000, 50), (3000, 64), (2000, 100)])
+@pytest.mark.parametrize("m,n", [(1000, 8), (5000 + 13, 32), (20000, 50), (3000, 64), (2000, 100), (700, 17),
+                                 (900, 33), (3000 + 1, 128), (1500, 256)])
 def test_tall_lu_matches_oracle(m, n):
+    # every element takes the steps' fused multiply-adds in step order on both
+    # sides (the blocked updates included), so L and N are the oracle's bit
+    # for bit; n = 17, 33, 100 end in partial panels and blocks, n = 128 and
+    # 256 take the widest updates
     x = np.asfortranarray(np.random.default_rng(m).standard_normal((m, n)))
     M, perm, info = _lib().tall_lu(to_dev(x))
     assert info.cpu().tolist()[0] == 0
     Mo, No, po, io = oracle.gepp(x)
     np.testing.assert_array_equal(perm.cpu().numpy(), po)
     lu = to_host(M)
-    np.testing.assert_allclose(np.tril(lu, -1)[:, :n], np.tril(Mo, -1), rtol=0, atol=1e-12)
-    np.testing.assert_allclose(np.triu(lu[:n]), No, rtol=0, atol=1e-12 * np.abs(No).max())
+    np.testing.assert_array_equal(np.tril(lu, -1)[:, :n], np.tril(Mo, -1))
+    np.testing.assert_array_equal(np.triu(lu[:n]), No)
 
 
 # ---------------------------------------------------------------- tournament pivoting
