@@ -66,13 +66,14 @@ def tall_bytes(m, n):
 
 
 def tall_lu_moved_bytes(m, n, widths=(4, 16, 32)):
-    """HBM bytes the blocked partial-pivoting LU moves (rows taken as m): the
-    copy of X, every column step's read and write of the rest of its panel,
-    and every block update's read of its L columns and read and write of the
-    columns it updates, with panels of widths[0] columns inside blocks of
-    widths[1] inside blocks of widths[2] (the launch order of the library)."""
+    """HBM bytes the blocked partial-pivoting LU moves (rows taken as m): every
+    column step's read and write of the rest of its panel, and every block
+    update's read of its L columns and read and write of the columns it
+    updates (a column's first update reads it from X), with panels of
+    widths[0] columns inside blocks of widths[1] inside blocks of widths[2]
+    (the launch order of the library)."""
     w0, w1, w2 = widths
-    passes = float(n)  # copy: one read and one write per column
+    passes = 0.0
 
     def update(c0, c1, ce):
         return 0.5 * (c1 - c0) + (ce - c1)

@@ -20,6 +20,11 @@
 // update applies its block's steps in order).
 // M is stored with its rows in pivoted order (position p holds original row
 // perm[p]); the upper n x n part holds N as in LAPACK getrf.
+// X is not copied into M first: a column enters M when a kernel first updates
+// it (the first column step for the first panel, the first update of each
+// level for the columns it covers), reading row i from X's row perm[i]; until
+// then a row swap only exchanges perm entries (and writes the new pivot row
+// into M), since a column no step has updated yet is X's column permuted.
 #include <limits.h>
 
 #include "device_common.hpp"
@@ -88,36 +93,29 @@ __device__ __forceinline__ void track(double a, int64_t i, double& best, int& id
   }
 }
 
-// Copy X into M, perm = identity, argmax partials of column 0.
-__global__ __launch_bounds__(LU_THREADS) void k_lu_init(const double* __restrict__ X, int64_t ldx, int64_t m, int n,
-                                                        double* __restrict__ M, int64_t ldm, int32_t* __restrict__ perm,
-                                                        LuPartial* part, const int32_t* info) {
+// perm = identity, argmax partials of column 0 (read from X).
+__global__ __launch_bounds__(LU_THREADS) void k_lu_init(const double* __restrict__ X, int64_t m,
+                                                        int32_t* __restrict__ perm, LuPartial* part,
+                                                        const int32_t* info) {
   if (info_failed(info)) return;
   double best = -1.0;
   int idx = INT_MAX, bad = 0;
   for (int64_t i = (int64_t)blockIdx.x * LU_THREADS + threadIdx.x; i < m; i += (int64_t)gridDim.x * LU_THREADS) {
-    // eight columns at a time, so that eight loads are in flight per thread
-    const double x0 = X[i];
-    int j = 0;
-    for (; j + 8 <= n; j += 8) {
-      double v[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = X[i + (int64_t)(j + q) * ldx];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) M[i + (int64_t)(j + q) * ldm] = v[q];
-    }
-    for (; j < n; ++j) M[i + (int64_t)j * ldm] = X[i + (int64_t)j * ldx];
     perm[i] = (int32_t)i;
-    track(x0, i, best, idx, bad);
+    track(X[i], i, best, idx, bad);
   }
   wg_argmax_write(best, idx, bad, part + blockIdx.x);
 }
 
 // Pivot of column k: reduce partials, test, swap rows k and p, keep the pivot row.
+// (columns f .. n - 1 are not in M yet: only perm is swapped there, and the
+// new pivot row's entries are read from X)
 __global__ __launch_bounds__(LU_THREADS) void k_lu_pivot(double* __restrict__ M, int64_t ldm, int n, int k,
                                                          int32_t* __restrict__ perm, const LuPartial* __restrict__ part,
-                                                         int nparts, double* __restrict__ prow, int32_t* info) {
-  __shared__ int s_p, s_fail;
+                                                         int nparts, double* __restrict__ prow,
+                                                         const double* __restrict__ X, int64_t ldx, int f,
+                                                         int32_t* info) {
+  __shared__ int s_p, s_fail, s_row;
   __shared__ double rv[LU_THREADS / 64];
   __shared__ int ri[LU_THREADS / 64], rb[LU_THREADS / 64];
   if (info_failed(info)) return;
@@ -177,25 +175,36 @@ __global__ __launch_bounds__(LU_THREADS) void k_lu_pivot(double* __restrict__ M,
       perm[k] = perm[bi];
       perm[bi] = t;
     }
+    s_row = perm[k];
   }
   __syncthreads();
   if (s_fail) return;
   const int p = s_p;
+  const int64_t xk = s_row;
   for (int j = threadIdx.x; j < n; j += LU_THREADS) {
-    const double a = M[k + j * ldm];
-    const double b = M[p + j * ldm];
-    if (p != k) {
+    if (j < f) {
+      const double a = M[k + j * ldm];
+      const double b = M[p + j * ldm];
+      if (p != k) {
+        M[k + j * ldm] = b;
+        M[p + j * ldm] = a;
+      }
+      prow[j] = b;
+    } else {
+      const double b = X[xk + (int64_t)j * ldx];
       M[k + j * ldm] = b;
-      M[p + j * ldm] = a;
+      prow[j] = b;
     }
-    prow[j] = b;
   }
 }
 
 // Panel update at step k: rows i > k.
+// (from_x: the panel's columns enter M here, read from X's rows perm[i])
 __global__ __launch_bounds__(LU_THREADS) void k_lu_panel(double* __restrict__ M, int64_t ldm, int64_t m, int k, int c1,
                                                          const double* __restrict__ prow, LuPartial* part,
-                                                         int want_next, const int32_t* info) {
+                                                         int want_next, const double* __restrict__ X, int64_t ldx,
+                                                         const int32_t* __restrict__ perm, int from_x,
+                                                         const int32_t* info) {
   if (info_failed(info)) return;
   const double piv = prow[k];
   double best = -1.0;
@@ -204,9 +213,11 @@ __global__ __launch_bounds__(LU_THREADS) void k_lu_panel(double* __restrict__ M,
        i += (int64_t)gridDim.x * LU_THREADS) {
     // the row's columns k .. c1 - 1 of the panel (at most LU_NB) are read
     // before any is written, so that their loads are in flight together
+    const double* src = from_x ? X + perm[i] : M + i;
+    const int64_t ld = from_x ? ldx : ldm;
     double v[LU_NB];
 #pragma unroll
-    for (int q = 0; q < LU_NB; ++q) v[q] = (k + q < c1) ? M[i + (int64_t)(k + q) * ldm] : 0.0;
+    for (int q = 0; q < LU_NB; ++q) v[q] = (k + q < c1) ? src[(int64_t)(k + q) * ld] : 0.0;
     const double l = v[0] / piv;
     M[i + (int64_t)k * ldm] = l;
 #pragma unroll
@@ -293,8 +304,12 @@ __global__ __launch_bounds__(LU_TRSM_LDS_THREADS) void k_lu_trsm12_lds(double* _
 // zero multiplier and a zero U12 entry, which leave every element unchanged
 // (fma(-0, 0, a) = a, signed zeros included).
 template <int NB>
+// (from_x: the columns c1 .. ce - 1 enter M here, read from X's rows perm[i])
 __global__ __launch_bounds__(LU_THREADS) void k_lu_trailing(double* __restrict__ M, int64_t ldm, int64_t m, int c0,
-                                                            int c1, int ce, LuPartial* part, const int32_t* info) {
+                                                            int c1, int ce, LuPartial* part,
+                                                            const double* __restrict__ X, int64_t ldx,
+                                                            const int32_t* __restrict__ perm, int from_x,
+                                                            const int32_t* info) {
   if (info_failed(info)) return;
   extern __shared__ double u[];  // (t, j) at t + j NB
   const int nb = c1 - c0, nt = ce - c1;
@@ -310,11 +325,14 @@ __global__ __launch_bounds__(LU_THREADS) void k_lu_trailing(double* __restrict__
     double l[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) l[q] = (q < nb) ? M[i + (int64_t)(c0 + q) * ldm] : 0.0;
+    // the row's entries of the columns c1 .. ce - 1 (src[j ld] for column c1 + j)
+    const double* src = from_x ? X + perm[i] + (int64_t)c1 * ldx : M + i + (int64_t)c1 * ldm;
+    const int64_t ld = from_x ? ldx : ldm;
     // column c1 first (its argmax partial), then eight columns at a time so
     // that eight loads are in flight per thread, then the rest one by one
     // (issuing the rest's loads together measured no faster)
     {
-      double a = M[i + (int64_t)c1 * ldm];
+      double a = src[0];
 #pragma unroll
       for (int q = 0; q < NB; ++q) a -= l[q] * u[q];
       M[i + (int64_t)c1 * ldm] = a;
@@ -324,7 +342,7 @@ __global__ __launch_bounds__(LU_THREADS) void k_lu_trailing(double* __restrict__
     for (; j + 7 < nt; j += 8) {
       double a[8];
 #pragma unroll
-      for (int w = 0; w < 8; ++w) a[w] = __builtin_nontemporal_load(M + i + (int64_t)(c1 + j + w) * ldm);
+      for (int w = 0; w < 8; ++w) a[w] = __builtin_nontemporal_load(src + (int64_t)(j + w) * ld);
 #pragma unroll
       for (int w = 0; w < 8; ++w) {
 #pragma unroll
@@ -333,7 +351,7 @@ __global__ __launch_bounds__(LU_THREADS) void k_lu_trailing(double* __restrict__
       }
     }
     for (; j < nt; ++j) {
-      double a = M[i + (int64_t)(c1 + j) * ldm];
+      double a = src[(int64_t)j * ld];
 #pragma unroll
       for (int q = 0; q < NB; ++q) a -= l[q] * u[q + j * NB];
       M[i + (int64_t)(c1 + j) * ldm] = a;
@@ -376,28 +394,36 @@ hipError_t launch_tall_lu(const double* X, int64_t m, int64_t n, int64_t ldx, do
   double* prow = (double*)((char*)scratch + off);
   int64_t rows_blocks = (m + LU_THREADS - 1) / LU_THREADS;
   const int g = (int)(rows_blocks < LU_GRID ? rows_blocks : LU_GRID);
-  hipLaunchKernelGGL(k_lu_init, dim3(g), dim3(LU_THREADS), 0, st, X, ldx, m, (int)n, M, ldm, perm, part, info);
+  hipLaunchKernelGGL(k_lu_init, dim3(g), dim3(LU_THREADS), 0, st, X, m, perm, part, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  // columns 0 .. f - 1 are in M; every kernel below updates either columns
+  // all in M or columns all outside it, which it then brings in (f grows to
+  // the end of its range)
+  int f = 0;
   // the update of the columns c1 .. ce - 1 by the steps c0 .. c1 - 1 (U12,
   // then A22 -= L21 U12), which also records the argmax partial of column c1
-  auto update = [&](int c0, int c1, int ce) {
+  auto update = [&](int c0, int c1, int ce) -> hipError_t {
+    if (c1 < f && ce > f) return hipErrorInvalidValue;  // not reached: the blocks nest
+    const int from_x = c1 >= f ? 1 : 0;
     const size_t lds = (size_t)(ce - c1) * sizeof(double);
     if (c1 - c0 <= LU_W0) {
       hipLaunchKernelGGL(k_lu_trsm12<LU_W0>, dim3(1), dim3(LU_THREADS), 0, st, M, ldm, c0, c1, c1, ce, info);
       hipLaunchKernelGGL(k_lu_trailing<LU_W0>, dim3(g), dim3(LU_THREADS), LU_W0 * lds, st, M, ldm, m, c0, c1, ce, part,
-                         info);
+                         X, ldx, perm, from_x, info);
     } else if (c1 - c0 <= LU_W1) {
       hipLaunchKernelGGL(k_lu_trsm12_lds<LU_W1>, dim3(1), dim3(LU_TRSM_LDS_THREADS), 0, st, M, ldm, c0, c1, c1, ce,
                          info);
       hipLaunchKernelGGL(k_lu_trailing<LU_W1>, dim3(g), dim3(LU_THREADS), LU_W1 * lds, st, M, ldm, m, c0, c1, ce, part,
-                         info);
+                         X, ldx, perm, from_x, info);
     } else {
       hipLaunchKernelGGL(k_lu_trsm12_lds<LU_W2>, dim3(1), dim3(LU_TRSM_LDS_THREADS), 0, st, M, ldm, c0, c1, c1, ce,
                          info);
       hipLaunchKernelGGL(k_lu_trailing<LU_W2>, dim3(g), dim3(LU_THREADS), LU_W2 * lds, st, M, ldm, m, c0, c1, ce, part,
-                         info);
+                         X, ldx, perm, from_x, info);
     }
+    if (from_x) f = ce;
+    return hipGetLastError();
   };
   // blocks of LU_W2 columns, made of blocks of LU_W1 columns, made of panels
   // of LU_W0 columns; each (sub-)block, once factored, updates the rest of
@@ -409,17 +435,20 @@ hipError_t launch_tall_lu(const double* X, int64_t m, int64_t n, int64_t ldx, do
       for (int c0 = s0; c0 < s1; c0 += LU_W0) {
         const int c1 = (c0 + LU_W0 < s1) ? c0 + LU_W0 : s1;
         for (int k = c0; k < c1; ++k) {
-          hipLaunchKernelGGL(k_lu_pivot, dim3(1), dim3(LU_THREADS), 0, st, M, ldm, (int)n, k, perm, part, g, prow,
-                             info);
+          if (k < f && c1 > f) return hipErrorInvalidValue;  // not reached: panels start outside M or inside it
+          hipLaunchKernelGGL(k_lu_pivot, dim3(1), dim3(LU_THREADS), 0, st, M, ldm, (int)n, k, perm, part, g, prow, X,
+                             ldx, f, info);
           const int want_next = (k + 1 < c1) ? 1 : 0;
-          hipLaunchKernelGGL(k_lu_panel, dim3(g), dim3(LU_THREADS), 0, st, M, ldm, m, k, c1, prow, part, want_next,
-                             info);
+          const int from_x = k >= f ? 1 : 0;
+          hipLaunchKernelGGL(k_lu_panel, dim3(g), dim3(LU_THREADS), 0, st, M, ldm, m, k, c1, prow, part, want_next, X,
+                             ldx, perm, from_x, info);
+          if (from_x) f = c1;
         }
-        if (c1 < s1) update(c0, c1, s1);
+        if (c1 < s1 && (e = update(c0, c1, s1)) != hipSuccess) return e;
       }
-      if (s1 < b1) update(s0, s1, b1);
+      if (s1 < b1 && (e = update(s0, s1, b1)) != hipSuccess) return e;
     }
-    if (b1 < n) update(b0, b1, (int)n);
+    if (b1 < n && (e = update(b0, b1, (int)n)) != hipSuccess) return e;
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -98,16 +98,16 @@ def test_tall_lu_moved_bytes(bench):
     for the three levels at n = 128, and the widths the library launches."""
     import re
     m = 1000
-    # one level of w-column panels: copy n, column steps n (w + 1) / 2, and
-    # after each panel but the last its L (w / 2) and the later columns
+    # one level of w-column panels: column steps n (w + 1) / 2, and after
+    # each panel but the last its L (w / 2) and the later columns
     n, w = 64, 8
     later = sum(n - c1 for c1 in range(w, n, w))
-    one = n + n * (w + 1) / 2 + (n // w - 1) * w / 2 + later
+    one = n * (w + 1) / 2 + (n // w - 1) * w / 2 + later
     assert bench.tall_lu_moved_bytes(m, n, widths=(w, w, n)) == int(one * 16 * m)
-    # three levels at n = 128: 128 + 320 + 240 + 96 + 240 passes
-    assert bench.tall_lu_moved_bytes(m, 128) == 1024 * 16 * m
-    # a single column: the copy and its step
-    assert bench.tall_lu_moved_bytes(m, 1) == 2 * 16 * m
+    # three levels at n = 128: 320 + 240 + 96 + 240 passes
+    assert bench.tall_lu_moved_bytes(m, 128) == 896 * 16 * m
+    # a single column: its step
+    assert bench.tall_lu_moved_bytes(m, 1) == 16 * m
     # the default widths are the ones the library uses
     src = open(os.path.join(ROOT, "paper_2412_06551_amd", "csrc", "k_tall_lu.hip")).read()
     got = re.search(r"LU_W0 = (\d+), LU_W1 = (\d+), LU_W2 = (\d+);", src)
