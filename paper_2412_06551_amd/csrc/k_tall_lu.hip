@@ -302,14 +302,14 @@ __global__ __launch_bounds__(LU_TRSM_LDS_THREADS) void k_lu_trsm12_lds(double* _
 // the L columns c0 .. c1 - 1 (c1 - c0 <= NB); records the argmax partial of
 // column c1. U12 (nb x nt) is staged in dynamic LDS. Steps beyond nb carry a
 // zero multiplier and a zero U12 entry, which leave every element unchanged
-// (fma(-0, 0, a) = a, signed zeros included).
-template <int NB>
-// (from_x: the columns c1 .. ce - 1 enter M here, read from X's rows perm[i])
+// (fma(-0, 0, a) = a, signed zeros included). FROM_X: the columns c1 .. ce - 1
+// enter M here, read from X's rows perm[i] (a template argument, so that the
+// other form keeps its loads and stores on M alone).
+template <int NB, bool FROM_X>
 __global__ __launch_bounds__(LU_THREADS) void k_lu_trailing(double* __restrict__ M, int64_t ldm, int64_t m, int c0,
                                                             int c1, int ce, LuPartial* part,
                                                             const double* __restrict__ X, int64_t ldx,
-                                                            const int32_t* __restrict__ perm, int from_x,
-                                                            const int32_t* info) {
+                                                            const int32_t* __restrict__ perm, const int32_t* info) {
   if (info_failed(info)) return;
   extern __shared__ double u[];  // (t, j) at t + j NB
   const int nb = c1 - c0, nt = ce - c1;
@@ -325,14 +325,14 @@ __global__ __launch_bounds__(LU_THREADS) void k_lu_trailing(double* __restrict__
     double l[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) l[q] = (q < nb) ? M[i + (int64_t)(c0 + q) * ldm] : 0.0;
-    // the row's entries of the columns c1 .. ce - 1 (src[j ld] for column c1 + j)
-    const double* src = from_x ? X + perm[i] + (int64_t)c1 * ldx : M + i + (int64_t)c1 * ldm;
-    const int64_t ld = from_x ? ldx : ldm;
+    // the row's entry of column c (FROM_X: the row's original in X)
+    const double* xr = FROM_X ? X + perm[i] : nullptr;
+    auto at = [&](int c) -> const double* { return FROM_X ? xr + (int64_t)c * ldx : M + i + (int64_t)c * ldm; };
     // column c1 first (its argmax partial), then eight columns at a time so
     // that eight loads are in flight per thread, then the rest one by one
     // (issuing the rest's loads together measured no faster)
     {
-      double a = src[0];
+      double a = *at(c1);
 #pragma unroll
       for (int q = 0; q < NB; ++q) a -= l[q] * u[q];
       M[i + (int64_t)c1 * ldm] = a;
@@ -342,7 +342,7 @@ __global__ __launch_bounds__(LU_THREADS) void k_lu_trailing(double* __restrict__
     for (; j + 7 < nt; j += 8) {
       double a[8];
 #pragma unroll
-      for (int w = 0; w < 8; ++w) a[w] = __builtin_nontemporal_load(src + (int64_t)(j + w) * ld);
+      for (int w = 0; w < 8; ++w) a[w] = __builtin_nontemporal_load(at(c1 + j + w));
 #pragma unroll
       for (int w = 0; w < 8; ++w) {
 #pragma unroll
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(LU_THREADS) void k_lu_trailing(double* __restrict__
       }
     }
     for (; j < nt; ++j) {
-      double a = src[(int64_t)j * ld];
+      double a = *at(c1 + j);
 #pragma unroll
       for (int q = 0; q < NB; ++q) a -= l[q] * u[q + j * NB];
       M[i + (int64_t)(c1 + j) * ldm] = a;
@@ -407,21 +407,26 @@ hipError_t launch_tall_lu(const double* X, int64_t m, int64_t n, int64_t ldx, do
     if (c1 < f && ce > f) return hipErrorInvalidValue;  // not reached: the blocks nest
     const int from_x = c1 >= f ? 1 : 0;
     const size_t lds = (size_t)(ce - c1) * sizeof(double);
+#define LU_TRAILING(NB)                                                                                             \
+  if (from_x)                                                                                                        \
+    hipLaunchKernelGGL((k_lu_trailing<NB, true>), dim3(g), dim3(LU_THREADS), NB * lds, st, M, ldm, m, c0, c1, ce,     \
+                       part, X, ldx, perm, info);                                                                    \
+  else                                                                                                               \
+    hipLaunchKernelGGL((k_lu_trailing<NB, false>), dim3(g), dim3(LU_THREADS), NB * lds, st, M, ldm, m, c0, c1, ce,    \
+                       part, X, ldx, perm, info);
     if (c1 - c0 <= LU_W0) {
       hipLaunchKernelGGL(k_lu_trsm12<LU_W0>, dim3(1), dim3(LU_THREADS), 0, st, M, ldm, c0, c1, c1, ce, info);
-      hipLaunchKernelGGL(k_lu_trailing<LU_W0>, dim3(g), dim3(LU_THREADS), LU_W0 * lds, st, M, ldm, m, c0, c1, ce, part,
-                         X, ldx, perm, from_x, info);
+      LU_TRAILING(LU_W0)
     } else if (c1 - c0 <= LU_W1) {
       hipLaunchKernelGGL(k_lu_trsm12_lds<LU_W1>, dim3(1), dim3(LU_TRSM_LDS_THREADS), 0, st, M, ldm, c0, c1, c1, ce,
                          info);
-      hipLaunchKernelGGL(k_lu_trailing<LU_W1>, dim3(g), dim3(LU_THREADS), LU_W1 * lds, st, M, ldm, m, c0, c1, ce, part,
-                         X, ldx, perm, from_x, info);
+      LU_TRAILING(LU_W1)
     } else {
       hipLaunchKernelGGL(k_lu_trsm12_lds<LU_W2>, dim3(1), dim3(LU_TRSM_LDS_THREADS), 0, st, M, ldm, c0, c1, c1, ce,
                          info);
-      hipLaunchKernelGGL(k_lu_trailing<LU_W2>, dim3(g), dim3(LU_THREADS), LU_W2 * lds, st, M, ldm, m, c0, c1, ce, part,
-                         X, ldx, perm, from_x, info);
+      LU_TRAILING(LU_W2)
     }
+#undef LU_TRAILING
     if (from_x) f = ce;
     return hipGetLastError();
   };
