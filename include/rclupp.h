@@ -371,7 +371,9 @@ int rclupp_chol(const double* G, int64_t n, int64_t m, int scholqr_shift, double
 
 /* LU with partial pivoting of a tall X (m x n): M (m x n, ld ldm, rows in
  * pivoted order, unit diagonal implied below, N in its upper n x n part as in
- * LAPACK getrf), perm (device int32[m]: position -> original row). */
+ * LAPACK getrf), perm (device int32[m]: position -> original row). M must not
+ * overlap X (X is read until the last column has entered M):
+ * RCLUPP_ERR_INVALID_ARG otherwise. */
 int rclupp_tall_lu(const double* X, int64_t m, int64_t n, int64_t ldx, double* M, int64_t ldm, int32_t* perm,
                    rclupp_info* d_info, hipStream_t stream);
 

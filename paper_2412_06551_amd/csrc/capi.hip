@@ -1583,6 +1583,10 @@ int rclupp_tall_lu_tournament(const double* X, int64_t m, int64_t n, int64_t ldx
 int rclupp_tall_lu(const double* X, int64_t m, int64_t n, int64_t ldx, double* M, int64_t ldm, int32_t* perm,
                    rclupp_info* d_info, hipStream_t stream) {
   if (!X || !M || !perm || n < 1 || m < n || ldx < m || ldm < m) return RCLUPP_ERR_INVALID_ARG;
+  // X is read until the last column has entered M: the two must not overlap
+  const uintptr_t x0 = (uintptr_t)X, x1 = (uintptr_t)(X + (n - 1) * ldx + m);
+  const uintptr_t m0 = (uintptr_t)M, m1 = (uintptr_t)(M + (n - 1) * ldm + m);
+  if (x0 < m1 && m0 < x1) return RCLUPP_ERR_INVALID_ARG;
   if (n > RCLUPP_MAX_N || m > (int64_t)INT32_MAX) return RCLUPP_ERR_UNSUPPORTED;
   const size_t sb = tall_lu_scratch_bytes(m, n);
   return with_scratch(sb + kAlign, stream, [&](char* p) {

@@ -65,3 +65,14 @@ def test_noalloc_rejects_sizes_beyond_its_scratch(lib):
     assert st == nat.ERR_INVALID_ARG
     st = lib.rclupp_qr_noalloc(nat.ALG["rclupp"], None, 100, 10, 100, 20, 0, fake, fake, None, None, None)
     assert st == nat.ERR_INVALID_ARG
+
+
+def test_tall_lu_rejects_overlapping_output(lib):
+    # M must not overlap X (the LU reads X until its last column has entered
+    # M); the check comes before any device work
+    m, n = 1000, 8
+    x = ctypes.c_void_p(1 << 24)
+    perm = ctypes.c_void_p(1 << 30)
+    for off in (0, 8 * m, 8 * (7 * m + 999)):
+        st = lib.rclupp_tall_lu(x, m, n, m, ctypes.c_void_p((1 << 24) + off), m, perm, None, None)
+        assert st == nat.ERR_INVALID_ARG, off
